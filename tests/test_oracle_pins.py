@@ -1,0 +1,414 @@
+"""Pins of the FP64 oracle against things other than itself (CPU only).
+
+Each test names what it pins: brute-force DFTs and alias sums, the DFT shift
+property, the a = 1 closed form of Sec. II-A, exact recovery of forced
+collisions, exhaustive uniqueness over on-grid supports, an independent root
+finder for the Appendix closed forms, flags for a > L, the Fig. 1 toy, the
+Theorem-5 vote condition, Gamma statistics of the noise floor, noise-free CS
+against syndrome decoding, and Subspace Pursuit on a textbook instance.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import sftgen
+from oracle import sfft as osf
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def brute_dft(x):
+    """O(N^2) forward DFT written out from its definition."""
+    n = len(x)
+    f = np.arange(n)[:, None] * np.arange(n)[None, :]
+    return np.exp(-2j * np.pi * f / n) @ x
+
+
+def alias_sum(xh, n, m, l):
+    """Right-hand side of Eq. (2): sum_t x_hat[k + tM] e^{i 2 pi (k + tM) l / N} per bin k."""
+    d = n // m
+    out = np.zeros(m, np.complex128)
+    for k in range(m):
+        for t in range(d):
+            s = k + t * m
+            out[k] += xh[s] * np.exp(2j * np.pi * s * l / n)
+    return out
+
+
+def exact_signal(n, locs, vals):
+    xh = np.zeros(n, np.complex128)
+    xh[np.asarray(locs)] = vals
+    return np.fft.ifft(xh)
+
+
+# ----------------------------------------------------------------- T1, T2
+
+@pytest.mark.parametrize("n,m", [(64, 8), (48, 12), (128, 128), (32, 1)])
+def test_syndromes_equal_alias_sum_bruteforce(n, m):
+    """T1: d * DFT_M of the shifted downsampled signal equals the alias sum of
+    Eq. (2)/(3), with x_hat from a brute-force DFT (dense random x, no sparsity)."""
+    g = np.random.default_rng(1)
+    x = g.standard_normal(n) + 1j * g.standard_normal(n)
+    xh = brute_dft(x)
+    shifts = [0, 1, 2, 5, n - 1]
+    ms = oracle.syndromes(x, n, m, shifts)
+    for i, l in enumerate(shifts):
+        ref = alias_sum(xh, n, m, l)
+        assert np.max(np.abs(ms[i] - ref)) <= 1e-12 * np.max(np.abs(xh)) * n
+
+
+def test_dft_convention_and_shift_property():
+    """T2: the generator's x = IDFT(x_hat) under the unnormalised forward DFT,
+    and DFT(x[n + l]) = x_hat[f] e^{i 2 pi f l / N} (the shift property the
+    syndromes rest on)."""
+    n = 96
+    s = sftgen.make_signal(n, 7, 3, dtype=np.complex128)
+    xh = np.zeros(n, np.complex128)
+    xh[s.locs] = s.vals
+    assert np.allclose(brute_dft(s.x), xh, atol=1e-12)
+    for l in (1, 5, 40):
+        shifted = np.roll(s.x, -l)           # shifted[j] = x[j + l]
+        ref = xh * np.exp(2j * np.pi * np.arange(n) * l / n)
+        assert np.allclose(brute_dft(shifted), ref, atol=1e-12)
+
+
+# ------------------------------------------------------------------- T3
+
+def test_a1_closed_form():
+    """T3 (Sec. II-A, the a = 1 case): |m_0| = |m_1| and m_1 / m_0 = e^{i 2 pi s0 / N};
+    the value is recovered as d * x_hat_{d,0}[k] = m_0."""
+    n, m, s0, v = 1024, 64, 777, 0.3 - 1.1j
+    x = exact_signal(n, [s0], [v])
+    ms = oracle.syndromes(x, n, m, [0, 1])
+    k = s0 % m
+    assert abs(abs(ms[0, k]) - abs(ms[1, k])) < 1e-13
+    assert abs(ms[1, k] / ms[0, k] - np.exp(2j * np.pi * s0 / n)) < 1e-13
+    assert abs(ms[0, k] - v) < 1e-13
+    r = oracle.sfft_exact(x, n, m, 4)
+    assert r.locs.tolist() == [s0] and abs(r.vals[0] - v) < 1e-12
+
+
+# ------------------------------------------------------------------- T4
+
+COLLISIONS = [
+    # (N, M, bin k, alias slots t)
+    (4096, 64, 5, [3]),
+    (4096, 64, 5, [3, 4]),                   # adjacent slots
+    (4096, 64, 63, [0, 63]),                 # adjacent across the wrap t = d-1 -> 0
+    (4096, 64, 0, [10, 11, 12]),
+    (4096, 64, 17, [0, 1, 2, 3]),            # four adjacent
+    (4096, 64, 33, [2, 19, 40, 61]),
+    (1 << 16, 256, 200, [1, 2, 100, 255]),
+    (32, 8, 3, [0, 1, 2, 3]),                # d = 4 < 2L: shifts wrap mod N
+    (64, 32, 7, [0, 1]),                     # d = 2
+]
+
+
+@pytest.mark.parametrize("n,m,k,slots", COLLISIONS)
+def test_forced_collisions_exact(n, m, k, slots):
+    """T4: a bin holding a = len(slots) <= L aliased tones is decoded exactly;
+    the accepted order equals a; other bins hold single tones."""
+    g = np.random.default_rng(len(slots) * 1000 + k)
+    locs, vals = sftgen.colliding_spectrum(n, m, k, slots,
+                                           np.exp(2j * np.pi * g.random(len(slots))))
+    others = [(k + 1) % m + 3 * m % n] if m > 1 and (k + 1) % m != k else []
+    others = [o for o in others if o % m != k]
+    all_locs = np.concatenate([locs, np.array(others, np.int64)])
+    all_vals = np.concatenate([vals, np.full(len(others), 0.7 + 0.2j)])
+    o = np.argsort(all_locs)
+    all_locs, all_vals = all_locs[o], all_vals[o]
+    x = exact_signal(n, all_locs, all_vals)
+    r = oracle.sfft_exact(x, n, m, 4)
+    assert r.flagged_bins == 0
+    assert r.locs.tolist() == all_locs.tolist()
+    assert np.max(np.abs(r.vals - all_vals)) < 1e-10
+    assert r.orders[k] == len(slots)
+
+
+def test_rank_order_matches_collision_count():
+    """The numerical rank of the L x L Hankel matrix equals the number of tones in a bin."""
+    n, m, k = 8192, 64, 9
+    g = np.random.default_rng(4)
+    for a in range(1, 5):
+        slots = g.choice(n // m, a, replace=False)
+        locs, vals = sftgen.colliding_spectrum(n, m, k, slots, g.standard_normal(a) + 1j)
+        ms = oracle.syndromes(exact_signal(n, locs, vals), n, m, range(8))
+        sv = oracle.hankel_singular_values(ms[:, k], 4)
+        assert oracle.rank_order(sv, 1e-10) == a
+
+
+def test_try_orders():
+    assert oracle.try_orders(1, 4) == [1, 2, 3, 4]
+    assert oracle.try_orders(3, 4) == [3, 4, 2, 1]
+    assert oracle.try_orders(4, 4) == [4, 3, 2, 1]
+    assert oracle.try_orders(2, 2) == [2, 1]
+
+
+# ------------------------------------------------------------------- T5
+
+def test_uniqueness_exhaustive_small_d():
+    """T5: for d = 16, every on-grid support of size <= L that fits the 2L
+    syndromes exactly puts non-zero values only on the true support (any 2L
+    columns of [w_d^{t l}] are independent), and the decoder returns it."""
+    n, m, L, k = 256, 16, 3, 6
+    d = n // m
+    g = np.random.default_rng(7)
+    for trial in range(4):
+        a = 1 + trial % L
+        slots = np.sort(g.choice(d, a, replace=False))
+        locs, vals = sftgen.colliding_spectrum(n, m, k, slots, g.standard_normal(a) + 1j * g.standard_normal(a))
+        ms = oracle.syndromes(exact_signal(n, locs, vals), n, m, range(2 * L))[:, k]
+        exact_fits = []
+        for size in range(1, L + 1):
+            for sup in itertools.combinations(range(d), size):
+                s = k + np.array(sup) * m
+                v = np.exp(2j * np.pi * np.outer(np.arange(2 * L), s) / n)
+                p = np.linalg.lstsq(v, ms, rcond=None)[0]
+                if np.linalg.norm(ms - v @ p) < 1e-9 * np.linalg.norm(ms):
+                    nz = s[np.abs(p) > 1e-8]
+                    exact_fits.append(tuple(nz))
+        assert set(exact_fits) == {tuple(locs)}
+        r = oracle.sfft_exact(exact_signal(n, locs, vals), n, m, L)
+        assert r.locs.tolist() == locs.tolist()
+
+
+# ------------------------------------------------------------------- T6
+
+def _match(a, b):
+    a, b = list(a), list(b)
+    err = 0.0
+    for z in a:
+        j = int(np.argmin([abs(z - w) for w in b]))
+        err = max(err, abs(z - b[j]))
+        b.pop(j)
+    return err
+
+
+@pytest.mark.parametrize("deg", [1, 2, 3, 4])
+def test_closed_form_roots_vs_eigenvalue_solver(deg):
+    """T6: the Appendix closed forms (corrected) agree with numpy's companion-
+    matrix eigenvalue root finder and with the roots a polynomial was built from."""
+    g = np.random.default_rng(deg)
+    for trial in range(50):
+        if trial % 2:
+            roots = np.exp(2j * np.pi * g.random(deg))            # on the unit circle
+        else:
+            roots = g.standard_normal(deg) + 1j * g.standard_normal(deg)
+        coeffs = np.poly(roots)                                   # highest power first
+        c = coeffs[::-1][:-1]                                     # c_0 .. c_{a-1}
+        got = oracle.poly_roots(c)
+        assert _match(got, roots) < 1e-9
+        assert _match(got, np.roots(coeffs)) < 1e-9
+
+
+@pytest.mark.parametrize("roots", [
+    [1.0, 2.0, 3.0, 4.0],                    # the principal cube root gives A ~ 0 here
+    [1.0, -1.0, 1j, -1j],                    # biquadratic z^4 - 1
+    [np.exp(2j * np.pi * t / 1024) for t in (7, 8, 9, 10)],   # four adjacent grid roots, d = 1024
+    [np.exp(2j * np.pi * t / 4096) for t in (7, 8, 9)],       # three adjacent grid roots, d = 4096
+    [2.0, 2.0 + 1e-3, -1.0],
+])
+def test_closed_form_hard_cases(roots):
+    coeffs = np.poly(roots)
+    got = oracle.poly_roots(coeffs[::-1][:-1])
+    assert _match(got, roots) < 1e-6
+
+
+# ------------------------------------------------------------------- T7
+
+def test_more_than_L_collisions_are_flagged():
+    """T7: a bin with a = L + 1 tones cannot be decoded and is flagged; a
+    zero signal gives an empty output."""
+    n, m, k = 4096, 64, 11
+    g = np.random.default_rng(3)
+    for L in (1, 2, 3, 4):
+        slots = g.choice(n // m, L + 1, replace=False)
+        locs, vals = sftgen.colliding_spectrum(n, m, k, slots, np.exp(2j * np.pi * g.random(L + 1)))
+        r = oracle.sfft_exact(exact_signal(n, locs, vals), n, m, L)
+        assert r.flagged_bins == 1 and len(r.locs) == 0
+    z = oracle.sfft_exact(np.zeros(n, np.complex128), n, m, 4)
+    assert len(z.locs) == 0 and z.active_bins == 0
+
+
+def test_flags_match_true_overflow_bins():
+    """On exact complex128 signals the oracle flags exactly the bins whose true
+    alias count exceeds L, and recovers every other frequency."""
+    n, k, m, L = 1 << 14, 300, 256, 2          # lambda = K/M > 1: many a > 2 bins
+    for seed in range(3):
+        s = sftgen.make_signal(n, k, 100 + seed, dtype=np.complex128)
+        counts = np.bincount(s.locs % m, minlength=m)
+        r = oracle.sfft_exact(s.x, n, m, L)
+        assert r.flagged_bins == int(np.sum(counts > L))
+        good = np.isin(s.locs % m, np.nonzero((counts >= 1) & (counts <= L))[0])
+        assert r.locs.tolist() == s.locs[good].tolist()
+
+
+# ------------------------------------------------------------------- T12
+
+def test_fig1_toy():
+    """T12 (Fig. 1): non-zeros at normalised frequencies 0, pi/2 and pi.  With
+    d = 2 the ones at 0 and pi share a bin (a = 2) and pi/2 is alone; four
+    syndromes (L = 2) solve everything, two (L = 1) only the lone one."""
+    with open(os.path.join(GOLDEN, "fig1_toy.json")) as f:
+        g = json.load(f)
+    n, d = g["n"], g["d"]
+    locs = [int(round(w * n / 2.0)) for w in g["normalised_freqs_over_pi"]]
+    vals = [1.0, 0.5j, -0.8]
+    x = exact_signal(n, locs, vals)
+    m = n // d
+    r2 = oracle.sfft_exact(x, n, m, 2, taus=oracle.default_taus(True))
+    assert r2.locs.tolist() == sorted(locs)
+    assert r2.orders == {0: g["order_of_bin_0"], n // 4: 1}
+    r1 = oracle.sfft_exact(x, n, m, 1, taus=oracle.default_taus(True))
+    assert r1.locs.tolist() == [n // 4] and r1.flagged_bins == 1
+
+
+# --------------------------------------------------------- vote, noise floor
+
+def test_vote_ties_and_counts():
+    sv = np.array([[3.0, 1.0], [3.0, 2.0], [0.5, 0.5]])
+    assert oracle.vote(sv, 1).tolist() == [1, 0, 0]          # tie on 3.0 -> lower bin
+    assert oracle.vote(sv, 3).tolist() == [1, 2, 0]
+    assert oracle.vote(sv, 5).tolist() == [2, 2, 1]          # tie on 0.5 -> lower index
+
+
+def test_vote_theorem5_condition():
+    """Theorem 5: if eps_min > 2 d q_max and every bin has a <= 1, the K-vote
+    finds exactly the occupied bins."""
+    n, m, k = 1 << 12, 256, 40
+    d = n // m
+    g = np.random.default_rng(11)
+    bins = g.choice(m, k, replace=False)
+    locs = np.sort(bins + m * g.integers(0, d, k))
+    vals = (1.0 + g.random(k)) * np.exp(2j * np.pi * g.random(k))
+    q_max = 0.9 / (2 * d)
+    xh = q_max * np.exp(2j * np.pi * g.random(n)) * g.random(n)
+    xh[locs] = vals
+    ms = oracle.syndromes(np.fft.ifft(xh), n, m, range(8))
+    sv = np.array([oracle.hankel_singular_values(ms[:, b], 4) for b in range(m)])
+    a0 = oracle.vote(sv, k)
+    assert sorted(np.nonzero(a0)[0].tolist()) == sorted(bins.tolist())
+    assert a0.max() == 1
+
+
+def test_noise_floor_gamma_median():
+    """For noise-only bins E_k / (d sigma^2) is Gamma(2L, 1); the floor
+    median / (2L - 1/3) estimates the per-syndrome noise variance d sigma^2."""
+    n, m, L = 1 << 18, 4096, 4
+    g = np.random.default_rng(2)
+    sigma2 = 0.37
+    xh = math.sqrt(sigma2 / 2) * (g.standard_normal(n) + 1j * g.standard_normal(n))
+    ms = oracle.syndromes(np.fft.ifft(xh), n, m, range(2 * L))
+    nu = oracle.noise_floor(oracle.bin_energy(ms), L)
+    assert abs(nu / ((n // m) * sigma2) - 1.0) < 0.03
+
+
+# ------------------------------------------------------------ CS, SP (T9, T10)
+
+def test_candidate_errors_vanish_at_roots():
+    n, m, k = 4096, 64, 21
+    slots = [4, 30, 31]
+    locs, vals = sftgen.colliding_spectrum(n, m, k, slots, [1.0, 2j, -0.5])
+    ms = oracle.syndromes(exact_signal(n, locs, vals), n, m, range(8))[:, k]
+    c = oracle.locator(ms, 3)
+    err = oracle.candidate_errors(c, k, n, m)
+    assert set(np.argsort(err)[:3].tolist()) == set(slots)
+    z = np.exp(2j * np.pi * (k + np.arange(n // m) * m) / n)
+    assert np.allclose(err, np.abs(np.polyval(np.concatenate([[1.0], c[::-1]]), z)))
+
+
+def test_noise_free_cs_equals_syndrome_decoding():
+    """T9 (Sec. III-A: the CS model degenerates to the syndrome equations when
+    Phi is pruned to the true columns): on an exact bin, pruning + SP return
+    the syndrome decoder's locations and values."""
+    n, m, k = 1 << 14, 128, 77
+    g = np.random.default_rng(5)
+    rsh = np.sort(g.choice(n // m, 12, replace=False))
+    for a in (1, 2, 3, 4):
+        slots = g.choice(n // m, a, replace=False)
+        locs, vals = sftgen.colliding_spectrum(n, m, k, slots, g.standard_normal(a) + 1j)
+        x = exact_signal(n, locs, vals)
+        mk = oracle.syndromes(x, n, m, range(8))[:, k]
+        yk = oracle.syndromes(x, n, m, rsh)[:, k]
+        s_cs, p_cs = oracle.cs_bin(mk, yk, k, n, m, a, rsh, 12)
+        o = np.argsort(s_cs)
+        assert s_cs[o].tolist() == locs.tolist()
+        assert np.max(np.abs(p_cs[o] - vals)) < 1e-9
+
+
+def test_subspace_pursuit_textbook():
+    """T10: SP recovers a sparse vector exactly from Gaussian measurements."""
+    g = np.random.default_rng(9)
+    for trial in range(20):
+        r, ncol, a = 24, 60, 3
+        phi = (g.standard_normal((r, ncol)) + 1j * g.standard_normal((r, ncol))) / math.sqrt(2 * r)
+        sup = np.sort(g.choice(ncol, a, replace=False))
+        x = np.zeros(ncol, np.complex128)
+        x[sup] = (1 + g.random(a)) * np.exp(2j * np.pi * g.random(a))
+        got_sup, coef = oracle.subspace_pursuit(phi @ x, phi, a)
+        assert got_sup.tolist() == sup.tolist()
+        assert np.allclose(coef, x[sup], atol=1e-10)
+
+
+def test_general_on_exact_input_equals_exact_mode():
+    """Noise-free input: the K-vote gives every bin its true order, so the
+    general driver returns the exact driver's (exact) output."""
+    n, k, m, L = 1 << 16, 200, 1024, 4
+    s = sftgen.make_signal(n, k, 21, amp="gauss", dtype=np.complex128)
+    g = np.random.default_rng(0)
+    rsh = np.sort(g.choice(n // m, 12, replace=False))
+    ge = oracle.sfft_general(s.x, n, k, m, L, rsh)
+    ex = oracle.sfft_exact(s.x, n, m, L)
+    assert ge.locs.tolist() == ex.locs.tolist() == s.locs.tolist()
+    assert np.allclose(ge.vals, s.vals, atol=1e-9)
+
+
+def test_noisy_recovery_monotone_in_snr():
+    """T11: support recovery and relative L2 improve as the input SNR rises."""
+    n, k, m, L = 1 << 16, 60, 256, 4
+    g = np.random.default_rng(1)
+    rsh = np.sort(g.choice(n // m, 12, replace=False))
+    sr, rl = [], []
+    for snr in (10, 20, 30, 40):
+        a, b = 0.0, 0.0
+        for seed in (5, 6, 7):
+            s = sftgen.make_signal(n, k, seed, amp="gauss", dtype=np.complex64, snr_db=snr)
+            r = oracle.sfft_general(s.x, n, k, m, L, rsh)
+            a += oracle.support_recovery(s.locs, r.locs) / 3
+            b += oracle.relative_l2(s.locs, s.vals, r.locs, r.vals) / 3
+        sr.append(a)
+        rl.append(b)
+    assert sr == sorted(sr) and rl == sorted(rl, reverse=True)
+    assert sr[-1] > 0.85 and sr[0] < 0.3
+
+
+# --------------------------------------------------------- printed numbers
+
+def test_theorem2_printed_constant():
+    """Sec. II-C, Theorem 2 example: a_m = 4, mu = 4 give a failure base of
+    about 5e-4 / tau, i.e. 1/20 at tau = 0.01."""
+    with open(os.path.join(GOLDEN, "theorem2.json")) as f:
+        g = json.load(f)
+    am, mu, tau = g["a_m"], g["mu"], g["tau"]
+    base = (1.0 / mu) ** am * math.e ** (am + 2) / (am + 1) ** (am + 1)
+    assert abs(base - g["printed_base_times_tau"]) / g["printed_base_times_tau"] < 0.01
+    assert abs(base / tau - g["printed_base_at_tau"]) < 0.002
+
+
+def test_lemma2_bound_holds_empirically():
+    """Lemma 2: Pr(some bin has a > a_m) <= (N/d) (d e K / (N (a_m + 1)))^(a_m + 1).
+    The oracle's flag count (= bins with a > L on exact input) obeys it."""
+    n, k, m, L = 1 << 14, 40, 128, 2
+    d = n // m
+    bound = (n / d) * (d * math.e * k / (n * (L + 1))) ** (L + 1)
+    hits = 0
+    trials = 40
+    for seed in range(trials):
+        s = sftgen.make_signal(n, k, 500 + seed, dtype=np.complex128)
+        hits += oracle.sfft_exact(s.x, n, m, L).flagged_bins > 0
+    assert hits / trials <= bound

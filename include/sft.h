@@ -1,0 +1,176 @@
+/*
+ * sft.h — C ABI of an MI355X (gfx950) implementation of non-iterative
+ * sFFT-DT: sparse FFT by downsampling in time and syndrome decoding
+ * (Hsieh, Lu, Pei, arXiv 1407.8315).
+ *
+ * Problem statement (Alg. 1 and Alg. 2, "Input: x, K; Output: x_hat"): given
+ * a length-N signal x whose spectrum x_hat has K significant entries, return
+ * those entries as a sparse list of (location, value).
+ *
+ * DFT convention: forward DFT unnormalised, X[f] = sum_n x[n] e^{-2 pi i f n/N},
+ * so a test signal is x = IDFT(x_hat) and the returned values are x_hat[s].
+ *
+ * The path on the device, per signal (Sec. II and III of the paper):
+ *   1. gather x_{d,l}[k'] = x[(d k' + l) mod N] for 2L consecutive shifts l
+ *      (general mode: also R random shifts n_j), M = N/d samples each;
+ *   2. m_l = d * FFT_M(x_{d,l}) (the syndromes, Eq. (2)-(3));
+ *   3. per bin k: activity test, order estimate (rank of the Hankel matrix
+ *      of Eq. (5) — or the K-vote of Sec. III-C Step 1 in general mode, or a
+ *      learned predictor), locator solve (Eq. (5)), roots matched to the grid
+ *      {k + t M} (Alg. 1 grid check), Vandermonde least squares for the
+ *      values (Step (iii)), residual judge, fallback over orders;
+ *   4. general mode: bins no order explains go through pruning (Sec. III-C
+ *      Steps 2-3) and Subspace Pursuit on the random-shift syndromes (Eq. (11));
+ *   5. output sorted by location (general mode: the K largest values first).
+ *
+ * Memory: every pointer argument named *_dev is device memory (hipMalloc or a
+ * torch CUDA tensor on the plan's device); everything else is host memory.
+ * The caller owns inputs and outputs; a plan owns its workspace, tables and
+ * graph until sft_destroy.  Calls are enqueued on the plan's stream and are
+ * asynchronous, except that passing a non-NULL sft_stats (or SFT_FLAG_SYNC)
+ * synchronises the stream and makes status codes such as SFT_E_CAPACITY
+ * observable.  A plan is not thread-safe: use one plan per stream.
+ * No call allocates device memory except sft_plan, sft_mlp_create and the
+ * first sft_batch call of a plan (graph instantiation).
+ *
+ * Errors: every call returns a status; no exception crosses the ABI;
+ * sft_last_error() gives the text of the last failure on the calling thread.
+ */
+#ifndef SFT_H
+#define SFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SFT_ABI_VERSION 1
+#define SFT_MAX_RSHIFTS 64
+
+typedef enum sft_status {
+    SFT_OK = 0,
+    SFT_E_INVALID = 1,      /* NULL pointer, K <= 0, K > N, bad dtype or mode, wrong plan kind */
+    SFT_E_UNSUPPORTED = 2,  /* N or M not a power of two, M does not divide N, L outside 1..4, M too large */
+    SFT_E_NOMEM = 3,        /* device or host allocation failed */
+    SFT_E_DEVICE = 4,       /* HIP runtime error (text in sft_last_error) */
+    SFT_E_CAPACITY = 5,     /* an output list was too small; its count holds the required size */
+    SFT_E_NONFINITE = 6     /* SFT_FLAG_CHECK_FINITE and a gathered sample is NaN or Inf */
+} sft_status;
+
+enum { SFT_C64 = 1, SFT_C128 = 2 };                 /* input element type: complex float / double, interleaved */
+enum { SFT_MODE_EXACT = 0, SFT_MODE_GENERAL = 1 };  /* Sec. II (exactly K-sparse) / Sec. III (generally K-sparse) */
+enum {
+    SFT_FLAG_LEARNED = 1u,       /* order estimate from the attached MLP; rank test as fallback */
+    SFT_FLAG_SYNC = 2u,          /* synchronise at the end of each call */
+    SFT_FLAG_CHECK_FINITE = 4u   /* count non-finite gathered samples; report SFT_E_NONFINITE (sync calls) */
+};
+
+/* Parameters of one signal.  Zero means "default" for m, l, r and every
+ * threshold.  Defaults: M = 4K rounded up to a power of two (at most N),
+ * L = 4 (the paper's a_m = 4, Sec. II-E), R = 3L (Sec. III-A: r = 3 a_m).
+ * Thresholds (complex64 / complex128 input): tau_zero 1e-4 / 1e-9 (activity:
+ * E_k > tau_zero^2 mean E), tau_rank 1e-5 / 1e-10 (order = #sigma_i > tau_rank
+ * sigma_1), tau_res 1e-4 / 1e-9 and c_res 3 (judge: residual^2 <= tau_res^2 E_k
+ * + c_res (2L - a) nu), tau_amp 1e-4 / 1e-9 (drop |p_j| < tau_amp max|p|),
+ * delta_grid 0.1 (root within 0.1 grid spacing of a point k + tM), delta_mag
+ * 0.05 (| |z| - 1 | bound). */
+typedef struct sft_params {
+    int64_t n;          /* N: signal length, power of two >= 2 */
+    int64_t k;          /* K: sparsity, 1 <= K <= N */
+    int64_t m;          /* M = N/d: downsampled length, power of two dividing N; 0 = auto */
+    int32_t l;          /* L = a_m: maximum collisions decoded per bin, 1..4; 0 = 4 */
+    int32_t r;          /* R: random shifts of the CS step (general mode), 1..64, <= d; 0 = min(3L, d) */
+    int32_t in_dtype;   /* SFT_C64 or SFT_C128 */
+    int32_t mode;       /* SFT_MODE_EXACT or SFT_MODE_GENERAL */
+    uint32_t flags;     /* SFT_FLAG_* */
+    uint32_t reserved;  /* must be 0 */
+    uint64_t seed;      /* seed of the random shifts n_j (general mode) */
+    double tau_zero, tau_rank, tau_res, tau_amp, c_res, delta_grid, delta_mag;
+} sft_params;
+
+/* A sparse output list.  loc_dev: int64[capacity] locations in [0, N), sorted
+ * ascending; val_dev: complex128 (two doubles) [capacity] values x_hat[loc];
+ * count_dev: one int64, set to the number of entries found.  When count >
+ * capacity only the `capacity` smallest locations (general mode: of the kept
+ * K) are written. */
+typedef struct sft_sparse_out {
+    int64_t* loc_dev;
+    void* val_dev;
+    int64_t capacity;
+    int64_t* count_dev;
+} sft_sparse_out;
+
+/* Totals over the signals of one call (filled only when requested). */
+typedef struct sft_stats {
+    int64_t active_bins;        /* bins that passed the activity test / got votes */
+    int64_t flagged_bins;       /* bins no order up to L explained */
+    int64_t cs_bins;            /* flagged bins recovered by pruning + SP (general mode) */
+    int64_t mlp_fallbacks;      /* learned mode: bins where the predicted order was rejected */
+    int64_t entries;            /* entries found (sum of counts) */
+    int64_t overflowed;         /* signals whose count exceeded the capacity */
+    int64_t nonfinite;          /* non-finite gathered samples (SFT_FLAG_CHECK_FINITE) */
+    double stage_ms[4];         /* gather+FFT, order estimate/vote, decode, output (HIP events) */
+} sft_stats;
+
+/* What a plan chose for one signal; the oracle consumes exactly these. */
+typedef struct sft_plan_info {
+    int64_t n, k, m, d;
+    int32_t l, r, in_dtype, mode;
+    uint32_t flags;
+    int32_t n_signals;          /* signals in the plan */
+    int64_t rshifts[SFT_MAX_RSHIFTS];   /* n_0 .. n_{R-1}, distinct, in [0, d), ascending */
+    double tau_zero, tau_rank, tau_res, tau_amp, c_res, delta_grid, delta_mag;
+    int64_t workspace_bytes;    /* device bytes owned by the plan */
+} sft_plan_info;
+
+typedef struct sft_plan_s* sft_plan_t;
+typedef struct sft_mlp_s* sft_mlp_t;
+
+/* Create a plan for n_params signals (1: single-signal plan for sft_exact /
+ * sft_general; >1: batch plan for sft_batch; signals may differ in every
+ * field).  hip_stream: a hipStream_t (NULL = default stream) on the current
+ * device.  Validates parameters, chooses M and L where 0 (autotuner for
+ * batch plans), draws the random shifts from the seed, allocates the
+ * workspace and tables.  Errors: SFT_E_INVALID, SFT_E_UNSUPPORTED, SFT_E_NOMEM,
+ * SFT_E_DEVICE; *out is NULL on failure. */
+sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params, void* hip_stream);
+
+/* Exactly K-sparse recovery of one signal (Sec. II, non-iterative).
+ * x_dev: N elements of the plan's in_dtype.  Requires a single-signal plan
+ * in SFT_MODE_EXACT.  stats may be NULL (then the call is asynchronous). */
+sft_status sft_exact(sft_plan_t plan, const void* x_dev, const sft_sparse_out* out, sft_stats* stats);
+
+/* Generally K-sparse recovery of one signal (Sec. III): syndrome decoding with
+ * the K-vote, pruning + Subspace Pursuit on flagged bins, the K largest kept.
+ * Requires a single-signal plan in SFT_MODE_GENERAL. */
+sft_status sft_general(sft_plan_t plan, const void* x_dev, const sft_sparse_out* out, sft_stats* stats);
+
+/* All signals of a batch plan in one stream-ordered launch sequence captured
+ * in a HIP graph (instantiated on the first call).  x_devs: host array of
+ * n_signals device pointers; outs: host array of n_signals output lists.
+ * Each signal runs in its own mode. */
+sft_status sft_batch(sft_plan_t plan, const void* const* x_devs, const sft_sparse_out* outs, sft_stats* stats);
+
+/* Steps 1-2 alone for a single-signal plan: the syndromes
+ * m_l[k] = d * FFT_M(x[(d k' + l) mod N])[k] (Sec. II-A, Eq. (2); Alg. 1 and
+ * Alg. 2 Part 1) for the plan's S = 2L (+ R) shifts, written to out_dev as
+ * [S][M] interleaved complex (float for SFT_C64 input, double for SFT_C128),
+ * shift-major; shift s is l = s for s < 2L and n_{s-2L} after that.  Same
+ * stream semantics as sft_exact (asynchronous). */
+sft_status sft_syndromes(sft_plan_t plan, const void* x_dev, void* out_dev);
+
+/* Parameters the plan chose for signal `index` (0-based). */
+sft_status sft_plan_get(sft_plan_t plan, int64_t index, sft_plan_info* info);
+
+/* Release a plan (waits for its stream).  NULL is ignored. */
+void sft_destroy(sft_plan_t plan);
+
+const char* sft_status_str(sft_status s);
+const char* sft_last_error(void);
+int32_t sft_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFT_H */

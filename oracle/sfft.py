@@ -59,21 +59,26 @@ def default_taus(complex128_input: bool) -> Taus:
 # ---------------------------------------------------------------- steps 1-2
 
 
-def syndromes(x, n: int, m: int, shifts) -> np.ndarray:
+def syndromes(x, n: int, m: int, shifts, fft_dtype=np.complex128) -> np.ndarray:
     """m_l[k] = d * FFT(x_{d,l})[k] with x_{d,l}[k'] = x[(d k' + l) mod N].
 
     Sec. II-A (x_{d,l}[k] = x[dk + l]) and Alg. 1, the two FFT lines scaled by
     d; Alg. 2, Part 1, for the random shifts n_j.  Indices wrap mod N, which
     only matters when d < 2L.  Returns an array [len(shifts), M] in FP64.
+
+    fft_dtype=np.complex64 runs the FFTs in single precision (the precision
+    of the fast path for complex64 input), so that decisions which depend on
+    that precision (e.g. clusters whose smallest Hankel singular value is
+    below single-precision resolution) are taken at the same precision.
     """
-    x = np.asarray(x).astype(np.complex128)
+    x = np.asarray(x).astype(fft_dtype)
     if n % m:
         raise ValueError("M must divide N")
     d = n // m
     kp = np.arange(m, dtype=np.int64)
     out = np.empty((len(shifts), m), np.complex128)
     for i, l in enumerate(shifts):
-        out[i] = d * np.fft.fft(x[(d * kp + int(l)) % n])
+        out[i] = (fft_dtype(d) * np.fft.fft(x[(d * kp + int(l)) % n])).astype(np.complex128)
     return out
 
 
@@ -165,14 +170,18 @@ def amplitudes(mk, s, n: int):
     return p, float(np.real(np.vdot(r, r)))
 
 
-def decode_bin(mk, k: int, n: int, m: int, L: int, a0: int, e_k: float, nu: float, taus: Taus):
+def decode_bin(mk, k: int, n: int, m: int, L: int, a0: int, e_k: float, nu: float, taus: Taus,
+               only=None, skip=()):
     """Syndrome decoding of one bin (Sec. II-B Steps (i)-(iii), Alg. 1 grid check),
     over the canonical order of hypotheses, with the residual judge.
 
     Returns (locations, values, accepted order) or None when every order is
-    rejected (the bin is flagged).
+    rejected (the bin is flagged).  `only` restricts the hypotheses tried;
+    `skip` removes some from the canonical order.
     """
-    for a in try_orders(a0, L):
+    for a in (only if only is not None else try_orders(a0, L)):
+        if a in skip:
+            continue
         c = locator(mk, a)
         if c is None:
             continue
@@ -205,14 +214,16 @@ def _sorted(locs, vals):
     return locs[o], vals[o]
 
 
-def sfft_exact(x, n: int, m: int, L: int, taus: Taus | None = None, orders=None) -> Result:
+def sfft_exact(x, n: int, m: int, L: int, taus: Taus | None = None, orders=None,
+               fft_dtype=np.complex128) -> Result:
     """Non-iterative sFFT-DT for exactly K-sparse signals (Sec. II-B/II-C):
     2L consecutive shifts, one FFT each, then syndrome decoding of every
-    active bin.  `orders` (optional, bin -> a0) replaces the rank test, which
-    is how a learned order predictor plugs in."""
+    active bin.  `orders` (optional, bin -> predicted order) is tried first,
+    before the rank test and the canonical order (the learned predictor's
+    hook); fft_dtype as in syndromes()."""
     if taus is None:
         taus = default_taus(np.asarray(x).dtype == np.complex128)
-    msyn = syndromes(x, n, m, range(2 * L))
+    msyn = syndromes(x, n, m, range(2 * L), fft_dtype)
     e = bin_energy(msyn)
     e_ref = float(np.mean(e))
     locs, vals = [], []
@@ -222,11 +233,14 @@ def sfft_exact(x, n: int, m: int, L: int, taus: Taus | None = None, orders=None)
             continue
         res.active_bins += 1
         mk = msyn[:, k]
-        if orders is not None and k in orders:
-            a0 = int(orders[k])
-        else:
+        a_pred = int(orders.get(k, 0)) if orders is not None else 0
+        out = None
+        if 1 <= a_pred <= L:
+            out = decode_bin(mk, k, n, m, L, a_pred, float(e[k]), 0.0, taus, only=[a_pred])
+        if out is None:
             a0 = rank_order(hankel_singular_values(mk, L), taus.tau_rank)
-        out = decode_bin(mk, k, n, m, L, a0, float(e[k]), 0.0, taus)
+            skip = [a_pred] if 1 <= a_pred <= L else []
+            out = decode_bin(mk, k, n, m, L, a0, float(e[k]), 0.0, taus, skip=skip)
         if out is None:
             res.flagged_bins += 1
             continue
@@ -313,18 +327,19 @@ def subspace_pursuit(y, phi, a: int, max_iter: int | None = None):
 
 def cs_bin(mk, yk, k: int, n: int, m: int, a0: int, rshifts, R: int):
     """CS recovery of one flagged bin (Sec. III-A Eq. (11), Sec. III-C Steps 2-3,
-    SP): prune U_k to the min(2 a0, R, d) roots with the smallest |P~(z)| (all d
-    when the locator system is singular), build Phi_p with
-    Phi_{j,t} = e^{i 2 pi (k + t M) n_j / N}, run SP with sparsity a0."""
+    SP): prune U_k to the min(2 a0, R, d) roots with the smallest |P~(z)|, where
+    P~ comes from the order-a0 locator, build Phi_p with
+    Phi_{j,t} = e^{i 2 pi (k + t M) n_j / N}, run SP with sparsity a0.
+    Returns None when the order-a0 locator system is singular (the bin then
+    stays flagged with no output)."""
     d = n // m
     c = locator(mk, a0)
     if c is None:
-        cand = np.arange(d, dtype=np.int64)
-    else:
-        err = candidate_errors(c, k, n, m)
-        keep = min(2 * a0, R, d)
-        o = np.lexsort((np.arange(d), err))
-        cand = np.sort(o[:keep]).astype(np.int64)
+        return None                     # nothing to prune with: the bin stays flagged
+    err = candidate_errors(c, k, n, m)
+    keep = min(2 * a0, R, d)
+    o = np.lexsort((np.arange(d), err))
+    cand = np.sort(o[:keep]).astype(np.int64)
     s_cand = k + cand * m
     nj = np.asarray(rshifts, np.int64)
     phi = np.exp(1j * TWO_PI * ((nj[:, None] * s_cand[None, :]) % n) / n)
@@ -332,7 +347,8 @@ def cs_bin(mk, yk, k: int, n: int, m: int, a0: int, rshifts, R: int):
     return s_cand[sup], coef
 
 
-def sfft_general(x, n: int, k_sparsity: int, m: int, L: int, rshifts, taus: Taus | None = None) -> Result:
+def sfft_general(x, n: int, k_sparsity: int, m: int, L: int, rshifts, taus: Taus | None = None,
+                 fft_dtype=np.complex128) -> Result:
     """Non-iterative sFFT-DT for generally K-sparse signals (Sec. III, Alg. 2),
     with the CS step run on the bins the syndrome decoder flags.
 
@@ -345,8 +361,8 @@ def sfft_general(x, n: int, k_sparsity: int, m: int, L: int, rshifts, taus: Taus
     if taus is None:
         taus = default_taus(np.asarray(x).dtype == np.complex128)
     R = len(rshifts)
-    msyn = syndromes(x, n, m, range(2 * L))
-    ysyn = syndromes(x, n, m, rshifts)
+    msyn = syndromes(x, n, m, range(2 * L), fft_dtype)
+    ysyn = syndromes(x, n, m, rshifts, fft_dtype)
     e = bin_energy(msyn)
     nu = noise_floor(e, L)
     sv_all = np.array([hankel_singular_values(msyn[:, k], L) for k in range(m)])
@@ -362,8 +378,11 @@ def sfft_general(x, n: int, k_sparsity: int, m: int, L: int, rshifts, taus: Taus
         out = decode_bin(mk, k, n, m, L, a0, float(e[k]), nu, taus)
         if out is None:
             res.flagged_bins += 1
+            cs = cs_bin(mk, ysyn[:, k], k, n, m, a0, rshifts, R)
+            if cs is None:
+                continue
             res.cs_bins += 1
-            s, p = cs_bin(mk, ysyn[:, k], k, n, m, a0, rshifts, R)
+            s, p = cs
         else:
             s, p = out[0], out[1]
             res.orders[k] = out[2]

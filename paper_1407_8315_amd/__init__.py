@@ -1,0 +1,190 @@
+"""sFFT-DT (arXiv 1407.8315) on MI355X: a thin Python binding over libsft.so.
+
+Every step of the path (downsampling, FFTs, syndrome decoding, CS recovery,
+output) runs in the HIP library; this module only marshals arguments.  torch
+supplies device memory and the stream.
+
+    plan = Plan(dict(n=1 << 20, k=1000, m=4096, l=4))        # exact mode
+    res = plan.exact(x)            # x: complex64 CUDA tensor of length n
+    res.loc, res.val               # sorted locations, complex128 values
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+from . import _lib
+from ._lib import (  # noqa: F401
+    SFT_C64, SFT_C128, SFT_MODE_EXACT, SFT_MODE_GENERAL,
+    SFT_FLAG_LEARNED, SFT_FLAG_SYNC, SFT_FLAG_CHECK_FINITE, SftError,
+)
+
+__all__ = ["Plan", "Result", "SftError", "make_params", "library_path"]
+
+
+def library_path() -> str:
+    return _lib.LIB_PATH
+
+
+def make_params(n, k, m=0, l=0, r=0, dtype="c64", mode="exact", flags=0, seed=0, **taus) -> _lib.Params:
+    p = _lib.Params()
+    p.n, p.k, p.m, p.l, p.r = int(n), int(k), int(m), int(l), int(r)
+    p.in_dtype = {"c64": SFT_C64, "c128": SFT_C128}[dtype]
+    p.mode = {"exact": SFT_MODE_EXACT, "general": SFT_MODE_GENERAL}[mode]
+    p.flags = int(flags)
+    p.reserved = 0
+    p.seed = int(seed) & ((1 << 64) - 1)
+    for name in ("tau_zero", "tau_rank", "tau_res", "tau_amp", "c_res", "delta_grid", "delta_mag"):
+        setattr(p, name, float(taus.pop(name, 0.0)))
+    if taus:
+        raise TypeError(f"unknown parameters {sorted(taus)}")
+    return p
+
+
+@dataclasses.dataclass
+class Result:
+    loc: object          # torch int64 [capacity] (device)
+    val: object          # torch complex128 [capacity] (device)
+    count: object        # torch int64 [1] (device)
+    stats: dict | None = None
+
+    def host(self):
+        """(locations, values) as numpy arrays, trimmed to the count."""
+        n = int(self.count.item())
+        n = min(n, self.loc.numel())
+        return self.loc[:n].cpu().numpy(), self.val[:n].cpu().numpy()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Plan:
+    """A plan for one signal (sft_exact / sft_general) or a batch (sft_batch).
+
+    params: a dict (or list of dicts) with keys n, k, m, l, r, dtype ("c64" or
+    "c128"), mode ("exact" or "general"), flags, seed and thresholds.  The
+    plan is bound to `stream` (default: torch's current stream)."""
+
+    def __init__(self, params, stream=None):
+        torch = _torch()
+        self._lib = _lib.load()
+        plist = params if isinstance(params, (list, tuple)) else [params]
+        arr = (_lib.Params * len(plist))(*[make_params(**p) if isinstance(p, dict) else p for p in plist])
+        self.n_signals = len(plist)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        handle = ctypes.c_void_p()
+        _lib.check(self._lib.sft_plan(ctypes.byref(handle), arr, len(plist), ctypes.c_void_p(stream.cuda_stream)),
+                   "sft_plan")
+        self._h = handle
+        self.infos = [self.info(i) for i in range(self.n_signals)]
+
+    # ------------------------------------------------------------ info
+    def info(self, i: int = 0) -> dict:
+        inf = _lib.PlanInfo()
+        _lib.check(self._lib.sft_plan_get(self._h, i, ctypes.byref(inf)), "sft_plan_get")
+        d = {f: getattr(inf, f) for f, _ in _lib.PlanInfo._fields_ if f != "rshifts"}
+        d["rshifts"] = [inf.rshifts[j] for j in range(inf.r)]
+        return d
+
+    # ------------------------------------------------------------ outputs
+    def new_output(self, capacity: int, device=None):
+        torch = _torch()
+        device = device or torch.device("cuda", torch.cuda.current_device())
+        loc = torch.empty(max(capacity, 1), dtype=torch.int64, device=device)
+        val = torch.empty(max(capacity, 1), dtype=torch.complex128, device=device)
+        cnt = torch.zeros(1, dtype=torch.int64, device=device)
+        return Result(loc, val, cnt)
+
+    @staticmethod
+    def _out_struct(res: Result, capacity: int) -> _lib.SparseOut:
+        o = _lib.SparseOut()
+        o.loc_dev = res.loc.data_ptr()
+        o.val_dev = res.val.data_ptr()
+        o.capacity = int(capacity)
+        o.count_dev = res.count.data_ptr()
+        return o
+
+    def default_capacity(self, i: int = 0) -> int:
+        inf = self.infos[i]
+        return int(inf["m"] * inf["l"])
+
+    def _check_input(self, x, i=0):
+        torch = _torch()
+        inf = self.infos[i]
+        want = torch.complex128 if inf["in_dtype"] == SFT_C128 else torch.complex64
+        if not x.is_cuda or x.dtype != want or x.numel() != inf["n"] or not x.is_contiguous():
+            raise ValueError(f"signal {i}: need a contiguous {want} CUDA tensor of {inf['n']} elements")
+
+    # ------------------------------------------------------------ calls
+    def _single(self, fn, x, out, capacity, stats):
+        self._check_input(x)
+        if capacity is None:
+            capacity = self.default_capacity()
+        if out is None:
+            out = self.new_output(capacity, x.device)
+        o = self._out_struct(out, capacity)
+        st = _lib.Stats() if stats else None
+        status = fn(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.byref(o),
+                    ctypes.byref(st) if st is not None else None)
+        if st is not None:
+            out.stats = st.as_dict()
+        if status == _lib.SFT_E_CAPACITY:
+            out.stats = (out.stats or {}) | {"capacity_exceeded": True}
+            return out
+        _lib.check(status, fn.__name__)
+        return out
+
+    def exact(self, x, out: Result | None = None, capacity=None, stats=False) -> Result:
+        return self._single(self._lib.sft_exact, x, out, capacity, stats)
+
+    def general(self, x, out: Result | None = None, capacity=None, stats=False) -> Result:
+        return self._single(self._lib.sft_general, x, out, capacity, stats)
+
+    def batch(self, xs, outs=None, capacities=None, stats=False):
+        if len(xs) != self.n_signals:
+            raise ValueError(f"expected {self.n_signals} signals")
+        for i, x in enumerate(xs):
+            self._check_input(x, i)
+        if capacities is None:
+            capacities = [self.default_capacity(i) for i in range(self.n_signals)]
+        if outs is None:
+            outs = [self.new_output(c, xs[0].device) for c in capacities]
+        xarr = (ctypes.c_void_p * len(xs))(*[x.data_ptr() for x in xs])
+        oarr = (_lib.SparseOut * len(xs))(*[self._out_struct(o, c) for o, c in zip(outs, capacities)])
+        st = _lib.Stats() if stats else None
+        status = self._lib.sft_batch(self._h, xarr, oarr, ctypes.byref(st) if st is not None else None)
+        if status != _lib.SFT_E_CAPACITY:
+            _lib.check(status, "sft_batch")
+        if st is not None:
+            d = st.as_dict()
+            for o in outs:
+                o.stats = d
+        self._keep = (xarr, oarr)      # keep the argument arrays alive until the next call
+        return outs
+
+    def syndromes(self, x):
+        """Steps 1-2 only: the [S, M] syndromes of a single-signal plan (device tensor)."""
+        torch = _torch()
+        self._check_input(x)
+        inf = self.infos[0]
+        s_lines = 2 * inf["l"] + inf["r"]
+        dt = torch.complex128 if inf["in_dtype"] == SFT_C128 else torch.complex64
+        out = torch.empty((s_lines, inf["m"]), dtype=dt, device=x.device)
+        _lib.check(self._lib.sft_syndromes(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr())),
+                   "sft_syndromes")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sft_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,115 @@
+"""ctypes declarations mirroring include/sft.h.  Loads the in-tree libsft.so
+and fails loudly when it has not been built: there is no other path."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsft.so")
+
+SFT_OK, SFT_E_INVALID, SFT_E_UNSUPPORTED, SFT_E_NOMEM, SFT_E_DEVICE, SFT_E_CAPACITY, SFT_E_NONFINITE = range(7)
+SFT_C64, SFT_C128 = 1, 2
+SFT_MODE_EXACT, SFT_MODE_GENERAL = 0, 1
+SFT_FLAG_LEARNED, SFT_FLAG_SYNC, SFT_FLAG_CHECK_FINITE = 1, 2, 4
+SFT_MAX_RSHIFTS = 64
+
+# Every symbol the header declares (checked by the CPU test suite).
+EXPORTS = [
+    "sft_plan", "sft_exact", "sft_general", "sft_batch", "sft_syndromes", "sft_plan_get", "sft_destroy",
+    "sft_status_str", "sft_last_error", "sft_abi_version",
+]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("k", ctypes.c_int64), ("m", ctypes.c_int64),
+        ("l", ctypes.c_int32), ("r", ctypes.c_int32), ("in_dtype", ctypes.c_int32), ("mode", ctypes.c_int32),
+        ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+        ("tau_zero", ctypes.c_double), ("tau_rank", ctypes.c_double), ("tau_res", ctypes.c_double),
+        ("tau_amp", ctypes.c_double), ("c_res", ctypes.c_double), ("delta_grid", ctypes.c_double),
+        ("delta_mag", ctypes.c_double),
+    ]
+
+
+class SparseOut(ctypes.Structure):
+    _fields_ = [
+        ("loc_dev", ctypes.c_void_p), ("val_dev", ctypes.c_void_p),
+        ("capacity", ctypes.c_int64), ("count_dev", ctypes.c_void_p),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("active_bins", ctypes.c_int64), ("flagged_bins", ctypes.c_int64), ("cs_bins", ctypes.c_int64),
+        ("mlp_fallbacks", ctypes.c_int64), ("entries", ctypes.c_int64), ("overflowed", ctypes.c_int64),
+        ("nonfinite", ctypes.c_int64), ("stage_ms", ctypes.c_double * 4),
+    ]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "stage_ms"}
+        d["stage_ms"] = list(self.stage_ms)
+        return d
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("k", ctypes.c_int64), ("m", ctypes.c_int64), ("d", ctypes.c_int64),
+        ("l", ctypes.c_int32), ("r", ctypes.c_int32), ("in_dtype", ctypes.c_int32), ("mode", ctypes.c_int32),
+        ("flags", ctypes.c_uint32), ("n_signals", ctypes.c_int32),
+        ("rshifts", ctypes.c_int64 * SFT_MAX_RSHIFTS),
+        ("tau_zero", ctypes.c_double), ("tau_rank", ctypes.c_double), ("tau_res", ctypes.c_double),
+        ("tau_amp", ctypes.c_double), ("c_res", ctypes.c_double), ("delta_grid", ctypes.c_double),
+        ("delta_mag", ctypes.c_double), ("workspace_bytes", ctypes.c_int64),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """The loaded library (built by __graft_entry__.build()); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(the sFFT-DT path runs only through the HIP library)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, st = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    lib.sft_plan.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Params), i64, vp]
+    lib.sft_plan.restype = st
+    for name in ("sft_exact", "sft_general"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, vp, ctypes.POINTER(SparseOut), ctypes.POINTER(Stats)]
+        f.restype = st
+    lib.sft_batch.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(SparseOut), ctypes.POINTER(Stats)]
+    lib.sft_batch.restype = st
+    lib.sft_syndromes.argtypes = [vp, vp, vp]
+    lib.sft_syndromes.restype = st
+    lib.sft_plan_get.argtypes = [vp, i64, ctypes.POINTER(PlanInfo)]
+    lib.sft_plan_get.restype = st
+    lib.sft_destroy.argtypes = [vp]
+    lib.sft_destroy.restype = None
+    lib.sft_status_str.argtypes = [st]
+    lib.sft_status_str.restype = ctypes.c_char_p
+    lib.sft_last_error.argtypes = []
+    lib.sft_last_error.restype = ctypes.c_char_p
+    lib.sft_abi_version.argtypes = []
+    lib.sft_abi_version.restype = ctypes.c_int32
+    _lib = lib
+    return lib
+
+
+class SftError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+def check(status: int, what: str = ""):
+    if status != SFT_OK:
+        lib = load()
+        name = lib.sft_status_str(status).decode()
+        detail = lib.sft_last_error().decode()
+        raise SftError(status, f"{what}: {name}: {detail}")

@@ -1,0 +1,482 @@
+// C ABI of the sFFT-DT device library: plans, calls, status codes.
+// The arithmetic of the method lives in fft.hip and decode.hip; this file
+// validates parameters, chooses defaults, draws the random shifts, lays out
+// the workspace, orders the work items and enqueues the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "plan_host.h"
+#include "sft.h"
+
+using namespace sft;
+
+namespace {
+
+thread_local std::string g_err;
+
+sft_status fail(sft_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIPCHK(call)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) return fail(SFT_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+}  // namespace
+
+struct sft_plan_s {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::vector<SigHost> sig;
+    bool fp64 = false;
+    bool any_general = false;
+    // device buffers
+    std::vector<void*> allocs;
+    SigDev* d_sigs = nullptr;
+    IoDev* d_io = nullptr;
+    void* d_synd = nullptr;
+    double* d_epart = nullptr;
+    double* d_sigma = nullptr;
+    double* d_ebin = nullptr;
+    SelDev* d_sel = nullptr;
+    SigCounters* d_cnt = nullptr;
+    int64_t* d_stloc = nullptr;
+    double2* d_stval = nullptr;
+    unsigned char* d_keep = nullptr;
+    int64_t* d_shifts = nullptr;
+    void* d_tw = nullptr;
+    double2* d_om = nullptr;
+    int4* d_synd_items = nullptr;
+    int2* d_bin_items = nullptr;
+    int2* d_out_items = nullptr;
+    int* d_gsigs = nullptr;
+    signed char* d_orders = nullptr;
+    int* d_flag = nullptr;
+    int n_synd_items = 0, n_bin_items = 0, n_out_items = 0, n_general = 0;
+    int tw_log2 = 0, om_log2 = 0;
+    int64_t ws_bytes = 0;
+    // host staging
+    IoDev* h_io = nullptr;
+    SigCounters* h_cnt = nullptr;
+    hipEvent_t ev_upload = nullptr;
+    bool upload_pending = false;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    sft_mlp_t mlp = nullptr;
+};
+
+namespace {
+
+template <typename T>
+sft_status dalloc(sft_plan_s* p, T** out, size_t count) {
+    *out = nullptr;
+    if (count == 0) count = 1;
+    void* ptr = nullptr;
+    hipError_t e = hipMalloc(&ptr, count * sizeof(T));
+    if (e != hipSuccess) return fail(SFT_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    p->allocs.push_back(ptr);
+    p->ws_bytes += (int64_t)(count * sizeof(T));
+    *out = (T*)ptr;
+    return SFT_OK;
+}
+
+void release(sft_plan_s* p) {
+    if (!p) return;
+    if (p->stream || true) (void)hipStreamSynchronize(p->stream);
+    for (void* a : p->allocs) (void)hipFree(a);
+    p->allocs.clear();
+    if (p->h_io) (void)hipHostFree(p->h_io);
+    if (p->h_cnt) (void)hipHostFree(p->h_cnt);
+    if (p->ev_upload) (void)hipEventDestroy(p->ev_upload);
+    for (auto& e : p->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    delete p;
+}
+
+LaunchCtx make_ctx(const sft_plan_s* p) {
+    LaunchCtx c{};
+    c.stream = p->stream;
+    c.sigs = p->d_sigs;
+    c.io = p->d_io;
+    c.n_sigs = (int)p->sig.size();
+    c.synd = p->d_synd;
+    c.fp64 = p->fp64;
+    c.epart = p->d_epart;
+    c.sigma = p->d_sigma;
+    c.ebin = p->d_ebin;
+    c.sel = p->d_sel;
+    c.cnt = p->d_cnt;
+    c.st_loc = p->d_stloc;
+    c.st_val = p->d_stval;
+    c.shifts = p->d_shifts;
+    c.twiddle = p->d_tw;
+    c.tw_log2 = p->tw_log2;
+    c.omega = p->d_om;
+    c.om_log2 = p->om_log2;
+    c.synd_items = p->d_synd_items;
+    c.n_synd_items = p->n_synd_items;
+    c.bin_items = p->d_bin_items;
+    c.n_bin_items = p->n_bin_items;
+    c.out_items = p->d_out_items;
+    c.n_out_items = p->n_out_items;
+    c.n_general = p->n_general;
+    c.general_sigs = p->d_gsigs;
+    c.orders = nullptr;
+    c.any_general = p->any_general ? 1 : 0;
+    c.keep = p->d_keep;
+    c.flag_list = p->d_flag;
+    return c;
+}
+
+// Enqueue the whole path.  With events != nullptr, record stage boundaries.
+sft_status enqueue(const sft_plan_s* p, const signed char* orders, hipEvent_t* events) {
+    LaunchCtx c = make_ctx(p);
+    c.orders = orders;
+    if (events) HIPCHK(hipEventRecord(events[0], p->stream));
+    HIPCHK(launch_zero_counters(c));
+    HIPCHK(launch_syndromes(c));
+    if (events) HIPCHK(hipEventRecord(events[1], p->stream));
+    HIPCHK(launch_singular_values(c));
+    HIPCHK(launch_select(c));
+    if (events) HIPCHK(hipEventRecord(events[2], p->stream));
+    HIPCHK(launch_decode(c));
+    HIPCHK(launch_cs(c));
+    if (events) HIPCHK(hipEventRecord(events[3], p->stream));
+    HIPCHK(launch_output(c));
+    if (events) HIPCHK(hipEventRecord(events[4], p->stream));
+    return SFT_OK;
+}
+
+sft_status upload_io(sft_plan_s* p, const void* const* xs, const sft_sparse_out* outs) {
+    const size_t n = p->sig.size();
+    for (size_t i = 0; i < n; ++i) {
+        if (!xs[i]) return fail(SFT_E_INVALID, "input pointer is NULL (signal " + std::to_string(i) + ")");
+        const sft_sparse_out& o = outs[i];
+        if (!o.count_dev || o.capacity < 0 || (o.capacity > 0 && (!o.loc_dev || !o.val_dev)))
+            return fail(SFT_E_INVALID, "output list is incomplete (signal " + std::to_string(i) + ")");
+    }
+    if (p->upload_pending) HIPCHK(hipEventSynchronize(p->ev_upload));
+    for (size_t i = 0; i < n; ++i)
+        p->h_io[i] = IoDev{xs[i], outs[i].loc_dev, (double2*)outs[i].val_dev, outs[i].capacity, outs[i].count_dev};
+    HIPCHK(hipMemcpyAsync(p->d_io, p->h_io, n * sizeof(IoDev), hipMemcpyHostToDevice, p->stream));
+    HIPCHK(hipEventRecord(p->ev_upload, p->stream));
+    p->upload_pending = true;
+    return SFT_OK;
+}
+
+// Wait, read the counters, fill stats, derive the status.
+sft_status finish(sft_plan_s* p, sft_stats* st, bool timed) {
+    const size_t n = p->sig.size();
+    HIPCHK(hipMemcpyAsync(p->h_cnt, p->d_cnt, n * sizeof(SigCounters), hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    HIPCHK(hipGetLastError());
+    sft_stats s{};
+    for (size_t i = 0; i < n; ++i) {
+        const SigCounters& c = p->h_cnt[i];
+        s.active_bins += c.active;
+        s.flagged_bins += c.flagged;
+        s.cs_bins += c.cs;
+        s.mlp_fallbacks += c.mlp_fb;
+        s.entries += c.kept;
+        s.nonfinite += c.nonfinite;
+        if (c.kept > p->h_io[i].cap) s.overflowed += 1;
+    }
+    for (int i = 0; i < 4; ++i) s.stage_ms[i] = -1.0;
+    if (timed)
+        for (int i = 0; i < 4; ++i) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, p->ev[i], p->ev[i + 1]));
+            s.stage_ms[i] = ms;
+        }
+    if (st) *st = s;
+    if (s.nonfinite > 0) {
+        bool check = false;
+        for (auto& g : p->sig) check |= (g.flags & SFT_FLAG_CHECK_FINITE) != 0;
+        if (check) return fail(SFT_E_NONFINITE, std::to_string(s.nonfinite) + " non-finite input samples gathered");
+    }
+    if (s.overflowed > 0)
+        return fail(SFT_E_CAPACITY, std::to_string(s.overflowed) + " output list(s) too small; count holds the size");
+    return SFT_OK;
+}
+
+bool any_sync(const sft_plan_s* p) {
+    for (auto& g : p->sig)
+        if (g.flags & SFT_FLAG_SYNC) return true;
+    return false;
+}
+
+sft_status run_single(sft_plan_t plan, const void* x, const sft_sparse_out* out, sft_stats* st, int mode) {
+    if (!plan || !out) return fail(SFT_E_INVALID, "plan or output is NULL");
+    if (plan->sig.size() != 1) return fail(SFT_E_INVALID, "batch plans run through sft_batch");
+    if (plan->sig[0].mode != mode)
+        return fail(SFT_E_INVALID, mode == kExact ? "plan is not in SFT_MODE_EXACT" : "plan is not in SFT_MODE_GENERAL");
+    if ((plan->sig[0].flags & SFT_FLAG_LEARNED) && !plan->mlp)
+        return fail(SFT_E_INVALID, "SFT_FLAG_LEARNED without an attached predictor");
+    const void* xs[1] = {x};
+    sft_status s = upload_io(plan, xs, out);
+    if (s != SFT_OK) return s;
+    const bool timed = st != nullptr;
+    s = sft_enqueue_learned(plan, timed ? plan->ev : nullptr);
+    if (s != SFT_OK) return s;
+    if (st || any_sync(plan)) return finish(plan, st, timed);
+    return SFT_OK;
+}
+
+}  // namespace
+
+// Learned-mode hook: the predictor (mlp.hip) fills per-bin orders before the
+// decoder runs; without a predictor this is the plain enqueue.
+sft_status sft_enqueue_learned(sft_plan_t plan, hipEvent_t* events) {
+    const signed char* orders = nullptr;
+    if (plan->mlp && (plan->sig[0].flags & SFT_FLAG_LEARNED)) {
+        sft_status s = sft_mlp_enqueue_orders(plan, &orders);
+        if (s != SFT_OK) return s;
+    }
+    return enqueue(plan, orders, events);
+}
+
+extern "C" {
+
+int32_t sft_abi_version(void) { return SFT_ABI_VERSION; }
+
+const char* sft_last_error(void) { return g_err.c_str(); }
+
+const char* sft_status_str(sft_status s) {
+    switch (s) {
+        case SFT_OK: return "SFT_OK";
+        case SFT_E_INVALID: return "SFT_E_INVALID";
+        case SFT_E_UNSUPPORTED: return "SFT_E_UNSUPPORTED";
+        case SFT_E_NOMEM: return "SFT_E_NOMEM";
+        case SFT_E_DEVICE: return "SFT_E_DEVICE";
+        case SFT_E_CAPACITY: return "SFT_E_CAPACITY";
+        case SFT_E_NONFINITE: return "SFT_E_NONFINITE";
+    }
+    return "unknown status";
+}
+
+sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params, void* hip_stream) {
+    if (!out) return fail(SFT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!params || n_params < 1) return fail(SFT_E_INVALID, "need at least one parameter set");
+    if (n_params > (1 << 24)) return fail(SFT_E_UNSUPPORTED, "too many signals in one plan");
+    std::vector<SigHost> sigs((size_t)n_params);
+    std::string msg;
+    for (int64_t i = 0; i < n_params; ++i) {
+        sft_status s = resolve_params(params[i], n_params > 1, &sigs[(size_t)i], &msg);
+        if (s != SFT_OK) return fail(s, "signal " + std::to_string(i) + ": " + msg);
+    }
+    for (auto& g : sigs)
+        if (g.dtype != sigs[0].dtype) return fail(SFT_E_UNSUPPORTED, "all signals of a plan need one input dtype");
+
+    sft_plan_s* p = new sft_plan_s();
+    p->stream = (hipStream_t)hip_stream;
+    p->sig = std::move(sigs);
+    p->fp64 = p->sig[0].dtype == SFT_C128;
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        release(p);
+        return fail(SFT_E_DEVICE, "no HIP device");
+    }
+    PlanLayout lay;
+    build_layout(p->sig, p->fp64, &lay);
+    p->any_general = lay.n_general > 0;
+    p->n_general = lay.n_general;
+    p->tw_log2 = lay.tw_log2;
+    p->om_log2 = lay.om_log2;
+    p->n_synd_items = (int)lay.synd_items.size();
+    p->n_bin_items = (int)lay.bin_items.size();
+    p->n_out_items = (int)lay.out_items.size();
+
+    const size_t ns = p->sig.size();
+    sft_status s = SFT_OK;
+#define TRY(x)             \
+    do {                   \
+        s = (x);           \
+        if (s != SFT_OK) { \
+            release(p);    \
+            return s;      \
+        }                  \
+    } while (0)
+    TRY(dalloc(p, &p->d_sigs, ns));
+    TRY(dalloc(p, &p->d_io, ns));
+    if (p->fp64) {
+        double2* t = nullptr;
+        TRY(dalloc(p, &t, (size_t)lay.synd_elems));
+        p->d_synd = t;
+        double2* tw = nullptr;
+        TRY(dalloc(p, &tw, (size_t)1 << lay.tw_log2));
+        p->d_tw = tw;
+    } else {
+        float2* t = nullptr;
+        TRY(dalloc(p, &t, (size_t)lay.synd_elems));
+        p->d_synd = t;
+        float2* tw = nullptr;
+        TRY(dalloc(p, &tw, (size_t)1 << lay.tw_log2));
+        p->d_tw = tw;
+    }
+    TRY(dalloc(p, &p->d_epart, (size_t)lay.epart_elems));
+    TRY(dalloc(p, &p->d_sigma, lay.n_general ? (size_t)lay.sigma_elems : 1));
+    TRY(dalloc(p, &p->d_ebin, lay.n_general ? (size_t)lay.bin_elems : 1));
+    TRY(dalloc(p, &p->d_sel, ns));
+    TRY(dalloc(p, &p->d_cnt, ns));
+    TRY(dalloc(p, &p->d_stloc, (size_t)lay.stage_elems));
+    TRY(dalloc(p, &p->d_stval, (size_t)lay.stage_elems));
+    TRY(dalloc(p, &p->d_keep, (size_t)lay.stage_elems));
+    TRY(dalloc(p, &p->d_shifts, lay.shifts.size()));
+    TRY(dalloc(p, &p->d_om, (size_t)1 << lay.om_log2));
+    TRY(dalloc(p, &p->d_synd_items, lay.synd_items.size()));
+    TRY(dalloc(p, &p->d_bin_items, lay.bin_items.size()));
+    TRY(dalloc(p, &p->d_out_items, lay.out_items.size()));
+    TRY(dalloc(p, &p->d_gsigs, lay.general_sigs.size()));
+    TRY(dalloc(p, &p->d_orders, (size_t)lay.bin_elems));
+    TRY(dalloc(p, &p->d_flag, lay.n_general ? (size_t)lay.bin_elems : 1));
+
+#define HIPTRY(call)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess) {                                                                        \
+            release(p);                                                                                \
+            return fail(SFT_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));              \
+        }                                                                                              \
+    } while (0)
+    HIPTRY(hipMemcpy(p->d_sigs, lay.sigdev.data(), ns * sizeof(SigDev), hipMemcpyHostToDevice));
+    HIPTRY(hipMemcpy(p->d_shifts, lay.shifts.data(), lay.shifts.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    if (p->fp64) {
+        std::vector<double2> tw;
+        twiddle_table_f64(lay.tw_log2, &tw);
+        HIPTRY(hipMemcpy(p->d_tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice));
+    } else {
+        std::vector<float2> tw;
+        twiddle_table_f32(lay.tw_log2, &tw);
+        HIPTRY(hipMemcpy(p->d_tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice));
+    }
+    {
+        std::vector<double2> om;
+        omega_table(lay.om_log2, &om);
+        HIPTRY(hipMemcpy(p->d_om, om.data(), om.size() * sizeof(double2), hipMemcpyHostToDevice));
+    }
+    HIPTRY(hipMemcpy(p->d_synd_items, lay.synd_items.data(), lay.synd_items.size() * sizeof(int4), hipMemcpyHostToDevice));
+    HIPTRY(hipMemcpy(p->d_bin_items, lay.bin_items.data(), lay.bin_items.size() * sizeof(int2), hipMemcpyHostToDevice));
+    HIPTRY(hipMemcpy(p->d_out_items, lay.out_items.data(), lay.out_items.size() * sizeof(int2), hipMemcpyHostToDevice));
+    if (!lay.general_sigs.empty())
+        HIPTRY(hipMemcpy(p->d_gsigs, lay.general_sigs.data(), lay.general_sigs.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPTRY(hipMemset(p->d_orders, 0, (size_t)lay.bin_elems));
+    HIPTRY(hipMemset(p->d_cnt, 0, ns * sizeof(SigCounters)));
+    HIPTRY(hipHostMalloc((void**)&p->h_io, ns * sizeof(IoDev), hipHostMallocDefault));
+    HIPTRY(hipHostMalloc((void**)&p->h_cnt, ns * sizeof(SigCounters), hipHostMallocDefault));
+    HIPTRY(hipEventCreateWithFlags(&p->ev_upload, hipEventDisableTiming));
+    for (auto& e : p->ev) HIPTRY(hipEventCreate(&e));
+    HIPTRY(hipDeviceSynchronize());
+    *out = p;
+    return SFT_OK;
+}
+
+sft_status sft_exact(sft_plan_t plan, const void* x_dev, const sft_sparse_out* out, sft_stats* stats) {
+    return run_single(plan, x_dev, out, stats, kExact);
+}
+
+sft_status sft_general(sft_plan_t plan, const void* x_dev, const sft_sparse_out* out, sft_stats* stats) {
+    return run_single(plan, x_dev, out, stats, kGeneral);
+}
+
+sft_status sft_batch(sft_plan_t plan, const void* const* x_devs, const sft_sparse_out* outs, sft_stats* stats) {
+    if (!plan || !x_devs || !outs) return fail(SFT_E_INVALID, "plan, inputs or outputs is NULL");
+    for (auto& g : plan->sig)
+        if (g.flags & SFT_FLAG_LEARNED) {
+            if (!plan->mlp) return fail(SFT_E_INVALID, "SFT_FLAG_LEARNED without an attached predictor");
+        }
+    sft_status s = upload_io(plan, x_devs, outs);
+    if (s != SFT_OK) return s;
+    if (stats) {
+        s = sft_enqueue_learned(plan, plan->ev);
+        if (s != SFT_OK) return s;
+        return finish(plan, stats, true);
+    }
+    if (plan->stream == nullptr) {
+        // the legacy default stream cannot be captured: enqueue directly
+        s = sft_enqueue_learned(plan, nullptr);
+    } else {
+        if (!plan->gexec) {
+            HIPCHK(hipStreamBeginCapture(plan->stream, hipStreamCaptureModeThreadLocal));
+            sft_status cs = sft_enqueue_learned(plan, nullptr);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(plan->stream, &g);
+            if (cs != SFT_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return cs;
+            }
+            if (e != hipSuccess) return fail(SFT_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+            plan->graph = g;
+            HIPCHK(hipGraphInstantiate(&plan->gexec, plan->graph, nullptr, nullptr, 0));
+        }
+        HIPCHK(hipGraphLaunch(plan->gexec, plan->stream));
+    }
+    if (s != SFT_OK) return s;
+    if (any_sync(plan)) return finish(plan, nullptr, false);
+    return SFT_OK;
+}
+
+sft_status sft_syndromes(sft_plan_t plan, const void* x_dev, void* out_dev) {
+    if (!plan || !x_dev || !out_dev) return fail(SFT_E_INVALID, "plan, input or output is NULL");
+    if (plan->sig.size() != 1) return fail(SFT_E_INVALID, "sft_syndromes needs a single-signal plan");
+    if (plan->upload_pending) HIPCHK(hipEventSynchronize(plan->ev_upload));
+    plan->h_io[0] = IoDev{x_dev, nullptr, nullptr, 0, nullptr};
+    HIPCHK(hipMemcpyAsync(plan->d_io, plan->h_io, sizeof(IoDev), hipMemcpyHostToDevice, plan->stream));
+    HIPCHK(hipEventRecord(plan->ev_upload, plan->stream));
+    plan->upload_pending = true;
+    LaunchCtx c = make_ctx(plan);
+    HIPCHK(launch_zero_counters(c));
+    HIPCHK(launch_syndromes(c));
+    const SigHost& g = plan->sig[0];
+    const size_t bytes = (size_t)g.S * (size_t)g.m * (plan->fp64 ? sizeof(double2) : sizeof(float2));
+    HIPCHK(hipMemcpyAsync(out_dev, plan->d_synd, bytes, hipMemcpyDeviceToDevice, plan->stream));
+    if (any_sync(plan)) HIPCHK(hipStreamSynchronize(plan->stream));
+    return SFT_OK;
+}
+
+sft_status sft_plan_get(sft_plan_t plan, int64_t index, sft_plan_info* info) {
+    if (!plan || !info) return fail(SFT_E_INVALID, "plan or info is NULL");
+    if (index < 0 || index >= (int64_t)plan->sig.size()) return fail(SFT_E_INVALID, "index out of range");
+    const SigHost& g = plan->sig[(size_t)index];
+    std::memset(info, 0, sizeof(*info));
+    info->n = g.n;
+    info->k = g.k;
+    info->m = g.m;
+    info->d = g.d;
+    info->l = g.L;
+    info->r = g.R;
+    info->in_dtype = g.dtype;
+    info->mode = g.mode;
+    info->flags = g.flags;
+    info->n_signals = (int32_t)plan->sig.size();
+    for (int j = 0; j < g.R; ++j) info->rshifts[j] = g.rshifts[(size_t)j];
+    info->tau_zero = g.tau_zero;
+    info->tau_rank = g.tau_rank;
+    info->tau_res = g.tau_res;
+    info->tau_amp = g.tau_amp;
+    info->c_res = g.c_res;
+    info->delta_grid = g.delta_grid;
+    info->delta_mag = g.delta_mag;
+    info->workspace_bytes = plan->ws_bytes;
+    return SFT_OK;
+}
+
+void sft_destroy(sft_plan_t plan) { release(plan); }
+
+}  // extern "C"
+
+// Accessors used by the learned-mode translation unit.
+sft_mlp_t& sft_plan_mlp_slot(sft_plan_t plan) { return plan->mlp; }
+signed char* sft_plan_orders(sft_plan_t plan) { return plan->d_orders; }
+LaunchCtx sft_plan_ctx(sft_plan_t plan) { return make_ctx(plan); }

@@ -1,0 +1,154 @@
+// Internal declarations of the sFFT-DT device library (gfx950).
+//
+// Layout in HBM (per plan; offsets are per signal and live in SigDev):
+//   syndromes  [sig][line][k]   line = shift index (2L consecutive shifts, then R
+//                               random shifts n_j), k = bin; complex float for
+//                               complex64 input, complex double for complex128.
+//                               Shift-major so that the FFT writer and the
+//                               lane-per-bin decoder both access it coalesced.
+//   epart      [sig][line]      sum_k |m_l[k]|^2 (FP64), for mean_k E_k
+//   sigma      [sig][k][L]      Hankel singular values (general mode)
+//   ebin       [sig][k]         E_k (general mode)
+//   staging    [sig][M*L]       (location, value) pairs appended by the decoder
+//   counters   [sig]            SigCounters
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sft {
+
+constexpr int kMaxL = 4;
+constexpr int kMaxLines = 2 * kMaxL + 64;   // 2L consecutive + up to 64 random shifts
+constexpr int kBlock = 256;                 // threads per block of every kernel but select
+constexpr int kFftPointsF32 = 8192;         // points per block in LDS (64 KiB)
+constexpr int kFftPointsF64 = 4096;
+
+enum Mode { kExact = 0, kGeneral = 1 };
+
+// Per-signal description, built by the plan and read by every kernel.
+struct SigDev {
+    int64_t n, d;            // N, d = N / M
+    int32_t m, log2m;        // M
+    int32_t L, R, S;         // max order, random shifts, lines = 2L (+ R)
+    int32_t mode, k_votes;   // Mode, K (general mode vote / output size)
+    int32_t flags;
+    int64_t synd_off;        // element offset of [S][M] in the syndrome buffer
+    int64_t epart_off;       // offset of [S] in epart
+    int64_t bin_off;         // offset of [M] per-bin arrays (sigma uses bin_off * L)
+    int64_t stage_off;       // offset of the staging list
+    int32_t stage_cap;       // = M * L
+    int32_t shift_off;       // offset of the S shift values in the shift table
+    int32_t tab_stride;      // omega table stride: w_d^q = tab[q * tab_stride]
+    int32_t pad0;
+    double tau_zero2, tau_rank, tau_res2, tau_amp, c_res, delta_grid, delta_mag;
+};
+
+// Per-call input/output pointers of a signal.
+struct IoDev {
+    const void* x;
+    int64_t* loc;
+    double2* val;
+    int64_t cap;
+    int64_t* count;
+};
+
+struct SigCounters {
+    int stage_count, active, flagged, cs, mlp_fb, nonfinite, kept, nflag;   // nflag: CS queue length
+};
+
+struct SelDev {             // per-signal results of the selection pass (general mode)
+    unsigned long long thr_key;   // K-th largest singular value (as ordered bits)
+    long long thr_idx;            // ties at thr_key vote when flat index <= thr_idx
+    double nu;                    // noise floor
+    double pad;
+};
+
+// ---------------------------------------------------------------- complex FP64
+
+struct zd {
+    double x, y;
+};
+__host__ __device__ inline zd mk(double a, double b) { return zd{a, b}; }
+__host__ __device__ inline zd operator+(zd a, zd b) { return zd{a.x + b.x, a.y + b.y}; }
+__host__ __device__ inline zd operator-(zd a, zd b) { return zd{a.x - b.x, a.y - b.y}; }
+__host__ __device__ inline zd operator-(zd a) { return zd{-a.x, -a.y}; }
+__host__ __device__ inline zd operator*(zd a, zd b) { return zd{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__host__ __device__ inline zd operator*(double s, zd a) { return zd{s * a.x, s * a.y}; }
+__host__ __device__ inline zd conj(zd a) { return zd{a.x, -a.y}; }
+__host__ __device__ inline double norm2(zd a) { return a.x * a.x + a.y * a.y; }
+__host__ __device__ inline double cabs(zd a) { return sqrt(norm2(a)); }
+__host__ __device__ inline zd cmul_conj(zd a, zd b) { return conj(a) * b; }   // conj(a) * b
+__host__ __device__ inline zd cdiv(zd a, zd b) {
+    // Smith's algorithm
+    if (fabs(b.x) >= fabs(b.y)) {
+        double r = b.y / b.x, den = b.x + b.y * r;
+        return zd{(a.x + a.y * r) / den, (a.y - a.x * r) / den};
+    }
+    double r = b.x / b.y, den = b.x * r + b.y;
+    return zd{(a.x * r + a.y) / den, (a.y * r - a.x) / den};
+}
+__host__ __device__ inline zd csqrt(zd a) {
+    double r = hypot(a.x, a.y);
+    if (r == 0.0) return zd{0.0, 0.0};
+    if (a.x >= 0.0) {
+        double t = sqrt(0.5 * (r + a.x));
+        return zd{t, a.y / (2.0 * t)};
+    }
+    double t = sqrt(0.5 * (r - a.x));
+    return zd{fabs(a.y) / (2.0 * t), copysign(t, a.y)};
+}
+__host__ __device__ inline bool cfinite(zd a) { return __builtin_isfinite(a.x) && __builtin_isfinite(a.y); }
+
+// e^{i 2 pi q / n} for an integer phase 0 <= q < n, n a power of two.
+__device__ inline zd unit_root(int64_t q, int64_t n) {
+    double s, c;
+    sincospi(2.0 * (double)q / (double)n, &s, &c);
+    return zd{c, s};
+}
+
+// ---------------------------------------------------------------- host launchers
+// Defined in the .hip translation units; called by the C ABI layer.
+
+struct LaunchCtx {
+    hipStream_t stream;
+    const SigDev* sigs;
+    const IoDev* io;
+    int n_sigs;
+    void* synd;              // float2* or double2*
+    bool fp64;
+    double* epart;
+    double* sigma;
+    double* ebin;
+    SelDev* sel;
+    SigCounters* cnt;
+    int64_t* st_loc;
+    double2* st_val;
+    const int64_t* shifts;
+    const void* twiddle;     // float2* / double2* of size 2^tw_log2: e^{-2 pi i q / 2^tw_log2}
+    int tw_log2;
+    const double2* omega;    // e^{+2 pi i q / 2^om_log2}, FP64
+    int om_log2;
+    const int4* synd_items;  // (sig, line0, nlines, 0)
+    int n_synd_items;
+    const int2* bin_items;   // (sig, bin0): tiles of kBlock bins
+    int n_bin_items;
+    const int2* out_items;   // (sig, entry0): tiles of kBlock staging entries
+    int n_out_items;
+    int n_general;           // signals in general mode
+    const int* general_sigs; // their indices
+    const signed char* orders;   // learned order per bin (nullable), indexed by bin_off + k
+    int any_general;
+    unsigned char* keep;     // per staging entry: kept in the output
+    int* flag_list;          // per signal [M]: bins queued for the CS step (general mode)
+};
+
+hipError_t launch_zero_counters(const LaunchCtx& c);
+hipError_t launch_syndromes(const LaunchCtx& c);
+hipError_t launch_singular_values(const LaunchCtx& c);
+hipError_t launch_select(const LaunchCtx& c);
+hipError_t launch_decode(const LaunchCtx& c);
+hipError_t launch_cs(const LaunchCtx& c);
+hipError_t launch_output(const LaunchCtx& c);
+
+}  // namespace sft

@@ -1,0 +1,299 @@
+// Host-side planning for the sFFT-DT device path.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <set>
+
+#include "plan_host.h"
+
+namespace sft {
+
+namespace {
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int ilog2(int64_t v) {
+    int r = 0;
+    while ((int64_t(1) << r) < v) ++r;
+    return r;
+}
+
+uint64_t splitmix64(uint64_t& s) {
+    uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+constexpr int64_t kMaxD = int64_t(1) << 22;   // omega table bound
+
+}  // namespace
+
+int64_t max_m(int dtype) { return dtype == SFT_C128 ? kFftPointsF64 : kFftPointsF32; }
+
+int64_t default_m(int64_t n, int64_t k, int dtype) {
+    int64_t m = 1;
+    while (m < 4 * k) m <<= 1;
+    if (m > n) m = n;
+    int64_t cap = max_m(dtype);
+    if (m > cap) m = cap;
+    while (n / m > kMaxD) m <<= 1;
+    return m;
+}
+
+std::vector<int64_t> draw_shifts(uint64_t seed, int64_t d, int r) {
+    std::set<int64_t> got;
+    uint64_t st = seed;
+    while ((int)got.size() < r) {
+        // unbiased draw in [0, d) for d a power of two
+        int64_t v = (int64_t)(splitmix64(st) & (uint64_t)(d - 1));
+        got.insert(v);
+    }
+    return std::vector<int64_t>(got.begin(), got.end());
+}
+
+sft_status resolve_params(const sft_params& in, bool batch, SigHost* g, std::string* msg) {
+    (void)batch;
+    if (in.reserved != 0) {
+        *msg = "reserved field must be 0";
+        return SFT_E_INVALID;
+    }
+    if (in.in_dtype != SFT_C64 && in.in_dtype != SFT_C128) {
+        *msg = "in_dtype must be SFT_C64 or SFT_C128";
+        return SFT_E_INVALID;
+    }
+    if (in.mode != SFT_MODE_EXACT && in.mode != SFT_MODE_GENERAL) {
+        *msg = "mode must be SFT_MODE_EXACT or SFT_MODE_GENERAL";
+        return SFT_E_INVALID;
+    }
+    if (in.n < 2 || in.k < 1 || in.k > in.n) {
+        *msg = "need N >= 2 and 1 <= K <= N";
+        return SFT_E_INVALID;
+    }
+    if (!is_pow2(in.n) || in.n > (int64_t(1) << 40)) {
+        *msg = "N must be a power of two (at most 2^40)";
+        return SFT_E_UNSUPPORTED;
+    }
+    const uint32_t known = SFT_FLAG_LEARNED | SFT_FLAG_SYNC | SFT_FLAG_CHECK_FINITE;
+    if (in.flags & ~known) {
+        *msg = "unknown flag bits";
+        return SFT_E_INVALID;
+    }
+    if ((in.flags & SFT_FLAG_LEARNED) && in.mode != SFT_MODE_EXACT) {
+        *msg = "the learned order predictor applies to SFT_MODE_EXACT";
+        return SFT_E_UNSUPPORTED;
+    }
+    g->n = in.n;
+    g->k = in.k;
+    g->dtype = in.in_dtype;
+    g->mode = in.mode;
+    g->flags = in.flags;
+    g->seed = in.seed;
+    g->L = in.l == 0 ? 4 : in.l;
+    if (g->L < 1 || g->L > kMaxL) {
+        *msg = "L must be in 1..4";
+        return SFT_E_UNSUPPORTED;
+    }
+    g->m = in.m == 0 ? default_m(in.n, in.k, in.in_dtype) : in.m;
+    if (!is_pow2(g->m) || g->m > in.n) {
+        *msg = "M must be a power of two dividing N";
+        return SFT_E_UNSUPPORTED;
+    }
+    if (g->m > max_m(in.in_dtype)) {
+        *msg = "M above " + std::to_string(max_m(in.in_dtype)) + " is not supported for this input type";
+        return SFT_E_UNSUPPORTED;
+    }
+    g->d = in.n / g->m;
+    if (g->d > kMaxD) {
+        *msg = "d = N/M above 2^22 is not supported";
+        return SFT_E_UNSUPPORTED;
+    }
+    if ((int64_t)g->m * g->L > (int64_t(1) << 30)) {
+        *msg = "M * L too large";
+        return SFT_E_UNSUPPORTED;
+    }
+    if (g->mode == SFT_MODE_GENERAL) {
+        int64_t r = in.r == 0 ? std::min<int64_t>(3 * g->L, g->d) : in.r;
+        if (r < 1 || r > 16 || r > g->d) {
+            *msg = "R must be in 1..16 and at most d";
+            return SFT_E_UNSUPPORTED;
+        }
+        g->R = (int)r;
+        g->rshifts = draw_shifts(in.seed, g->d, g->R);
+        if (g->k > (int64_t)g->m * g->L) {
+            *msg = "K exceeds M * L: the vote cannot assign K orders";
+            return SFT_E_UNSUPPORTED;
+        }
+    } else {
+        if (in.r != 0) {
+            *msg = "R applies to SFT_MODE_GENERAL only";
+            return SFT_E_INVALID;
+        }
+        g->R = 0;
+    }
+    g->S = 2 * g->L + g->R;
+    const bool c128 = in.in_dtype == SFT_C128;
+    auto pick = [](double v, double def) { return v == 0.0 ? def : v; };
+    g->tau_zero = pick(in.tau_zero, c128 ? 1e-9 : 1e-4);
+    g->tau_rank = pick(in.tau_rank, c128 ? 1e-10 : 1e-5);
+    g->tau_res = pick(in.tau_res, c128 ? 1e-9 : 1e-4);
+    g->tau_amp = pick(in.tau_amp, c128 ? 1e-9 : 1e-4);
+    g->c_res = pick(in.c_res, 3.0);
+    g->delta_grid = pick(in.delta_grid, 0.1);
+    g->delta_mag = pick(in.delta_mag, 0.05);
+    for (double v : {g->tau_zero, g->tau_rank, g->tau_res, g->tau_amp, g->c_res, g->delta_grid, g->delta_mag})
+        if (!(v > 0.0) || !std::isfinite(v)) {
+            *msg = "thresholds must be positive and finite";
+            return SFT_E_INVALID;
+        }
+    if (g->delta_grid >= 0.5) {
+        *msg = "delta_grid must be below 0.5";
+        return SFT_E_INVALID;
+    }
+    return SFT_OK;
+}
+
+void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) {
+    const int64_t pmax = fp64 ? kFftPointsF64 : kFftPointsF32;
+    int64_t mmax = 1, dmax = 1;
+    for (auto& g : sigs) {
+        mmax = std::max(mmax, g.m);
+        dmax = std::max(dmax, g.d);
+    }
+    lay->tw_log2 = ilog2(mmax);
+    lay->om_log2 = ilog2(dmax);
+
+    // Assign signals to 8 lanes (one per XCD) by greedy balancing of their
+    // syndrome work, so that every block of a signal runs on one XCD.
+    const int kLanes = 8;
+    std::vector<std::vector<int>> lane_sigs(kLanes);
+    {
+        std::vector<int> order(sigs.size());
+        for (size_t i = 0; i < sigs.size(); ++i) order[i] = (int)i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return sigs[a].S * sigs[a].m > sigs[b].S * sigs[b].m;
+        });
+        std::vector<int64_t> load(kLanes, 0);
+        for (int s : order) {
+            int best = 0;
+            for (int l = 1; l < kLanes; ++l)
+                if (load[l] < load[best]) best = l;
+            lane_sigs[best].push_back(s);
+            load[best] += sigs[s].S * sigs[s].m;
+        }
+        for (auto& v : lane_sigs) std::sort(v.begin(), v.end());
+    }
+
+    int64_t synd = 0, ep = 0, bins = 0, stage = 0;
+    lay->sigdev.resize(sigs.size());
+    for (size_t i = 0; i < sigs.size(); ++i) {
+        const SigHost& g = sigs[i];
+        SigDev& s = lay->sigdev[i];
+        std::memset(&s, 0, sizeof(s));
+        s.n = g.n;
+        s.d = g.d;
+        s.m = (int32_t)g.m;
+        s.log2m = ilog2(g.m);
+        s.L = g.L;
+        s.R = g.R;
+        s.S = g.S;
+        s.mode = g.mode;
+        s.k_votes = (int32_t)std::min<int64_t>(g.k, INT32_MAX);
+        s.flags = (int32_t)g.flags;
+        s.synd_off = synd;
+        s.epart_off = ep;
+        s.bin_off = bins;
+        s.stage_off = stage;
+        s.stage_cap = (int32_t)(g.m * g.L);
+        s.shift_off = (int32_t)lay->shifts.size();
+        s.tab_stride = (int32_t)(dmax / g.d);
+        s.tau_zero2 = g.tau_zero * g.tau_zero;
+        s.tau_rank = g.tau_rank;
+        s.tau_res2 = g.tau_res * g.tau_res;
+        s.tau_amp = g.tau_amp;
+        s.c_res = g.c_res;
+        s.delta_grid = g.delta_grid;
+        s.delta_mag = g.delta_mag;
+        for (int l = 0; l < 2 * g.L; ++l) lay->shifts.push_back(l);
+        for (int64_t v : g.rshifts) lay->shifts.push_back(v);
+        synd += (int64_t)g.S * g.m;
+        ep += g.S;
+        bins += g.m;
+        stage += g.m * g.L;
+        if (g.mode == SFT_MODE_GENERAL) lay->general_sigs.push_back((int)i);
+    }
+    lay->synd_elems = synd;
+    lay->epart_elems = ep;
+    lay->bin_elems = bins;
+    lay->sigma_elems = bins * kMaxL;
+    lay->stage_elems = stage;
+    lay->n_general = (int)lay->general_sigs.size();
+
+    // Work items per lane, then interleaved so that item id % 8 == lane: the
+    // hardware hands consecutive block ids to the XCDs in turn.  Short lanes
+    // are padded with no-op items.
+    auto interleave = [&](auto per_signal, auto pad, auto& out) {
+        using Item = typename std::decay<decltype(out)>::type::value_type;
+        std::vector<std::vector<Item>> lanes(kLanes);
+        for (int l = 0; l < kLanes; ++l)
+            for (int s : lane_sigs[l]) per_signal(s, lanes[l]);
+        size_t len = 0;
+        for (auto& v : lanes) len = std::max(len, v.size());
+        size_t used = 0;
+        for (int l = 0; l < kLanes; ++l)
+            if (!lanes[l].empty()) used = l + 1;
+        if (sigs.size() < (size_t)kLanes) {
+            // few signals: no padding, items of each signal stay adjacent
+            for (auto& v : lanes)
+                for (auto& it : v) out.push_back(it);
+            return;
+        }
+        (void)used;
+        for (size_t j = 0; j < len; ++j)
+            for (int l = 0; l < kLanes; ++l) out.push_back(j < lanes[l].size() ? lanes[l][j] : pad);
+    };
+    interleave(
+        [&](int s, std::vector<int4>& v) {
+            const SigHost& g = sigs[s];
+            int nl = (int)std::max<int64_t>(1, std::min<int64_t>(g.S, pmax / g.m));
+            for (int l0 = 0; l0 < g.S; l0 += nl) v.push_back(int4{s, l0, std::min(nl, g.S - l0), 0});
+        },
+        int4{-1, 0, 0, 0}, lay->synd_items);
+    interleave(
+        [&](int s, std::vector<int2>& v) {
+            for (int64_t b = 0; b < sigs[s].m; b += kBlock) v.push_back(int2{s, (int)b});
+        },
+        int2{-1, 0}, lay->bin_items);
+    interleave(
+        [&](int s, std::vector<int2>& v) {
+            for (int64_t e = 0; e < sigs[s].m * sigs[s].L; e += kBlock) v.push_back(int2{s, (int)e});
+        },
+        int2{-1, 0}, lay->out_items);
+}
+
+void twiddle_table_f64(int log2n, std::vector<double2>* out) {
+    const int64_t n = int64_t(1) << log2n;
+    out->resize((size_t)n);
+    for (int64_t q = 0; q < n; ++q) {
+        const double a = -2.0 * M_PI * (double)q / (double)n;
+        (*out)[(size_t)q] = double2{std::cos(a), std::sin(a)};
+    }
+}
+
+void twiddle_table_f32(int log2n, std::vector<float2>* out) {
+    std::vector<double2> t;
+    twiddle_table_f64(log2n, &t);
+    out->resize(t.size());
+    for (size_t i = 0; i < t.size(); ++i) (*out)[i] = float2{(float)t[i].x, (float)t[i].y};
+}
+
+void omega_table(int log2n, std::vector<double2>* out) {
+    const int64_t n = int64_t(1) << log2n;
+    out->resize((size_t)n);
+    for (int64_t q = 0; q < n; ++q) {
+        const double a = 2.0 * M_PI * (double)q / (double)n;
+        (*out)[(size_t)q] = double2{std::cos(a), std::sin(a)};
+    }
+}
+
+}  // namespace sft

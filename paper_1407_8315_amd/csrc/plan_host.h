@@ -1,0 +1,64 @@
+// Host-side planning: parameter resolution, random shifts, workspace layout,
+// work-item order, tables.  Pure host C++ (no device code).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "sft.h"
+
+namespace sft {
+
+struct SigHost {
+    int64_t n = 0, k = 0, m = 0, d = 0;
+    int L = 0, R = 0, S = 0, mode = 0, dtype = 0;
+    uint32_t flags = 0;
+    uint64_t seed = 0;
+    std::vector<int64_t> rshifts;   // n_0 .. n_{R-1}
+    double tau_zero = 0, tau_rank = 0, tau_res = 0, tau_amp = 0, c_res = 0, delta_grid = 0, delta_mag = 0;
+};
+
+struct PlanLayout {
+    std::vector<SigDev> sigdev;
+    std::vector<int64_t> shifts;          // per signal: 0..2L-1, then n_j
+    std::vector<int4> synd_items;         // (sig, line0, nlines, 0); sig < 0 = padding
+    std::vector<int2> bin_items;          // (sig, bin0)
+    std::vector<int2> out_items;          // (sig, entry0)
+    std::vector<int> general_sigs;
+    int64_t synd_elems = 0, epart_elems = 0, sigma_elems = 0, bin_elems = 0, stage_elems = 0;
+    int tw_log2 = 0, om_log2 = 0;
+    int n_general = 0;
+};
+
+// Largest supported downsampled length per input type (one block's LDS).
+int64_t max_m(int dtype);
+
+// Fill defaults and validate one parameter set.
+sft_status resolve_params(const sft_params& in, bool batch, SigHost* out, std::string* msg);
+
+// Default M for K: 4K rounded up to a power of two, at most N (Sec. II-E's
+// d = N / (4K)); batch plans refine M and L with the autotuner.
+int64_t default_m(int64_t n, int64_t k, int dtype);
+
+// R distinct shifts in [0, d), uniform, from a splitmix64 stream of `seed`; ascending.
+std::vector<int64_t> draw_shifts(uint64_t seed, int64_t d, int r);
+
+void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay);
+
+void twiddle_table_f32(int log2n, std::vector<float2>* out);    // e^{-2 pi i q / 2^log2n}
+void twiddle_table_f64(int log2n, std::vector<double2>* out);
+void omega_table(int log2n, std::vector<double2>* out);         // e^{+2 pi i q / 2^log2n}
+
+}  // namespace sft
+
+// Enqueue the path of a plan (learned orders first when a predictor is attached).
+sft_status sft_enqueue_learned(sft_plan_t plan, hipEvent_t* events);
+// Learned mode: run the predictor over the plan's bins and return the order array.
+sft_status sft_mlp_enqueue_orders(sft_plan_t plan, const signed char** orders);
+// Plan accessors for other translation units.
+sft_mlp_t& sft_plan_mlp_slot(sft_plan_t plan);
+signed char* sft_plan_orders(sft_plan_t plan);
+sft::LaunchCtx sft_plan_ctx(sft_plan_t plan);

@@ -1,0 +1,112 @@
+"""The C ABI without a GPU: the library loads, exports every function the
+header declares, its struct layouts match the ctypes mirror, and parameter
+validation answers with the documented status codes before touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sft.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1407_8315_amd import _lib
+
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1407_8315_amd import build
+
+        build.build(verbose=False)
+    return _lib.load()
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sft_\w+)\s*\(", text)))
+
+
+def test_every_declared_function_is_exported(lib):
+    from paper_1407_8315_amd import _lib
+
+    declared = header_functions()
+    assert sorted(_lib.EXPORTS) == declared
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_version_and_status_strings(lib):
+    from paper_1407_8315_amd import _lib
+
+    assert lib.sft_abi_version() == 1
+    assert lib.sft_status_str(_lib.SFT_E_CAPACITY) == b"SFT_E_CAPACITY"
+    assert lib.sft_status_str(99) == b"unknown status"
+
+
+def test_struct_layouts_match_c(tmp_path):
+    from paper_1407_8315_amd import _lib
+
+    prog = tmp_path / "layout.c"
+    prog.write_text("""
+#include <stddef.h>
+#include <stdio.h>
+#include "sft.h"
+int main(void) {
+  printf("%zu %zu %zu %zu\\n", sizeof(sft_params), sizeof(sft_sparse_out), sizeof(sft_stats), sizeof(sft_plan_info));
+  printf("%zu %zu %zu\\n", offsetof(sft_params, seed), offsetof(sft_params, delta_mag), offsetof(sft_plan_info, rshifts));
+  printf("%zu %zu\\n", offsetof(sft_plan_info, tau_zero), offsetof(sft_stats, stage_ms));
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    got = list(map(int, out))
+    want = [ctypes.sizeof(_lib.Params), ctypes.sizeof(_lib.SparseOut), ctypes.sizeof(_lib.Stats),
+            ctypes.sizeof(_lib.PlanInfo), _lib.Params.seed.offset, _lib.Params.delta_mag.offset,
+            _lib.PlanInfo.rshifts.offset, _lib.PlanInfo.tau_zero.offset, _lib.Stats.stage_ms.offset]
+    assert got == want
+
+
+def _plan_status(lib, **kw):
+    from paper_1407_8315_amd import _lib, make_params
+
+    p = make_params(**kw)
+    h = ctypes.c_void_p()
+    st = lib.sft_plan(ctypes.byref(h), ctypes.byref(p), 1, None)
+    return st, h
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n=1000, k=10), "SFT_E_UNSUPPORTED"),                 # N not a power of two
+    (dict(n=1 << 14, k=0), "SFT_E_INVALID"),                   # K <= 0
+    (dict(n=1 << 14, k=(1 << 14) + 1), "SFT_E_INVALID"),       # K > N
+    (dict(n=1 << 14, k=50, m=100), "SFT_E_UNSUPPORTED"),       # M not a power of two
+    (dict(n=1 << 14, k=50, m=1 << 15), "SFT_E_UNSUPPORTED"),   # M does not divide N
+    (dict(n=1 << 14, k=50, l=5), "SFT_E_UNSUPPORTED"),         # L outside 1..4
+    (dict(n=1 << 20, k=50, m=1 << 14), "SFT_E_UNSUPPORTED"),   # M above one block's LDS
+    (dict(n=1 << 14, k=50, r=3), "SFT_E_INVALID"),             # R in exact mode
+    (dict(n=1 << 14, k=50, mode="general", r=40), "SFT_E_UNSUPPORTED"),
+    (dict(n=1 << 14, k=50, flags=64), "SFT_E_INVALID"),        # unknown flag
+    (dict(n=1 << 14, k=50, tau_res=-1.0), "SFT_E_INVALID"),
+])
+def test_parameter_validation(lib, kw, status):
+    st, h = _plan_status(lib, **kw)
+    assert lib.sft_status_str(st).decode() == status
+    assert h.value is None
+    assert lib.sft_last_error()
+
+
+def test_null_arguments(lib):
+    from paper_1407_8315_amd import _lib
+
+    assert lib.sft_plan(None, None, 1, None) == _lib.SFT_E_INVALID
+    h = ctypes.c_void_p()
+    assert lib.sft_plan(ctypes.byref(h), None, 1, None) == _lib.SFT_E_INVALID
+    assert lib.sft_exact(None, None, None, None) == _lib.SFT_E_INVALID
+    assert lib.sft_batch(None, None, None, None) == _lib.SFT_E_INVALID
+    assert lib.sft_plan_get(None, 0, None) == _lib.SFT_E_INVALID
+    lib.sft_destroy(None)

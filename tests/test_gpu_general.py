@@ -1,0 +1,112 @@
+"""GPU parity of the generally K-sparse path and of batches, through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import sftgen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def sft():
+    import paper_1407_8315_amd as m
+
+    return m
+
+
+def to_dev(torch, x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+@pytest.mark.parametrize("snr", [10, 20, 30, 40, None])
+def test_general_n20_metrics_match_oracle(torch, sft, snr):
+    """N = 2^20, K = 1000, M = 4096, L = 4, R = 12, complex64: support recovery
+    and relative L2 error within 1e-3 of the oracle's (averaged over 2 signals),
+    and the same entries for all but a few bins."""
+    n, k, m, L = 1 << 20, 1000, 4096, 4
+    sr_g, sr_o, rl_g, rl_o, same, tot = 0.0, 0.0, 0.0, 0.0, 0, 0
+    for i in range(2):
+        say(f"[general] snr={snr} signal={i}")
+        s = sftgen.make_signal(n, k, 900 + i, amp="gauss", dtype=np.complex64, snr_db=snr)
+        plan = sft.Plan(dict(n=n, k=k, m=m, l=L, mode="general", seed=77 + i))
+        res = plan.general(to_dev(torch, s.x), stats=True)
+        loc, val = res.host()
+        rsh = plan.info()["rshifts"]
+        plan.close()
+        ref = oracle.sfft_general(s.x, n, k, m, L, rsh)
+        sr_g += oracle.support_recovery(s.locs, loc) / 2
+        sr_o += oracle.support_recovery(s.locs, ref.locs) / 2
+        rl_g += oracle.relative_l2(s.locs, s.vals, loc, val) / 2
+        rl_o += oracle.relative_l2(s.locs, s.vals, ref.locs, ref.vals) / 2
+        same += len(np.intersect1d(loc, ref.locs))
+        tot += max(len(loc), len(ref.locs))
+        assert len(loc) == len(ref.locs)
+    say(f"  recovery gpu {sr_g:.5f} oracle {sr_o:.5f}; rel L2 gpu {rl_g:.5f} oracle {rl_o:.5f}; same {same}/{tot}")
+    assert abs(sr_g - sr_o) <= 1e-3
+    assert abs(rl_g - rl_o) <= 1e-3
+    assert same >= tot - 4
+
+
+def test_general_exact_input_is_exact(torch, sft):
+    n, k, m, L = 1 << 16, 200, 1024, 4
+    s = sftgen.make_signal(n, k, 21, amp="gauss", dtype=np.complex128)
+    say("[general exact input]")
+    plan = sft.Plan(dict(n=n, k=k, m=m, l=L, mode="general", dtype="c128", seed=3))
+    loc, val = plan.general(to_dev(torch, s.x)).host()
+    plan.close()
+    assert loc.tolist() == s.locs.tolist()
+    assert np.max(np.abs(val - s.vals)) < 1e-9
+
+
+def test_batch_equals_single_calls_and_replays(torch, sft):
+    """A batch of uneven signals (exact and general) gives each signal's
+    single-call result, and replaying the captured graph repeats it bit for bit."""
+    specs = [
+        (1 << 14, 50, 128, "exact", None), (1 << 16, 300, 1024, "exact", None),
+        (1 << 20, 1000, 4096, "general", 20), (1 << 12, 16, 64, "exact", None),
+        (1 << 18, 600, 4096, "general", 30), (1 << 16, 100, 512, "exact", None),
+        (1 << 14, 40, 256, "general", 40), (1 << 20, 2000, 8192, "exact", None),
+        (1 << 15, 64, 256, "exact", None),
+    ]
+    xs, params = [], []
+    for i, (n, k, m, mode, snr) in enumerate(specs):
+        s = sftgen.make_signal(n, k, 300 + i, amp="gauss", dtype=np.complex64, snr_db=snr)
+        xs.append(to_dev(torch, s.x))
+        params.append(dict(n=n, k=k, m=m, l=4, mode=mode, seed=i))
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        say("[batch] plan")
+        plan = sft.Plan(params, stream=stream)
+        outs1 = plan.batch(xs)
+        torch.cuda.synchronize()
+        r1 = [o.host() for o in outs1]
+        outs2 = plan.batch(xs)
+        torch.cuda.synchronize()
+        r2 = [o.host() for o in outs2]
+        plan.close()
+        for i, (p, x) in enumerate(zip(params, xs)):
+            say(f"[batch] single {i}")
+            single = sft.Plan(p, stream=stream)
+            fn = single.general if p["mode"] == "general" else single.exact
+            loc, val = fn(x).host()
+            single.close()
+            assert r1[i][0].tolist() == loc.tolist()
+            assert np.array_equal(r1[i][1], val)
+            assert r2[i][0].tolist() == loc.tolist()
+            assert np.array_equal(r2[i][1], val)

@@ -183,12 +183,13 @@ __host__ __device__ inline bool poly_roots(const zd* c, int a, zd* z) {
         const double ang = M_PI * (2.0 * j / a + 0.123);
         z[j] = zd{cos(ang), sin(ang)};
     }
-    // Stop when the largest correction is below 1e-13 (relative); near a
+    // Stop when the largest correction is below 1e-10 (relative); near a
     // cluster of roots rounding keeps the corrections around eps / spacing^(a-1),
     // so after the iteration cap a final correction below 1e-7 is accepted
-    // (the grid check that follows needs far less than that).
+    // (the grid check that follows needs far less than that: it compares the
+    // root's angle with the grid spacing, at least 2 pi / 2^22).
     double step = 0.0;
-    for (int it = 0; it < 80; ++it) {
+    for (int it = 0; it < 40; ++it) {
         double scale = 0.0;
         step = 0.0;
         bool bad = false;
@@ -210,7 +211,7 @@ __host__ __device__ inline bool poly_roots(const zd* c, int a, zd* z) {
             scale = fmax(scale, norm2(z[j]));
         }
         if (bad) return false;
-        if (step <= 1e-26 * fmax(scale, 1.0)) return true;
+        if (step <= 1e-20 * fmax(scale, 1.0)) return true;
     }
     return step <= 1e-14;
 }

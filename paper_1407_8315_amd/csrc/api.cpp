@@ -340,7 +340,7 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     TRY(dalloc(p, &p->d_out_items, lay.out_items.size()));
     TRY(dalloc(p, &p->d_gsigs, lay.general_sigs.size()));
     TRY(dalloc(p, &p->d_orders, (size_t)lay.bin_elems));
-    TRY(dalloc(p, &p->d_flag, lay.n_general ? (size_t)lay.bin_elems : 1));
+    TRY(dalloc(p, &p->d_flag, lay.n_general ? (size_t)lay.bin_elems * kMaxL : 1));
 
 #define HIPTRY(call)                                                                                   \
     do {                                                                                               \

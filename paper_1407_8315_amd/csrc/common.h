@@ -54,7 +54,8 @@ struct IoDev {
 };
 
 struct SigCounters {
-    int stage_count, active, flagged, cs, mlp_fb, nonfinite, kept, nflag;   // nflag: CS queue length
+    int stage_count, active, flagged, cs, mlp_fb, nonfinite, kept, pad;
+    int nflag[kMaxL];   // CS queue lengths per vote order a0 = 1..L
 };
 
 struct SelDev {             // per-signal results of the selection pass (general mode)
@@ -140,7 +141,7 @@ struct LaunchCtx {
     const signed char* orders;   // learned order per bin (nullable), indexed by bin_off + k
     int any_general;
     unsigned char* keep;     // per staging entry: kept in the output
-    int* flag_list;          // per signal [M]: bins queued for the CS step (general mode)
+    int* flag_list;          // per signal [kMaxL][M]: bins queued for the CS step, by a0 (general mode)
 };
 
 hipError_t launch_zero_counters(const LaunchCtx& c);

@@ -37,6 +37,27 @@ __device__ inline void load_derotated(const typename V2<T>::type* __restrict__ s
     }
 }
 
+// Raw syndromes m_l[k] of the lines [0, cnt) (no de-rotation), FP64.
+template <typename T, int MAXC>
+__device__ inline void load_raw(const typename V2<T>::type* __restrict__ syn, int log2m, int64_t k, int cnt, zd* out) {
+#pragma unroll
+    for (int l = 0; l < MAXC; ++l) {
+        out[l] = zd{0.0, 0.0};
+        if (l < cnt) {
+            auto v = syn[((int64_t)l << log2m) + k];
+            out[l] = zd{(double)v.x, (double)v.y};
+        }
+    }
+}
+
+// In place: m_l <- e^{-i 2 pi (k sh_l mod N) / N} m_l.
+template <int MAXC>
+__device__ inline void derotate(zd* m, int64_t k, int64_t n, const int64_t* sh, int cnt) {
+#pragma unroll
+    for (int l = 0; l < MAXC; ++l)
+        if (l < cnt) m[l] = cmul_conj(unit_root((k * sh[l]) & (n - 1), n), m[l]);
+}
+
 __device__ inline unsigned long long sv_key(double s) {
     if (!(s >= 0.0) || !isfinite(s)) return 0ull;
     return (unsigned long long)__double_as_longlong(s);
@@ -169,6 +190,17 @@ __device__ inline bool try_order(const zd* mt, int L, int a, double e, double nu
     zd c[kMaxL], z[kMaxL], p[kMaxL];
     int64_t t[kMaxL];
     if (!locator(mt, a, c)) return false;
+    // |c_0| is the product of the root magnitudes: when it lies outside
+    // [(1 - delta_mag)^a, (1 + delta_mag)^a] some root fails the grid check.
+    double lo = 1.0, hi = 1.0;
+#pragma unroll
+    for (int j = 0; j < kMaxL; ++j)
+        if (j < a) {
+            lo *= 1.0 - sg.delta_mag;
+            hi *= 1.0 + sg.delta_mag;
+        }
+    const double c0 = cabs(c[0]);
+    if (!(c0 >= lo && c0 <= hi)) return false;
     if (!poly_roots(c, a, z)) return false;
     if (!roots_to_grid(z, a, sg.d, sg.delta_grid, sg.delta_mag, t)) return false;
     double r2;
@@ -197,162 +229,225 @@ __device__ inline int order_at(int a0, int L, int step) {
     return (step <= L - a0) ? a0 + step : a0 - (step - (L - a0));
 }
 
-// Least squares on the columns `sel` (positions into the candidate list)
-// of Phi_{j,c} = w_d^{(t_c n_j) mod d}: coefficients and residual vector.
-__device__ inline bool cs_ls(const zd* y, int R, const int64_t* nj, const int64_t* cand_t, const int* sel, int ns,
-                             int64_t d, const double2* tab, int stride, zd* coef, zd* res, double& rn2) {
-    zd g[kMaxCand * (kMaxCand + 1) / 2];
-    for (int a = 0; a < ns; ++a) {
-        int64_t ta = cand_t[sel[a]];
-        zd b{0.0, 0.0};
-        for (int j = 0; j < R; ++j) b = b + cmul_conj(omega(tab, stride, (ta * nj[j]) & (d - 1)), y[j]);
-        coef[a] = b;
+// Subspace Pursuit works on sets of at most kMaxCand candidate columns,
+// represented as bit masks so that every register array is indexed by
+// unrolled constants.  Columns: Phi_{j,c} = w_d^{(t_c n_j) mod d}.  Every
+// quantity SP needs follows from the candidates' Gram matrix
+// G_{cc'} = sum_j conj(Phi_jc) Phi_jc', from b = Phi^H y and from ||y||^2:
+// least squares on a set T solves G_T x = b_T, the residual's correlations are
+// b - G x, and its energy is ||y||^2 - Re(b_T^H x).
+
+// Least squares on the columns in `mask` as a fixed kMaxCand system (identity
+// rows outside the mask).  Returns the residual energy in rn2.
+template <int KC>
+__device__ inline bool cs_ls(const zd* g, const zd* b, double yy, unsigned mask, zd* coef, double& rn2) {
+    zd gm[KC * (KC + 1) / 2];
+#pragma unroll
+    for (int a = 0; a < KC; ++a) {
+        const bool ia = (mask >> a) & 1u;
+        coef[a] = ia ? b[a] : zd{0.0, 0.0};
+#pragma unroll
         for (int bb = 0; bb <= a; ++bb) {
-            int64_t tb = cand_t[sel[bb]];
-            zd s{0.0, 0.0};
-            for (int j = 0; j < R; ++j)
-                s = s + omega(tab, stride, (((tb - ta) * nj[j]) % d + d) & (d - 1));
-            g[a * (a + 1) / 2 + bb] = s;   // sum_j conj(Phi_ja) Phi_jb
+            const bool ib = (mask >> bb) & 1u;
+            gm[a * (a + 1) / 2 + bb] = (ia && ib) ? g[a * (a + 1) / 2 + bb] : (a == bb ? zd{1.0, 0.0} : zd{0.0, 0.0});
         }
     }
-    if (!chol_solve<kMaxCand>(g, coef, ns)) return false;
-    rn2 = 0.0;
-    for (int j = 0; j < R; ++j) {
-        zd e = y[j];
-        for (int a = 0; a < ns; ++a) e = e - omega(tab, stride, (cand_t[sel[a]] * nj[j]) & (d - 1)) * coef[a];
-        res[j] = e;
-        rn2 += norm2(e);
-    }
-    return isfinite(rn2);
+    if (!chol_solve<KC>(gm, coef, KC)) return false;
+    double bx = 0.0;
+#pragma unroll
+    for (int a = 0; a < KC; ++a)
+        if ((mask >> a) & 1u) bx += b[a].x * coef[a].x + b[a].y * coef[a].y;   // Re(conj(b) x)
+    rn2 = fmax(yy - bx, 0.0);
+    return __builtin_isfinite(rn2);
 }
 
-// Positions of the cnt largest values (ties to the lower position), sorted.
-__device__ inline void top_positions(const double* v, int n, int cnt, int* out) {
-    int m = 0;
-    for (int i = 0; i < n; ++i) {
-        // insertion into out[0..m) ordered by value desc, position asc
-        if (m < cnt || v[i] > v[out[m - 1]]) {
-            int pos = (m < cnt) ? m++ : cnt - 1;
-            while (pos > 0 && v[i] > v[out[pos - 1]]) {
-                out[pos] = out[pos - 1];
-                --pos;
+// |(b - G x)_c|^2 for every candidate c: correlations of the residual.
+template <int KC>
+__device__ inline void cs_residual_corr(const zd* g, const zd* b, const zd* coef, int keep, double* corr) {
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+        zd r = b[c];
+#pragma unroll
+        for (int e = 0; e < KC; ++e) {
+            // G is Hermitian: G_ce = g[c][e] for e <= c, conj(g[e][c]) otherwise
+            zd gce = (e <= c) ? g[c * (c + 1) / 2 + e] : conj(g[e * (e + 1) / 2 + c]);
+            r = r - gce * coef[e];
+        }
+        corr[c] = (c < keep) ? norm2(r) : 0.0;
+    }
+}
+
+// Mask of the cnt largest v[i] among i in `allowed` (ties to the lower position).
+template <int KC>
+__device__ inline unsigned top_mask(const double* v, unsigned allowed, int cnt) {
+    unsigned out = 0u;
+    for (int r = 0; r < cnt; ++r) {
+        int best = -1;
+        double bv = 0.0;
+#pragma unroll
+        for (int i = 0; i < KC; ++i) {
+            const bool ok = ((allowed >> i) & 1u) && !((out >> i) & 1u);
+            if (ok && (best < 0 || v[i] > bv)) {
+                best = i;
+                bv = v[i];
             }
-            out[pos] = i;
+        }
+        if (best < 0) break;
+        out |= 1u << best;
+    }
+    return out;
+}
+
+// Subspace Pursuit over the first `keep` (<= KC) candidates with sparsity s;
+// writes the final support mask and its coefficients.
+template <int KC>
+__device__ inline bool sp_run(const int64_t* cand, int keep, unsigned all, int s, const zd* y, int R,
+                              const int64_t* nj, int64_t d, const double2* tab, int stride, unsigned& T_out,
+                              zd* coef_out) {
+    // b = Phi^H y, G = Phi^H Phi, ||y||^2
+    zd b[KC], g[KC * (KC + 1) / 2];
+    double yy = 0.0;
+    #pragma unroll
+    for (int j = 0; j < kMaxR; ++j) yy += (j < R) ? norm2(y[j]) : 0.0;
+#pragma unroll
+    for (int i = 0; i < KC; ++i) {
+        zd acc{0.0, 0.0};
+        if (i < keep)
+#pragma unroll
+            for (int j = 0; j < kMaxR; ++j)
+                if (j < R) acc = acc + cmul_conj(omega(tab, stride, (cand[i] * nj[j]) & (d - 1)), y[j]);
+        b[i] = acc;
+#pragma unroll
+        for (int e = 0; e <= i; ++e) {
+            zd sum{0.0, 0.0};
+            if (i < keep)
+                for (int j = 0; j < R; ++j) sum = sum + omega(tab, stride, (((cand[e] - cand[i]) * nj[j]) % d + d) & (d - 1));
+            g[i * (i + 1) / 2 + e] = sum;
         }
     }
-    for (int i = 1; i < m; ++i) {   // sort positions ascending
-        int x = out[i], j = i;
-        while (j > 0 && out[j - 1] > x) {
-            out[j] = out[j - 1];
-            --j;
-        }
-        out[j] = x;
+    double corr[KC];
+#pragma unroll
+    for (int i = 0; i < KC; ++i) corr[i] = norm2(b[i]);
+    unsigned T = top_mask<KC>(corr, all, s);
+    zd coef[KC];
+    double rn2;
+    if (!cs_ls<KC>(g, b, yy, T, coef, rn2)) return false;
+    for (int it = 0; it < 2 * s + 2; ++it) {
+        cs_residual_corr<KC>(g, b, coef, keep, corr);
+        const unsigned U = T | top_mask<KC>(corr, all, s);
+        zd cu[KC];
+        double dummy;
+        if (!cs_ls<KC>(g, b, yy, U, cu, dummy)) break;
+        double mag[KC];
+#pragma unroll
+        for (int i = 0; i < KC; ++i) mag[i] = norm2(cu[i]);
+        const unsigned Tn = top_mask<KC>(mag, U, s);
+        zd cn[KC];
+        double rn2n;
+        if (!cs_ls<KC>(g, b, yy, Tn, cn, rn2n)) break;
+        if (rn2n >= rn2) break;
+        T = Tn;
+        rn2 = rn2n;
+#pragma unroll
+        for (int i = 0; i < KC; ++i) coef[i] = cn[i];
     }
+    T_out = T;
+#pragma unroll
+    for (int i = 0; i < KC; ++i) coef_out[i] = coef[i];
+    return true;
 }
 
 // CS recovery of a flagged bin with order a0 (general mode).  Pruning Step 2:
 // the min(2 a0, R, d) roots of unity with the smallest |P~(z)| (P~ from the
 // order-a0 locator; a singular system leaves the bin flagged); Step 3:
 // Phi_p; then Subspace Pursuit with sparsity a0 on the R random-shift
-// syndromes y_j (de-rotated by e^{-i 2 pi k n_j / N}).
-__device__ inline bool cs_recover(const zd* mt, const zd* y, int R, const int64_t* nj, int a0, const SigDev& sg,
+// syndromes y_j (de-rotated by e^{-i 2 pi k n_j / N}): start from the a0
+// columns most correlated with y, then repeatedly merge the a0 columns most
+// correlated with the residual, solve least squares on the merged set, keep
+// its a0 largest coefficients, re-solve, and stop once the residual stops
+// decreasing.
+template <int A0>
+__device__ inline bool cs_recover(const zd* mt, const zd* y, int R, const int64_t* nj, const SigDev& sg,
                                   const double2* tab, BinOut& o) {
+    const int a0 = A0;
+    constexpr int KC = 2 * A0;   // candidate bound min(2 a0, R, d) <= 2 A0
     const int64_t d = sg.d;
-    int64_t cand[kMaxCand];
-    int nc;
     zd c[kMaxL];
-    if (locator(mt, a0, c)) {
-        int keep = 2 * a0;
-        if (keep > R) keep = R;
-        if ((int64_t)keep > d) keep = (int)d;
-        double best[kMaxCand];
-        int64_t bt[kMaxCand];
-        int m = 0;
-        for (int64_t t = 0; t < d; ++t) {
-            zd p, dp;
-            poly_eval(c, a0, omega(tab, sg.tab_stride, t), p, dp);
-            double e = norm2(p);
-            if (m < keep || e < best[m - 1]) {
-                int pos = (m < keep) ? m++ : keep - 1;
-                while (pos > 0 && e < best[pos - 1]) {
-                    best[pos] = best[pos - 1];
-                    bt[pos] = bt[pos - 1];
-                    --pos;
-                }
-                best[pos] = e;
-                bt[pos] = t;
+    if (!locator(mt, a0, c)) return false;   // nothing to prune with: the bin stays flagged
+    int keep = 2 * a0;
+    if (keep > R) keep = R;
+    if ((int64_t)keep > d) keep = (int)d;
+    // the `keep` smallest |P~(w_d^t)|, ties to the lower t (kept sorted by error)
+    double best[KC];
+    int64_t bt[KC];
+#pragma unroll
+    for (int i = 0; i < KC; ++i) {
+        best[i] = __builtin_inf();
+        bt[i] = INT64_MAX;
+    }
+    for (int64_t t = 0; t < d; ++t) {
+        zd p, dp;
+        poly_eval(c, a0, omega(tab, sg.tab_stride, t), p, dp);
+        double e = norm2(p);
+        if (!(e < best[keep - 1])) continue;
+        // insertion into the sorted prefix of length keep (fixed-index shifts)
+        double ce = e;
+        int64_t ct = t;
+#pragma unroll
+        for (int i = 0; i < KC; ++i) {
+            if (i < keep && ce < best[i]) {
+                double te = best[i];
+                int64_t tt = bt[i];
+                best[i] = ce;
+                bt[i] = ct;
+                ce = te;
+                ct = tt;
             }
         }
-        nc = m;
-        for (int i = 1; i < nc; ++i) {   // ascending t
-            int64_t x = bt[i];
-            int j = i;
-            while (j > 0 && bt[j - 1] > x) {
-                bt[j] = bt[j - 1];
-                --j;
+    }
+    // candidates in ascending t (positions 0..keep-1), unused slots last
+    int64_t cand[KC];
+#pragma unroll
+    for (int i = 0; i < KC; ++i) cand[i] = bt[i];
+#pragma unroll
+    for (int i = 0; i < KC; ++i)
+#pragma unroll
+        for (int j = 0; j < KC - 1; ++j)
+            if (cand[j] > cand[j + 1]) {
+                int64_t x = cand[j];
+                cand[j] = cand[j + 1];
+                cand[j + 1] = x;
             }
-            bt[j] = x;
-        }
-        for (int i = 0; i < nc; ++i) cand[i] = bt[i];
-    } else {
-        return false;   // singular order-a0 locator: nothing to prune with, the bin stays flagged
-    }
-    const int s = a0 < nc ? a0 : nc;
-    double corr[kMaxCand];
-    int T[kMaxL], E[kMaxL], U[2 * kMaxL], Tn[kMaxL];
-    zd coef[kMaxCand], res[kMaxR], cu[kMaxCand], resn[kMaxR];
-    for (int i = 0; i < nc; ++i) {
-        zd b{0.0, 0.0};
-        for (int j = 0; j < R; ++j) b = b + cmul_conj(omega(tab, sg.tab_stride, (cand[i] * nj[j]) & (d - 1)), y[j]);
-        corr[i] = norm2(b);
-    }
-    top_positions(corr, nc, s, T);
-    double rn2;
-    if (!cs_ls(y, R, nj, cand, T, s, d, tab, sg.tab_stride, coef, res, rn2)) return false;
-    for (int it = 0; it < 2 * s + 2; ++it) {
-        for (int i = 0; i < nc; ++i) {
-            zd b{0.0, 0.0};
-            for (int j = 0; j < R; ++j)
-                b = b + cmul_conj(omega(tab, sg.tab_stride, (cand[i] * nj[j]) & (d - 1)), res[j]);
-            corr[i] = norm2(b);
-        }
-        top_positions(corr, nc, s, E);
-        int nu_ = 0, ia = 0, ib = 0;   // merge sorted T and E
-        while (ia < s || ib < s) {
-            int v;
-            if (ib >= s || (ia < s && T[ia] <= E[ib])) {
-                v = T[ia++];
-                if (ib < s && E[ib] == v) ++ib;
-            } else {
-                v = E[ib++];
-            }
-            U[nu_++] = v;
-        }
-        double dummy;
-        zd rtmp[kMaxR];
-        if (!cs_ls(y, R, nj, cand, U, nu_, d, tab, sg.tab_stride, cu, rtmp, dummy)) break;
-        double mag[2 * kMaxL];
-        for (int i = 0; i < nu_; ++i) mag[i] = norm2(cu[i]);
-        int pos[kMaxL];
-        top_positions(mag, nu_, s, pos);
-        for (int i = 0; i < s; ++i) Tn[i] = U[pos[i]];
-        zd cn[kMaxCand];
-        double rn2n;
-        if (!cs_ls(y, R, nj, cand, Tn, s, d, tab, sg.tab_stride, cn, resn, rn2n)) break;
-        if (rn2n >= rn2) break;
-        for (int i = 0; i < s; ++i) {
-            T[i] = Tn[i];
-            coef[i] = cn[i];
-        }
-        for (int j = 0; j < R; ++j) res[j] = resn[j];
-        rn2 = rn2n;
-    }
-    o.n = s;
+    const unsigned all = (1u << keep) - 1u;
+    const int s = a0 < keep ? a0 : keep;
+    unsigned T = 0u;
+    zd coef[KC];
+    bool ok;
+    ok = sp_run<KC>(cand, keep, all, s, y, R, nj, d, tab, sg.tab_stride, T, coef);
+    if (!ok) return false;
+    // emit the members of T in ascending t
+    o.n = 0;
+    int q = 0;
+#pragma unroll
     for (int i = 0; i < kMaxL; ++i) {
-        o.keep[i] = i < s;
-        o.t[i] = i < s ? cand[T[i]] : 0;
-        o.p[i] = i < s ? coef[i] : zd{0.0, 0.0};
+        o.keep[i] = false;
+        o.t[i] = 0;
+        o.p[i] = zd{0.0, 0.0};
     }
+#pragma unroll
+    for (int i = 0; i < KC; ++i) {
+        if ((T >> i) & 1u) {
+#pragma unroll
+            for (int j = 0; j < kMaxL; ++j)
+                if (j == q) {
+                    o.keep[j] = true;
+                    o.t[j] = cand[i];
+                    o.p[j] = coef[i];
+                }
+            ++q;
+        }
+    }
+    o.n = q;
     return true;
 }
 
@@ -372,7 +467,9 @@ __device__ inline void emit(const SigDev& sg, SigCounters* cnt, int64_t k, const
     }
 }
 
-template <typename T>
+// MODES: bit 0 = the plan has exact-mode signals, bit 1 = general-mode ones;
+// each instantiation carries only the code its modes need.
+template <typename T, int MODES>
 __global__ __launch_bounds__(kBlock) void decode_kernel(const SigDev* __restrict__ sigs, const int2* __restrict__ items,
                                                         const int64_t* __restrict__ shifts,
                                                         const typename V2<T>::type* __restrict__ synd,
@@ -391,15 +488,16 @@ __global__ __launch_bounds__(kBlock) void decode_kernel(const SigDev* __restrict
     const int L = sg.L;
     zd mt[2 * kMaxL];
     const int64_t* sh = shifts + sg.shift_off;
-    load_derotated<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, sg.n, sh, 2 * L, mt);
-    double e = 0.0;
+    load_raw<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, 2 * L, mt);
+    double e = 0.0;   // E_k (de-rotation keeps magnitudes)
 #pragma unroll
     for (int l = 0; l < 2 * kMaxL; ++l) e += norm2(mt[l]);   // zero beyond 2L
 
     int a0 = 0;       // 0: rank test not yet computed
     double nu = 0.0;
     int a_pred = 0;
-    if (sg.mode == kExact) {
+    const bool exact = (MODES == 1) || (MODES == 3 && sg.mode == kExact);
+    if (exact) {
         double eref = 0.0;
         for (int l = 0; l < 2 * L; ++l) eref += epart[sg.epart_off + l];
         eref /= (double)sg.m;
@@ -418,6 +516,7 @@ __global__ __launch_bounds__(kBlock) void decode_kernel(const SigDev* __restrict
         nu = sd.nu;
     }
     atomicAdd(&cnt[s].active, 1);
+    derotate<2 * kMaxL>(mt, k, sg.n, sh, 2 * L);
 
     // Hypotheses: the learned order first (when given), then the canonical
     // order from a0 (rank test in exact mode, votes in general mode).
@@ -430,7 +529,7 @@ __global__ __launch_bounds__(kBlock) void decode_kernel(const SigDev* __restrict
         if (step < 0) {
             a = a_pred;
         } else {
-            if (a0 == 0) {
+            if ((MODES & 1) && a0 == 0) {
                 double sv[kMaxL];
                 hankel_singular_values(mt, L, sv);
                 a0 = rank_order(sv, L, sg.tau_rank);
@@ -443,21 +542,22 @@ __global__ __launch_bounds__(kBlock) void decode_kernel(const SigDev* __restrict
     }
     if (!done) {
         atomicAdd(&cnt[s].flagged, 1);
-        if (sg.mode == kGeneral) {
-            int q = atomicAdd(&cnt[s].nflag, 1);   // q < M: each bin is queued at most once
-            flag_list[sg.bin_off + q] = (int)k;
+        if (!exact) {
+            // queue by a0 (1..L); q < M: each bin is queued at most once
+            int q = atomicAdd(&cnt[s].nflag[a0 - 1], 1);
+            flag_list[(int64_t)(a0 - 1) * sg.m + sg.bin_off * kMaxL + q] = (int)k;
         }
         return;
     }
     emit(sg, &cnt[s], k, o, st_loc, st_val);
 }
 
-// CS step for the bins the decoder queued (general mode), one lane per bin.
-template <typename T>
+// CS step for the bins the decoder queued (general mode), one lane per bin;
+// one instantiation per vote order A0, so every wave runs one code path.
+template <typename T, int A0>
 __global__ __launch_bounds__(kBlock) void cs_kernel(const SigDev* __restrict__ sigs, const int2* __restrict__ items,
                                                     const int64_t* __restrict__ shifts,
                                                     const typename V2<T>::type* __restrict__ synd,
-                                                    const double* __restrict__ sigma, const SelDev* __restrict__ sel,
                                                     const double2* __restrict__ tab, SigCounters* __restrict__ cnt,
                                                     int64_t* __restrict__ st_loc, double2* __restrict__ st_val,
                                                     const int* __restrict__ flag_list) {
@@ -465,29 +565,20 @@ __global__ __launch_bounds__(kBlock) void cs_kernel(const SigDev* __restrict__ s
     if (it.x < 0) return;   // padding item
     const int s = it.x;
     const SigDev& sg = sigs[s];
-    if (sg.mode != kGeneral) return;
+    if (sg.mode != kGeneral || A0 > sg.L) return;
     const int q = it.y + threadIdx.x;
-    if (q >= cnt[s].nflag) return;
-    const int64_t k = flag_list[sg.bin_off + q];
+    if (q >= cnt[s].nflag[A0 - 1]) return;
+    const int64_t k = flag_list[(int64_t)(A0 - 1) * sg.m + sg.bin_off * kMaxL + q];
     const int L = sg.L;
     const int64_t* sh = shifts + sg.shift_off;
     zd mt[2 * kMaxL];
     load_derotated<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, sg.n, sh, 2 * L, mt);
-    const SelDev sd = sel[s];
-    int a0 = 0;
-#pragma unroll
-    for (int i = 0; i < kMaxL; ++i) {
-        if (i >= L) continue;
-        int64_t flat = k * L + i;
-        unsigned long long kv = sv_key(sigma[(sg.bin_off + k) * L + i]);
-        a0 += (kv > sd.thr_key || (kv == sd.thr_key && flat <= sd.thr_idx)) ? 1 : 0;
-    }
     zd y[kMaxR];
     const int R = sg.R;
     load_derotated<T, kMaxR>(synd + sg.synd_off + ((int64_t)(2 * L) << sg.log2m), sg.log2m, k, sg.n, sh + 2 * L, R, y);
     BinOut o;
     o.n = 0;
-    if (!cs_recover(mt, y, R, sh + 2 * L, a0, sg, tab, o)) return;
+    if (!cs_recover<A0>(mt, y, R, sh + 2 * L, sg, tab, o)) return;
     atomicAdd(&cnt[s].cs, 1);
     emit(sg, &cnt[s], k, o, st_loc, st_val);
 }
@@ -610,29 +701,46 @@ hipError_t launch_output(const LaunchCtx& c) {
     return hipGetLastError();
 }
 
+template <typename T, int MODES>
+static void launch_decode_t(const LaunchCtx& c) {
+    using V = typename V2<T>::type;
+    hipLaunchKernelGGL((decode_kernel<T, MODES>), dim3(c.n_bin_items), dim3(kBlock), 0, c.stream, c.sigs, c.bin_items,
+                       c.shifts, (const V*)c.synd, c.epart, c.sigma, c.sel, c.omega, c.orders, c.cnt, c.st_loc,
+                       c.st_val, c.flag_list);
+}
+
 hipError_t launch_decode(const LaunchCtx& c) {
     if (c.n_bin_items == 0) return hipSuccess;
-    if (c.fp64)
-        hipLaunchKernelGGL(decode_kernel<double>, dim3(c.n_bin_items), dim3(kBlock), 0, c.stream, c.sigs, c.bin_items,
-                           c.shifts, (const double2*)c.synd, c.epart, c.sigma, c.sel, c.omega, c.orders, c.cnt,
-                           c.st_loc, c.st_val, c.flag_list);
-    else
-        hipLaunchKernelGGL(decode_kernel<float>, dim3(c.n_bin_items), dim3(kBlock), 0, c.stream, c.sigs, c.bin_items,
-                           c.shifts, (const float2*)c.synd, c.epart, c.sigma, c.sel, c.omega, c.orders, c.cnt,
-                           c.st_loc, c.st_val, c.flag_list);
+    const int modes = (c.n_general < c.n_sigs ? 1 : 0) | (c.n_general > 0 ? 2 : 0);
+    if (c.fp64) {
+        if (modes == 1) launch_decode_t<double, 1>(c);
+        else if (modes == 2) launch_decode_t<double, 2>(c);
+        else launch_decode_t<double, 3>(c);
+    } else {
+        if (modes == 1) launch_decode_t<float, 1>(c);
+        else if (modes == 2) launch_decode_t<float, 2>(c);
+        else launch_decode_t<float, 3>(c);
+    }
     return hipGetLastError();
+}
+
+template <typename T>
+static void launch_cs_t(const LaunchCtx& c) {
+    using V = typename V2<T>::type;
+    hipLaunchKernelGGL((cs_kernel<T, 1>), dim3(c.n_bin_items), dim3(kBlock), 0, c.stream, c.sigs, c.bin_items, c.shifts,
+                       (const V*)c.synd, c.omega, c.cnt, c.st_loc, c.st_val, c.flag_list);
+    hipLaunchKernelGGL((cs_kernel<T, 2>), dim3(c.n_bin_items), dim3(kBlock), 0, c.stream, c.sigs, c.bin_items, c.shifts,
+                       (const V*)c.synd, c.omega, c.cnt, c.st_loc, c.st_val, c.flag_list);
+    hipLaunchKernelGGL((cs_kernel<T, 3>), dim3(c.n_bin_items), dim3(kBlock), 0, c.stream, c.sigs, c.bin_items, c.shifts,
+                       (const V*)c.synd, c.omega, c.cnt, c.st_loc, c.st_val, c.flag_list);
+    hipLaunchKernelGGL((cs_kernel<T, 4>), dim3(c.n_bin_items), dim3(kBlock), 0, c.stream, c.sigs, c.bin_items, c.shifts,
+                       (const V*)c.synd, c.omega, c.cnt, c.st_loc, c.st_val, c.flag_list);
 }
 
 hipError_t launch_cs(const LaunchCtx& c) {
     if (!c.any_general || c.n_bin_items == 0) return hipSuccess;
-    if (c.fp64)
-        hipLaunchKernelGGL(cs_kernel<double>, dim3(c.n_bin_items), dim3(kBlock), 0, c.stream, c.sigs, c.bin_items,
-                           c.shifts, (const double2*)c.synd, c.sigma, c.sel, c.omega, c.cnt, c.st_loc, c.st_val,
-                           c.flag_list);
-    else
-        hipLaunchKernelGGL(cs_kernel<float>, dim3(c.n_bin_items), dim3(kBlock), 0, c.stream, c.sigs, c.bin_items,
-                           c.shifts, (const float2*)c.synd, c.sigma, c.sel, c.omega, c.cnt, c.st_loc, c.st_val,
-                           c.flag_list);
+    if (c.fp64) launch_cs_t<double>(c);
+    else launch_cs_t<float>(c);
     return hipGetLastError();
 }
 

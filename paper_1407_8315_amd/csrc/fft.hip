@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void syndrome_kernel(const SigDev* __restri
 
 __global__ void zero_counters_kernel(SigCounters* cnt, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) cnt[i] = SigCounters{0, 0, 0, 0, 0, 0, 0, 0};
+    if (i < n) cnt[i] = SigCounters{0, 0, 0, 0, 0, 0, 0, 0, {0, 0, 0, 0}};
 }
 
 hipError_t launch_zero_counters(const LaunchCtx& c) {

@@ -58,10 +58,15 @@ struct sft_plan_s {
     int4* d_synd_items = nullptr;
     int2* d_bin_items = nullptr;
     int2* d_out_items = nullptr;
+    int2* d_act_items = nullptr;
     int* d_gsigs = nullptr;
     signed char* d_orders = nullptr;
-    int* d_flag = nullptr;
-    int n_synd_items = 0, n_bin_items = 0, n_out_items = 0, n_general = 0;
+    WorkCounters* d_work = nullptr;
+    int2* d_active = nullptr;
+    int2* d_cslist = nullptr;
+    int64_t list_cap = 0;
+    int n_work_blocks = 0;
+    int n_synd_items = 0, n_bin_items = 0, n_out_items = 0, n_act_items = 0, n_general = 0;
     int tw_log2 = 0, om_log2 = 0;
     int64_t ws_bytes = 0;
     // host staging
@@ -131,12 +136,18 @@ LaunchCtx make_ctx(const sft_plan_s* p) {
     c.n_bin_items = p->n_bin_items;
     c.out_items = p->d_out_items;
     c.n_out_items = p->n_out_items;
+    c.act_items = p->d_act_items;
+    c.n_act_items = p->n_act_items;
     c.n_general = p->n_general;
     c.general_sigs = p->d_gsigs;
     c.orders = nullptr;
     c.any_general = p->any_general ? 1 : 0;
     c.keep = p->d_keep;
-    c.flag_list = p->d_flag;
+    c.work = p->d_work;
+    c.active_list = p->d_active;
+    c.cs_list = p->d_cslist;
+    c.list_cap = p->list_cap;
+    c.n_work_blocks = p->n_work_blocks;
     return c;
 }
 
@@ -150,6 +161,7 @@ sft_status enqueue(const sft_plan_s* p, const signed char* orders, hipEvent_t* e
     if (events) HIPCHK(hipEventRecord(events[1], p->stream));
     HIPCHK(launch_singular_values(c));
     HIPCHK(launch_select(c));
+    HIPCHK(launch_activity(c));
     if (events) HIPCHK(hipEventRecord(events[2], p->stream));
     HIPCHK(launch_decode(c));
     HIPCHK(launch_cs(c));
@@ -297,6 +309,7 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     p->n_synd_items = (int)lay.synd_items.size();
     p->n_bin_items = (int)lay.bin_items.size();
     p->n_out_items = (int)lay.out_items.size();
+    p->n_act_items = (int)lay.act_items.size();
 
     const size_t ns = p->sig.size();
     sft_status s = SFT_OK;
@@ -338,9 +351,19 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     TRY(dalloc(p, &p->d_synd_items, lay.synd_items.size()));
     TRY(dalloc(p, &p->d_bin_items, lay.bin_items.size()));
     TRY(dalloc(p, &p->d_out_items, lay.out_items.size()));
+    TRY(dalloc(p, &p->d_act_items, lay.act_items.size()));
     TRY(dalloc(p, &p->d_gsigs, lay.general_sigs.size()));
     TRY(dalloc(p, &p->d_orders, (size_t)lay.bin_elems));
-    TRY(dalloc(p, &p->d_flag, lay.n_general ? (size_t)lay.bin_elems * kMaxL : 1));
+    TRY(dalloc(p, &p->d_work, 1));
+    TRY(dalloc(p, &p->d_active, (size_t)lay.bin_elems));
+    TRY(dalloc(p, &p->d_cslist, lay.n_general ? (size_t)lay.bin_elems * kMaxL : 1));
+    p->list_cap = lay.bin_elems;
+    {
+        // grid of the list-driven kernels: enough blocks to fill every CU a few
+        // times over, never more than the bins themselves need
+        int64_t need = (lay.bin_elems + kBlock - 1) / kBlock;
+        p->n_work_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(need, 4096));
+    }
 
 #define HIPTRY(call)                                                                                   \
     do {                                                                                               \
@@ -369,6 +392,7 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     HIPTRY(hipMemcpy(p->d_synd_items, lay.synd_items.data(), lay.synd_items.size() * sizeof(int4), hipMemcpyHostToDevice));
     HIPTRY(hipMemcpy(p->d_bin_items, lay.bin_items.data(), lay.bin_items.size() * sizeof(int2), hipMemcpyHostToDevice));
     HIPTRY(hipMemcpy(p->d_out_items, lay.out_items.data(), lay.out_items.size() * sizeof(int2), hipMemcpyHostToDevice));
+    HIPTRY(hipMemcpy(p->d_act_items, lay.act_items.data(), lay.act_items.size() * sizeof(int2), hipMemcpyHostToDevice));
     if (!lay.general_sigs.empty())
         HIPTRY(hipMemcpy(p->d_gsigs, lay.general_sigs.data(), lay.general_sigs.size() * sizeof(int), hipMemcpyHostToDevice));
     HIPTRY(hipMemset(p->d_orders, 0, (size_t)lay.bin_elems));

@@ -23,6 +23,7 @@ constexpr int kMaxLines = 2 * kMaxL + 64;   // 2L consecutive + up to 64 random 
 constexpr int kBlock = 256;                 // threads per block of every kernel but select
 constexpr int kFftPointsF32 = 8192;         // points per block in LDS (64 KiB)
 constexpr int kFftPointsF64 = 4096;
+constexpr int kActivityTile = 4096;         // bins per block of the activity pass
 
 enum Mode { kExact = 0, kGeneral = 1 };
 
@@ -55,7 +56,15 @@ struct IoDev {
 
 struct SigCounters {
     int stage_count, active, flagged, cs, mlp_fb, nonfinite, kept, pad;
-    int nflag[kMaxL];   // CS queue lengths per vote order a0 = 1..L
+};
+
+// Plan-wide work lists, rebuilt by every call: the active bins (decoder input)
+// and, per vote order a0 = 1..kMaxL, the flagged bins of the CS step.
+// Entries are (signal, k << 3 | a0).
+struct WorkCounters {
+    int n_active;
+    int n_cs[kMaxL];
+    int pad[3];
 };
 
 struct SelDev {             // per-signal results of the selection pass (general mode)
@@ -136,18 +145,25 @@ struct LaunchCtx {
     int n_bin_items;
     const int2* out_items;   // (sig, entry0): tiles of kBlock staging entries
     int n_out_items;
+    const int2* act_items;   // (sig, bin0): tiles of kActivityTile bins
+    int n_act_items;
     int n_general;           // signals in general mode
     const int* general_sigs; // their indices
     const signed char* orders;   // learned order per bin (nullable), indexed by bin_off + k
     int any_general;
     unsigned char* keep;     // per staging entry: kept in the output
-    int* flag_list;          // per signal [kMaxL][M]: bins queued for the CS step, by a0 (general mode)
+    WorkCounters* work;      // list lengths
+    int2* active_list;       // [list_cap]
+    int2* cs_list;           // [kMaxL][list_cap]
+    int64_t list_cap;        // total bins of the plan
+    int n_work_blocks;       // grid of the list-driven kernels
 };
 
 hipError_t launch_zero_counters(const LaunchCtx& c);
 hipError_t launch_syndromes(const LaunchCtx& c);
 hipError_t launch_singular_values(const LaunchCtx& c);
 hipError_t launch_select(const LaunchCtx& c);
+hipError_t launch_activity(const LaunchCtx& c);
 hipError_t launch_decode(const LaunchCtx& c);
 hipError_t launch_cs(const LaunchCtx& c);
 hipError_t launch_output(const LaunchCtx& c);

@@ -58,6 +58,59 @@ __device__ inline void derotate(zd* m, int64_t k, int64_t n, const int64_t* sh, 
         if (l < cnt) m[l] = cmul_conj(unit_root((k * sh[l]) & (n - 1), n), m[l]);
 }
 
+// Append to a list shared by many lanes with one atomic per wavefront: every
+// lane of the wave that is still running must call this (pred may be false);
+// returns the slot of a lane with pred set.
+__device__ inline int wave_append(int* counter, bool pred) {
+    const unsigned long long mask = __ballot(pred);
+    if (mask == 0ull) return -1;
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, __popcll(mask));
+    base = __shfl(base, leader);
+    return base + __popcll(mask & ((1ull << lane) - 1ull));
+}
+
+// Add n (>= 0) to *addr for every running lane of the wave and return each
+// lane's previous value plus the sum over lower lanes with the same address:
+// one atomic per wave when all lanes share the address (the common case: a
+// wave's bins belong to one signal), one per lane otherwise.
+__device__ inline int wave_add(int* addr, int n) {
+    const unsigned long long run = __ballot(true);
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)run) - 1;
+    const unsigned long long a_lead = __shfl((unsigned long long)addr, leader);
+    if (__ballot((unsigned long long)addr != a_lead) != 0ull) return atomicAdd(addr, n);
+    // inclusive prefix sum of n over the running lanes
+    int incl = n;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int v = __shfl_up(incl, off);
+        if (lane >= off && ((run >> (lane - off)) & 1ull)) incl += v;
+    }
+    const int last = 63 - __clzll((long long)run);
+    const int total = __shfl(incl, last);
+    int base = 0;
+    if (lane == leader && total > 0) base = atomicAdd(addr, total);
+    base = __shfl(base, leader);
+    return base + incl - n;
+}
+
+// Count pred over the wave into *addr: one atomic per wave when every running
+// lane has the same address, one per lane otherwise.
+__device__ inline void wave_count(int* addr, bool pred) {
+    const unsigned long long run = __ballot(true);
+    const unsigned long long m = __ballot(pred);
+    const int leader = __ffsll((long long)run) - 1;
+    const unsigned long long a_lead = __shfl((unsigned long long)addr, leader);
+    if (__ballot((unsigned long long)addr != a_lead) != 0ull) {
+        if (pred) atomicAdd(addr, 1);
+        return;
+    }
+    if (__lane_id() == leader && m != 0ull) atomicAdd(addr, __popcll(m));
+}
+
 __device__ inline unsigned long long sv_key(double s) {
     if (!(s >= 0.0) || !isfinite(s)) return 0ull;
     return (unsigned long long)__double_as_longlong(s);
@@ -451,13 +504,14 @@ __device__ inline bool cs_recover(const zd* mt, const zd* y, int R, const int64_
     return true;
 }
 
+// Append the kept entries of a bin to its signal's staging list.  Every
+// running lane of the wave calls this (with o.n = 0 when it has nothing).
 __device__ inline void emit(const SigDev& sg, SigCounters* cnt, int64_t k, const BinOut& o, int64_t* st_loc,
                             double2* st_val) {
-    if (o.n == 0) return;
-    int pos = atomicAdd(&cnt->stage_count, o.n);
+    int pos = wave_add(&cnt->stage_count, o.n);
 #pragma unroll
     for (int j = 0; j < kMaxL; ++j) {
-        if (o.keep[j]) {
+        if (o.n > 0 && o.keep[j]) {
             if (pos < sg.stage_cap) {
                 st_loc[sg.stage_off + pos] = k + o.t[j] * (int64_t)sg.m;
                 st_val[sg.stage_off + pos] = double2{o.p[j].x, o.p[j].y};
@@ -467,120 +521,189 @@ __device__ inline void emit(const SigDev& sg, SigCounters* cnt, int64_t k, const
     }
 }
 
-// MODES: bit 0 = the plan has exact-mode signals, bit 1 = general-mode ones;
-// each instantiation carries only the code its modes need.
-template <typename T, int MODES>
-__global__ __launch_bounds__(kBlock) void decode_kernel(const SigDev* __restrict__ sigs, const int2* __restrict__ items,
-                                                        const int64_t* __restrict__ shifts,
-                                                        const typename V2<T>::type* __restrict__ synd,
-                                                        const double* __restrict__ epart,
-                                                        const double* __restrict__ sigma, const SelDev* __restrict__ sel,
-                                                        const double2* __restrict__ tab,
-                                                        const signed char* __restrict__ orders,
-                                                        SigCounters* __restrict__ cnt, int64_t* __restrict__ st_loc,
-                                                        double2* __restrict__ st_val, int* __restrict__ flag_list) {
+// Activity pass: exact mode tests E_k > tau_zero^2 mean E, general mode counts
+// the bin's votes.  One block per tile of up to kActivityTile bins of a signal
+// stages its active bins in LDS and reserves room in the plan-wide work list
+// with a single atomic (the order of the list does not matter: the output is
+// sorted at the end).
+
+__global__ __launch_bounds__(kBlock) void activity_kernel(const SigDev* __restrict__ sigs,
+                                                          const int2* __restrict__ items,
+                                                          const float2* __restrict__ synd32,
+                                                          const double2* __restrict__ synd64,
+                                                          const double* __restrict__ epart,
+                                                          const double* __restrict__ sigma,
+                                                          const SelDev* __restrict__ sel,
+                                                          WorkCounters* __restrict__ work, int2* __restrict__ list,
+                                                          SigCounters* __restrict__ cnt) {
+    __shared__ int stage[kActivityTile];
+    __shared__ int n_here, base;
     const int2 it = items[blockIdx.x];
     if (it.x < 0) return;   // padding item
     const int s = it.x;
     const SigDev& sg = sigs[s];
-    const int64_t k = it.y + threadIdx.x;
-    if (k >= sg.m) return;
     const int L = sg.L;
-    zd mt[2 * kMaxL];
-    const int64_t* sh = shifts + sg.shift_off;
-    load_raw<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, 2 * L, mt);
-    double e = 0.0;   // E_k (de-rotation keeps magnitudes)
-#pragma unroll
-    for (int l = 0; l < 2 * kMaxL; ++l) e += norm2(mt[l]);   // zero beyond 2L
-
-    int a0 = 0;       // 0: rank test not yet computed
-    double nu = 0.0;
-    int a_pred = 0;
-    const bool exact = (MODES == 1) || (MODES == 3 && sg.mode == kExact);
-    if (exact) {
-        double eref = 0.0;
-        for (int l = 0; l < 2 * L; ++l) eref += epart[sg.epart_off + l];
-        eref /= (double)sg.m;
-        if (!(e > sg.tau_zero2 * eref)) return;
-        if (orders) a_pred = orders[sg.bin_off + k];
-    } else {
-        const SelDev sd = sel[s];
-#pragma unroll
-        for (int i = 0; i < kMaxL; ++i) {
-            if (i >= L) continue;
-            int64_t flat = k * L + i;
-            unsigned long long kv = sv_key(sigma[(sg.bin_off + k) * L + i]);
-            a0 += (kv > sd.thr_key || (kv == sd.thr_key && flat <= sd.thr_idx)) ? 1 : 0;
-        }
-        if (a0 == 0) return;
-        nu = sd.nu;
-    }
-    atomicAdd(&cnt[s].active, 1);
-    derotate<2 * kMaxL>(mt, k, sg.n, sh, 2 * L);
-
-    // Hypotheses: the learned order first (when given), then the canonical
-    // order from a0 (rank test in exact mode, votes in general mode).
-    BinOut o;
-    o.n = 0;
-    bool done = false;
-    const bool has_pred = a_pred >= 1 && a_pred <= L;
-    for (int step = has_pred ? -1 : 0; step < L && !done; ++step) {
-        int a;
-        if (step < 0) {
-            a = a_pred;
-        } else {
-            if ((MODES & 1) && a0 == 0) {
-                double sv[kMaxL];
-                hankel_singular_values(mt, L, sv);
-                a0 = rank_order(sv, L, sg.tau_rank);
+    const int64_t k0 = it.y;
+    const int64_t k1 = (k0 + kActivityTile < sg.m) ? k0 + kActivityTile : sg.m;
+    if (threadIdx.x == 0) n_here = 0;
+    double eref = 0.0;
+    for (int l = 0; l < 2 * L; ++l) eref += epart[sg.epart_off + l];
+    eref /= (double)sg.m;
+    SelDev sd{};
+    if (sg.mode != kExact) sd = sel[s];
+    __syncthreads();
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += kBlock) {
+        int a0 = 0;
+        bool active;
+        if (sg.mode == kExact) {
+            double e = 0.0;
+            for (int l = 0; l < 2 * L; ++l) {
+                const int64_t idx = sg.synd_off + ((int64_t)l << sg.log2m) + k;
+                double re, im;
+                if (synd32) {
+                    float2 v = synd32[idx];
+                    re = v.x;
+                    im = v.y;
+                } else {
+                    double2 v = synd64[idx];
+                    re = v.x;
+                    im = v.y;
+                }
+                e += re * re + im * im;
             }
-            a = order_at(a0, L, step);
-            if (has_pred && a == a_pred) continue;
+            active = e > sg.tau_zero2 * eref;
+        } else {
+            for (int i = 0; i < L; ++i) {
+                int64_t flat = k * L + i;
+                unsigned long long kv = sv_key(sigma[(sg.bin_off + k) * L + i]);
+                a0 += (kv > sd.thr_key || (kv == sd.thr_key && flat <= sd.thr_idx)) ? 1 : 0;
+            }
+            active = a0 > 0;
         }
-        done = try_order(mt, L, a, e, nu, sg, tab, o);
-        if (step < 0 && !done) atomicAdd(&cnt[s].mlp_fb, 1);
+        if (active) stage[atomicAdd(&n_here, 1)] = (int)(k << 3) | a0;
     }
-    if (!done) {
-        atomicAdd(&cnt[s].flagged, 1);
-        if (!exact) {
-            // queue by a0 (1..L); q < M: each bin is queued at most once
-            int q = atomicAdd(&cnt[s].nflag[a0 - 1], 1);
-            flag_list[(int64_t)(a0 - 1) * sg.m + sg.bin_off * kMaxL + q] = (int)k;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        base = atomicAdd(&work->n_active, n_here);
+        atomicAdd(&cnt[s].active, n_here);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_here; i += kBlock) list[base + i] = int2{s, stage[i]};
+}
+
+// MODES: bit 0 = the plan has exact-mode signals, bit 1 = general-mode ones;
+// each instantiation carries only the code its modes need.  One lane per
+// active bin, grid-stride over the compacted work list.
+template <typename T, int MODES>
+__global__ __launch_bounds__(kBlock) void decode_kernel(const SigDev* __restrict__ sigs,
+                                                        const int64_t* __restrict__ shifts,
+                                                        const typename V2<T>::type* __restrict__ synd,
+                                                        const SelDev* __restrict__ sel,
+                                                        const double2* __restrict__ tab,
+                                                        const signed char* __restrict__ orders,
+                                                        SigCounters* __restrict__ cnt, int64_t* __restrict__ st_loc,
+                                                        double2* __restrict__ st_val, WorkCounters* __restrict__ work,
+                                                        const int2* __restrict__ list, int2* __restrict__ cs_list,
+                                                        int64_t list_cap) {
+    __shared__ int q_cnt[kMaxL], q_base[kMaxL];
+    const int total = work->n_active;
+    for (int base0 = blockIdx.x * kBlock; base0 < total; base0 += gridDim.x * kBlock) {
+        const int item = base0 + threadIdx.x;
+        if (threadIdx.x < kMaxL) q_cnt[threadIdx.x] = 0;
+        __syncthreads();
+        int q_slot = -1, q_a = 0;
+        if (item < total) {
+        const int2 en = list[item];
+        const int s = en.x;
+        const int64_t k = en.y >> 3;
+        int a0 = en.y & 7;   // general mode: votes; exact mode: 0 (rank test when needed)
+        const SigDev& sg = sigs[s];
+        const int L = sg.L;
+        const bool exact = (MODES == 1) || (MODES == 3 && sg.mode == kExact);
+        zd mt[2 * kMaxL];
+        const int64_t* sh = shifts + sg.shift_off;
+        load_raw<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, 2 * L, mt);
+        double e = 0.0;   // E_k (de-rotation keeps magnitudes)
+#pragma unroll
+        for (int l = 0; l < 2 * kMaxL; ++l) e += norm2(mt[l]);   // zero beyond 2L
+        const double nu = exact ? 0.0 : sel[s].nu;
+        const int a_pred = (exact && orders) ? (int)orders[sg.bin_off + k] : 0;
+        derotate<2 * kMaxL>(mt, k, sg.n, sh, 2 * L);
+
+        // Hypotheses: the learned order first (when given), then the canonical
+        // order from a0 (rank test in exact mode, votes in general mode).
+        BinOut o;
+        o.n = 0;
+        bool done = false, fallback = false;
+        const bool has_pred = a_pred >= 1 && a_pred <= L;
+        for (int step = has_pred ? -1 : 0; step < L && !done; ++step) {
+            int a;
+            if (step < 0) {
+                a = a_pred;
+            } else {
+                if ((MODES & 1) && a0 == 0) {
+                    double sv[kMaxL];
+                    hankel_singular_values(mt, L, sv);
+                    a0 = rank_order(sv, L, sg.tau_rank);
+                }
+                a = order_at(a0, L, step);
+                if (has_pred && a == a_pred) continue;
+            }
+            done = try_order(mt, L, a, e, nu, sg, tab, o);
+            if (step < 0 && !done) fallback = true;
         }
-        return;
+        if (!done) o.n = 0;
+        wave_count(&cnt[s].flagged, !done);
+        if (MODES & 1) wave_count(&cnt[s].mlp_fb, fallback);
+        emit(sg, &cnt[s], k, o, st_loc, st_val);
+        // general mode: queue flagged bins for the CS step, by a0
+        if ((MODES & 2) && !done && !exact) {
+            q_a = a0;
+            q_slot = atomicAdd(&q_cnt[a0 - 1], 1);
+        }
+        }
+        __syncthreads();
+        if (threadIdx.x < kMaxL) q_base[threadIdx.x] = q_cnt[threadIdx.x] ? atomicAdd(&work->n_cs[threadIdx.x], q_cnt[threadIdx.x]) : 0;
+        __syncthreads();
+        if (q_slot >= 0) {
+            const int2 en = list[item];
+            cs_list[(int64_t)(q_a - 1) * list_cap + q_base[q_a - 1] + q_slot] = int2{en.x, en.y >> 3};
+        }
+        __syncthreads();
     }
-    emit(sg, &cnt[s], k, o, st_loc, st_val);
 }
 
 // CS step for the bins the decoder queued (general mode), one lane per bin;
 // one instantiation per vote order A0, so every wave runs one code path.
 template <typename T, int A0>
-__global__ __launch_bounds__(kBlock) void cs_kernel(const SigDev* __restrict__ sigs, const int2* __restrict__ items,
+__global__ __launch_bounds__(kBlock) void cs_kernel(const SigDev* __restrict__ sigs,
                                                     const int64_t* __restrict__ shifts,
                                                     const typename V2<T>::type* __restrict__ synd,
                                                     const double2* __restrict__ tab, SigCounters* __restrict__ cnt,
                                                     int64_t* __restrict__ st_loc, double2* __restrict__ st_val,
-                                                    const int* __restrict__ flag_list) {
-    const int2 it = items[blockIdx.x];
-    if (it.x < 0) return;   // padding item
-    const int s = it.x;
-    const SigDev& sg = sigs[s];
-    if (sg.mode != kGeneral || A0 > sg.L) return;
-    const int q = it.y + threadIdx.x;
-    if (q >= cnt[s].nflag[A0 - 1]) return;
-    const int64_t k = flag_list[(int64_t)(A0 - 1) * sg.m + sg.bin_off * kMaxL + q];
-    const int L = sg.L;
-    const int64_t* sh = shifts + sg.shift_off;
-    zd mt[2 * kMaxL];
-    load_derotated<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, sg.n, sh, 2 * L, mt);
-    zd y[kMaxR];
-    const int R = sg.R;
-    load_derotated<T, kMaxR>(synd + sg.synd_off + ((int64_t)(2 * L) << sg.log2m), sg.log2m, k, sg.n, sh + 2 * L, R, y);
-    BinOut o;
-    o.n = 0;
-    if (!cs_recover<A0>(mt, y, R, sh + 2 * L, sg, tab, o)) return;
-    atomicAdd(&cnt[s].cs, 1);
-    emit(sg, &cnt[s], k, o, st_loc, st_val);
+                                                    const WorkCounters* __restrict__ work,
+                                                    const int2* __restrict__ cs_list, int64_t list_cap) {
+    const int total = work->n_cs[A0 - 1];
+    for (int item = blockIdx.x * kBlock + threadIdx.x; item < total; item += gridDim.x * kBlock) {
+        const int2 en = cs_list[(int64_t)(A0 - 1) * list_cap + item];
+        const int s = en.x;
+        const int64_t k = en.y;
+        const SigDev& sg = sigs[s];
+        const int L = sg.L;
+        const int64_t* sh = shifts + sg.shift_off;
+        zd mt[2 * kMaxL];
+        load_derotated<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, sg.n, sh, 2 * L, mt);
+        zd y[kMaxR];
+        const int R = sg.R;
+        load_derotated<T, kMaxR>(synd + sg.synd_off + ((int64_t)(2 * L) << sg.log2m), sg.log2m, k, sg.n, sh + 2 * L,
+                                 R, y);
+        BinOut o;
+        o.n = 0;
+        const bool ok = cs_recover<A0>(mt, y, R, sh + 2 * L, sg, tab, o);
+        if (!ok) o.n = 0;
+        wave_count(&cnt[s].cs, ok);
+        emit(sg, &cnt[s], k, o, st_loc, st_val);
+    }
 }
 
 // ------------------------------------------------------------ output lists
@@ -701,12 +824,20 @@ hipError_t launch_output(const LaunchCtx& c) {
     return hipGetLastError();
 }
 
+hipError_t launch_activity(const LaunchCtx& c) {
+    if (c.n_act_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(activity_kernel, dim3(c.n_act_items), dim3(kBlock), 0, c.stream, c.sigs, c.act_items,
+                       c.fp64 ? nullptr : (const float2*)c.synd, c.fp64 ? (const double2*)c.synd : nullptr, c.epart,
+                       c.sigma, c.sel, c.work, c.active_list, c.cnt);
+    return hipGetLastError();
+}
+
 template <typename T, int MODES>
 static void launch_decode_t(const LaunchCtx& c) {
     using V = typename V2<T>::type;
-    hipLaunchKernelGGL((decode_kernel<T, MODES>), dim3(c.n_bin_items), dim3(kBlock), 0, c.stream, c.sigs, c.bin_items,
-                       c.shifts, (const V*)c.synd, c.epart, c.sigma, c.sel, c.omega, c.orders, c.cnt, c.st_loc,
-                       c.st_val, c.flag_list);
+    hipLaunchKernelGGL((decode_kernel<T, MODES>), dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs, c.shifts,
+                       (const V*)c.synd, c.sel, c.omega, c.orders, c.cnt, c.st_loc, c.st_val, c.work, c.active_list,
+                       c.cs_list, c.list_cap);
 }
 
 hipError_t launch_decode(const LaunchCtx& c) {
@@ -724,17 +855,19 @@ hipError_t launch_decode(const LaunchCtx& c) {
     return hipGetLastError();
 }
 
+template <typename T, int A0>
+static void launch_cs_one(const LaunchCtx& c) {
+    using V = typename V2<T>::type;
+    hipLaunchKernelGGL((cs_kernel<T, A0>), dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs, c.shifts,
+                       (const V*)c.synd, c.omega, c.cnt, c.st_loc, c.st_val, c.work, c.cs_list, c.list_cap);
+}
+
 template <typename T>
 static void launch_cs_t(const LaunchCtx& c) {
-    using V = typename V2<T>::type;
-    hipLaunchKernelGGL((cs_kernel<T, 1>), dim3(c.n_bin_items), dim3(kBlock), 0, c.stream, c.sigs, c.bin_items, c.shifts,
-                       (const V*)c.synd, c.omega, c.cnt, c.st_loc, c.st_val, c.flag_list);
-    hipLaunchKernelGGL((cs_kernel<T, 2>), dim3(c.n_bin_items), dim3(kBlock), 0, c.stream, c.sigs, c.bin_items, c.shifts,
-                       (const V*)c.synd, c.omega, c.cnt, c.st_loc, c.st_val, c.flag_list);
-    hipLaunchKernelGGL((cs_kernel<T, 3>), dim3(c.n_bin_items), dim3(kBlock), 0, c.stream, c.sigs, c.bin_items, c.shifts,
-                       (const V*)c.synd, c.omega, c.cnt, c.st_loc, c.st_val, c.flag_list);
-    hipLaunchKernelGGL((cs_kernel<T, 4>), dim3(c.n_bin_items), dim3(kBlock), 0, c.stream, c.sigs, c.bin_items, c.shifts,
-                       (const V*)c.synd, c.omega, c.cnt, c.st_loc, c.st_val, c.flag_list);
+    launch_cs_one<T, 1>(c);
+    launch_cs_one<T, 2>(c);
+    launch_cs_one<T, 3>(c);
+    launch_cs_one<T, 4>(c);
 }
 
 hipError_t launch_cs(const LaunchCtx& c) {

@@ -200,14 +200,15 @@ __global__ __launch_bounds__(kBlock) void syndrome_kernel(const SigDev* __restri
     }
 }
 
-__global__ void zero_counters_kernel(SigCounters* cnt, int n) {
+__global__ void zero_counters_kernel(SigCounters* cnt, int n, WorkCounters* work) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) cnt[i] = SigCounters{0, 0, 0, 0, 0, 0, 0, 0, {0, 0, 0, 0}};
+    if (i < n) cnt[i] = SigCounters{0, 0, 0, 0, 0, 0, 0, 0};
+    if (i == 0) *work = WorkCounters{0, {0, 0, 0, 0}, {0, 0, 0}};
 }
 
 hipError_t launch_zero_counters(const LaunchCtx& c) {
     int blocks = (c.n_sigs + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(zero_counters_kernel, dim3(blocks), dim3(kBlock), 0, c.stream, c.cnt, c.n_sigs);
+    hipLaunchKernelGGL(zero_counters_kernel, dim3(blocks), dim3(kBlock), 0, c.stream, c.cnt, c.n_sigs, c.work);
     return hipGetLastError();
 }
 

@@ -27,6 +27,7 @@ struct PlanLayout {
     std::vector<int4> synd_items;         // (sig, line0, nlines, 0); sig < 0 = padding
     std::vector<int2> bin_items;          // (sig, bin0)
     std::vector<int2> out_items;          // (sig, entry0)
+    std::vector<int2> act_items;          // (sig, bin0), tiles of kActivityTile
     std::vector<int> general_sigs;
     int64_t synd_elems = 0, epart_elems = 0, sigma_elems = 0, bin_elems = 0, stage_elems = 0;
     int tw_log2 = 0, om_log2 = 0;

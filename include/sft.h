@@ -160,6 +160,61 @@ sft_status sft_batch(sft_plan_t plan, const void* const* x_devs, const sft_spars
  * stream semantics as sft_exact (asynchronous). */
 sft_status sft_syndromes(sft_plan_t plan, const void* x_dev, void* out_dev);
 
+/* ---------------------------------------------------------------------------
+ * Learned order predictor (a project addition).  An MLP maps an active bin to
+ * its number of aliased frequencies 0..4, replacing the rank test of the order
+ * estimate in SFT_MODE_EXACT plans with L = 4 and SFT_FLAG_LEARNED; the rank
+ * test remains the fallback and the residual check the judge, so the output
+ * is that of the plain method (paper analogue: the order estimate of Sec.
+ * III-C, Pruning Step 1).
+ *
+ * Features of a bin (32 floats): with mt_l the de-rotated syndromes
+ * e^{-i 2 pi k l / N} m_l (l < 8), E = sum |mt_l|^2, rms = sqrt(E / 8) and
+ * u_l = mt_l conj(mt_0) / (|mt_0| rms): [Re u_0, Im u_0, ..., Re u_7, Im u_7,
+ * |mt_0| / rms, ..., |mt_7| / rms, log(E / mean bin energy), 0 x 7].
+ * Network: h1 = gelu(W1 f + b1) (128), h2 = gelu(W2 h1 + b2) (128),
+ * logits = W3 h2 + b3 (5); gelu(x) = x Phi(x).  Parameters: FP32 vector
+ * [W1 (128 x 32), b1, W2 (128 x 128), b2, W3 (5 x 128), b3], row-major,
+ * SFT_MLP_PARAMS values; the device computes with BF16 copies of W1..W3 and
+ * FP32 accumulation (MFMA).  Training minimises the mean cross-entropy with
+ * Adam (beta 0.9 / 0.999, eps 1e-8) on the FP32 master weights.
+ * ------------------------------------------------------------------------- */
+#define SFT_MLP_FEATURES 32
+#define SFT_MLP_CLASSES 5
+#define SFT_MLP_PARAMS 21381
+
+/* New predictor with He-uniform weights drawn from `seed`, zero biases.
+ * Calls on it are ordered on hip_stream (NULL = default stream). */
+sft_status sft_mlp_create(sft_mlp_t* out, uint64_t seed, void* hip_stream);
+void sft_mlp_destroy(sft_mlp_t mlp);
+/* Copy the FP32 master parameters out / in (host arrays of n = SFT_MLP_PARAMS;
+ * set also resets the Adam state).  Both synchronise the predictor's stream. */
+sft_status sft_mlp_get_params(sft_mlp_t mlp, float* host, int64_t n);
+sft_status sft_mlp_set_params(sft_mlp_t mlp, const float* host, int64_t n);
+/* logits_dev[rows][5] for feat_dev[rows][32] (device, FP32). */
+sft_status sft_mlp_forward(sft_mlp_t mlp, const float* feat_dev, int64_t rows, float* logits_dev);
+/* Gradient of the mean cross-entropy (labels_dev[rows] in 0..4) with respect
+ * to the parameters, into grad_dev[SFT_MLP_PARAMS], and the loss into
+ * loss_dev[0]; no update. */
+sft_status sft_mlp_grad(sft_mlp_t mlp, const float* feat_dev, const int32_t* labels_dev, int64_t rows,
+                        float* grad_dev, float* loss_dev);
+/* One Adam step with learning rate lr on the mean cross-entropy of the rows;
+ * the loss before the step goes to loss_dev[0] (may be NULL). */
+sft_status sft_mlp_train_step(sft_mlp_t mlp, const float* feat_dev, const int32_t* labels_dev, int64_t rows,
+                              float lr, float* loss_dev);
+const char* sft_mlp_last_error(void);
+
+/* Use `mlp` (or NULL to detach) for the plan's SFT_FLAG_LEARNED signals.  The
+ * predictor must outlive the plan's use of it. */
+sft_status sft_plan_attach_mlp(sft_plan_t plan, sft_mlp_t mlp);
+
+/* Features of the active bins of x (single-signal SFT_MODE_EXACT plan, L = 4):
+ * feat_dev[capacity][32] (FP32), bins_dev[capacity] (bin index k), and the
+ * number of active bins into count_dev[0] (entries beyond capacity are not
+ * written).  Rows come in no particular order.  Asynchronous. */
+sft_status sft_features(sft_plan_t plan, const void* x_dev, float* feat_dev, int64_t* bins_dev, int64_t capacity,
+                        int64_t* count_dev);
+
 /* Parameters the plan chose for signal `index` (0-based). */
 sft_status sft_plan_get(sft_plan_t plan, int64_t index, sft_plan_info* info);
 

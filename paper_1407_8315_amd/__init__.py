@@ -19,7 +19,7 @@ from ._lib import (  # noqa: F401
     SFT_FLAG_LEARNED, SFT_FLAG_SYNC, SFT_FLAG_CHECK_FINITE, SftError,
 )
 
-__all__ = ["Plan", "Result", "SftError", "make_params", "library_path"]
+__all__ = ["Plan", "Result", "SftError", "Mlp", "make_params", "library_path"]
 
 
 def library_path() -> str:
@@ -178,9 +178,100 @@ class Plan:
                    "sft_syndromes")
         return out
 
+    def attach(self, mlp):
+        """Use a learned order predictor for this plan's SFT_FLAG_LEARNED signals (None detaches)."""
+        _lib.check(self._lib.sft_plan_attach_mlp(self._h, mlp._h if mlp is not None else None), "sft_plan_attach_mlp")
+        self._mlp = mlp
+
+    def features(self, x, capacity=None):
+        """Predictor features of the active bins of x: (features [n, 32], bins [n]) device tensors."""
+        torch = _torch()
+        self._check_input(x)
+        cap = capacity if capacity is not None else self.infos[0]["m"]
+        feat = torch.empty((max(cap, 1), _lib.MLP_FEATURES), dtype=torch.float32, device=x.device)
+        bins = torch.empty(max(cap, 1), dtype=torch.int64, device=x.device)
+        cnt = torch.zeros(1, dtype=torch.int64, device=x.device)
+        _lib.check(self._lib.sft_features(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(feat.data_ptr()),
+                                          ctypes.c_void_p(bins.data_ptr()), cap, ctypes.c_void_p(cnt.data_ptr())),
+                   "sft_features")
+        n = min(int(cnt.item()), cap)
+        return feat[:n], bins[:n]
+
     def close(self):
         if getattr(self, "_h", None):
             self._lib.sft_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mlp:
+    """The learned order predictor (device weights, FP32 master + BF16 copies)."""
+
+    PARAMS = _lib.MLP_PARAMS
+
+    def __init__(self, seed: int = 0, stream=None):
+        torch = _torch()
+        self._lib = _lib.load()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _lib.check(self._lib.sft_mlp_create(ctypes.byref(h), int(seed), ctypes.c_void_p(self.stream.cuda_stream)),
+                   "sft_mlp_create")
+        self._h = h
+
+    def get_params(self):
+        import numpy as np
+        out = np.empty(self.PARAMS, np.float32)
+        _lib.check(self._lib.sft_mlp_get_params(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                self.PARAMS), "sft_mlp_get_params")
+        return out
+
+    def set_params(self, theta):
+        import numpy as np
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        _lib.check(self._lib.sft_mlp_set_params(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size),
+                   "sft_mlp_set_params")
+
+    def forward(self, feat):
+        torch = _torch()
+        feat = feat.contiguous().float()
+        logits = torch.empty((feat.shape[0], _lib.MLP_CLASSES), dtype=torch.float32, device=feat.device)
+        _lib.check(self._lib.sft_mlp_forward(self._h, ctypes.c_void_p(feat.data_ptr()), feat.shape[0],
+                                             ctypes.c_void_p(logits.data_ptr())), "sft_mlp_forward")
+        return logits
+
+    def grad(self, feat, labels):
+        torch = _torch()
+        feat = feat.contiguous().float()
+        labels = labels.contiguous().to(torch.int32)
+        g = torch.empty(self.PARAMS, dtype=torch.float32, device=feat.device)
+        loss = torch.empty(1, dtype=torch.float32, device=feat.device)
+        _lib.check(self._lib.sft_mlp_grad(self._h, ctypes.c_void_p(feat.data_ptr()), ctypes.c_void_p(labels.data_ptr()),
+                                          feat.shape[0], ctypes.c_void_p(g.data_ptr()),
+                                          ctypes.c_void_p(loss.data_ptr())), "sft_mlp_grad")
+        return g, loss
+
+    def train_step(self, feat, labels, lr, loss=None):
+        _lib.check(self._lib.sft_mlp_train_step(self._h, ctypes.c_void_p(feat.data_ptr()),
+                                                ctypes.c_void_p(labels.data_ptr()), feat.shape[0], float(lr),
+                                                ctypes.c_void_p(loss.data_ptr()) if loss is not None else None),
+                   "sft_mlp_train_step")
+
+    def save(self, path):
+        import numpy as np
+        np.save(path, self.get_params())
+
+    def load(self, path):
+        import numpy as np
+        self.set_params(np.load(path, allow_pickle=False))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sft_mlp_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -18,7 +18,10 @@ SFT_MAX_RSHIFTS = 64
 EXPORTS = [
     "sft_plan", "sft_exact", "sft_general", "sft_batch", "sft_syndromes", "sft_plan_get", "sft_destroy",
     "sft_status_str", "sft_last_error", "sft_abi_version",
+    "sft_mlp_create", "sft_mlp_destroy", "sft_mlp_get_params", "sft_mlp_set_params", "sft_mlp_forward",
+    "sft_mlp_grad", "sft_mlp_train_step", "sft_mlp_last_error", "sft_plan_attach_mlp", "sft_features",
 ]
+MLP_FEATURES, MLP_CLASSES, MLP_PARAMS = 32, 5, 21381
 
 
 class Params(ctypes.Structure):
@@ -97,6 +100,22 @@ def load():
     lib.sft_last_error.restype = ctypes.c_char_p
     lib.sft_abi_version.argtypes = []
     lib.sft_abi_version.restype = ctypes.c_int32
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.sft_mlp_create.argtypes = [ctypes.POINTER(vp), ctypes.c_uint64, vp]
+    lib.sft_mlp_destroy.argtypes = [vp]
+    lib.sft_mlp_destroy.restype = None
+    lib.sft_mlp_get_params.argtypes = [vp, fp, i64]
+    lib.sft_mlp_set_params.argtypes = [vp, fp, i64]
+    lib.sft_mlp_forward.argtypes = [vp, vp, i64, vp]
+    lib.sft_mlp_grad.argtypes = [vp, vp, vp, i64, vp, vp]
+    lib.sft_mlp_train_step.argtypes = [vp, vp, vp, i64, ctypes.c_float, vp]
+    lib.sft_mlp_last_error.argtypes = []
+    lib.sft_mlp_last_error.restype = ctypes.c_char_p
+    lib.sft_plan_attach_mlp.argtypes = [vp, vp]
+    lib.sft_features.argtypes = [vp, vp, vp, vp, i64, vp]
+    for name in ("sft_mlp_create", "sft_mlp_get_params", "sft_mlp_set_params", "sft_mlp_forward", "sft_mlp_grad",
+                 "sft_mlp_train_step", "sft_plan_attach_mlp", "sft_features"):
+        getattr(lib, name).restype = st
     _lib = lib
     return lib
 
@@ -111,5 +130,5 @@ def check(status: int, what: str = ""):
     if status != SFT_OK:
         lib = load()
         name = lib.sft_status_str(status).decode()
-        detail = lib.sft_last_error().decode()
+        detail = (lib.sft_mlp_last_error() if what.startswith("sft_mlp") else lib.sft_last_error()).decode()
         raise SftError(status, f"{what}: {name}: {detail}")

@@ -151,10 +151,18 @@ LaunchCtx make_ctx(const sft_plan_s* p) {
     return c;
 }
 
+bool learned(const sft_plan_s* p) {
+    for (auto& g : p->sig)
+        if (g.flags & SFT_FLAG_LEARNED) return true;
+    return false;
+}
+
 // Enqueue the whole path.  With events != nullptr, record stage boundaries.
-sft_status enqueue(const sft_plan_s* p, const signed char* orders, hipEvent_t* events) {
+// Learned plans run the predictor between the activity pass and the decoder.
+sft_status enqueue(const sft_plan_s* p, hipEvent_t* events) {
     LaunchCtx c = make_ctx(p);
-    c.orders = orders;
+    const bool use_mlp = learned(p) && p->mlp;
+    c.orders = use_mlp ? p->d_orders : nullptr;
     if (events) HIPCHK(hipEventRecord(events[0], p->stream));
     HIPCHK(launch_zero_counters(c));
     HIPCHK(launch_syndromes(c));
@@ -162,6 +170,10 @@ sft_status enqueue(const sft_plan_s* p, const signed char* orders, hipEvent_t* e
     HIPCHK(launch_singular_values(c));
     HIPCHK(launch_select(c));
     HIPCHK(launch_activity(c));
+    if (use_mlp) {
+        sft_status s = sft_mlp_launch_infer(p->mlp, c, p->d_orders);
+        if (s != SFT_OK) return s;
+    }
     if (events) HIPCHK(hipEventRecord(events[2], p->stream));
     HIPCHK(launch_decode(c));
     HIPCHK(launch_cs(c));
@@ -240,24 +252,13 @@ sft_status run_single(sft_plan_t plan, const void* x, const sft_sparse_out* out,
     sft_status s = upload_io(plan, xs, out);
     if (s != SFT_OK) return s;
     const bool timed = st != nullptr;
-    s = sft_enqueue_learned(plan, timed ? plan->ev : nullptr);
+    s = enqueue(plan, timed ? plan->ev : nullptr);
     if (s != SFT_OK) return s;
     if (st || any_sync(plan)) return finish(plan, st, timed);
     return SFT_OK;
 }
 
 }  // namespace
-
-// Learned-mode hook: the predictor (mlp.hip) fills per-bin orders before the
-// decoder runs; without a predictor this is the plain enqueue.
-sft_status sft_enqueue_learned(sft_plan_t plan, hipEvent_t* events) {
-    const signed char* orders = nullptr;
-    if (plan->mlp && (plan->sig[0].flags & SFT_FLAG_LEARNED)) {
-        sft_status s = sft_mlp_enqueue_orders(plan, &orders);
-        if (s != SFT_OK) return s;
-    }
-    return enqueue(plan, orders, events);
-}
 
 extern "C" {
 
@@ -423,17 +424,17 @@ sft_status sft_batch(sft_plan_t plan, const void* const* x_devs, const sft_spars
     sft_status s = upload_io(plan, x_devs, outs);
     if (s != SFT_OK) return s;
     if (stats) {
-        s = sft_enqueue_learned(plan, plan->ev);
+        s = enqueue(plan, plan->ev);
         if (s != SFT_OK) return s;
         return finish(plan, stats, true);
     }
     if (plan->stream == nullptr) {
         // the legacy default stream cannot be captured: enqueue directly
-        s = sft_enqueue_learned(plan, nullptr);
+        s = enqueue(plan, nullptr);
     } else {
         if (!plan->gexec) {
             HIPCHK(hipStreamBeginCapture(plan->stream, hipStreamCaptureModeThreadLocal));
-            sft_status cs = sft_enqueue_learned(plan, nullptr);
+            sft_status cs = enqueue(plan, nullptr);
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamEndCapture(plan->stream, &g);
             if (cs != SFT_OK) {
@@ -498,9 +499,38 @@ sft_status sft_plan_get(sft_plan_t plan, int64_t index, sft_plan_info* info) {
 
 void sft_destroy(sft_plan_t plan) { release(plan); }
 
+sft_status sft_plan_attach_mlp(sft_plan_t plan, sft_mlp_t mlp) {
+    if (!plan) return fail(SFT_E_INVALID, "plan is NULL");
+    if (plan->gexec) {
+        (void)hipGraphExecDestroy(plan->gexec);
+        plan->gexec = nullptr;
+        (void)hipGraphDestroy(plan->graph);
+        plan->graph = nullptr;
+    }
+    plan->mlp = mlp;
+    return SFT_OK;
+}
+
+sft_status sft_features(sft_plan_t plan, const void* x_dev, float* feat_dev, int64_t* bins_dev, int64_t capacity,
+                        int64_t* count_dev) {
+    if (!plan || !x_dev || !count_dev || capacity < 0 || (capacity > 0 && (!feat_dev || !bins_dev)))
+        return fail(SFT_E_INVALID, "bad argument");
+    if (plan->sig.size() != 1 || plan->sig[0].mode != kExact || plan->sig[0].L != 4)
+        return fail(SFT_E_UNSUPPORTED, "features need a single-signal exact-mode plan with L = 4");
+    if (plan->upload_pending) HIPCHK(hipEventSynchronize(plan->ev_upload));
+    plan->h_io[0] = IoDev{x_dev, nullptr, nullptr, 0, nullptr};
+    HIPCHK(hipMemcpyAsync(plan->d_io, plan->h_io, sizeof(IoDev), hipMemcpyHostToDevice, plan->stream));
+    HIPCHK(hipEventRecord(plan->ev_upload, plan->stream));
+    plan->upload_pending = true;
+    LaunchCtx c = make_ctx(plan);
+    HIPCHK(launch_zero_counters(c));
+    HIPCHK(launch_syndromes(c));
+    HIPCHK(launch_activity(c));
+    sft_status s = sft_features_enqueue(c, feat_dev, bins_dev, capacity, count_dev);
+    if (s != SFT_OK) return s;
+    if (any_sync(plan)) HIPCHK(hipStreamSynchronize(plan->stream));
+    return SFT_OK;
+}
+
 }  // extern "C"
 
-// Accessors used by the learned-mode translation unit.
-sft_mlp_t& sft_plan_mlp_slot(sft_plan_t plan) { return plan->mlp; }
-signed char* sft_plan_orders(sft_plan_t plan) { return plan->d_orders; }
-LaunchCtx sft_plan_ctx(sft_plan_t plan) { return make_ctx(plan); }

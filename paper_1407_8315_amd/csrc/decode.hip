@@ -8,7 +8,6 @@
 namespace sft {
 
 constexpr int kMaxR = 16;     // random shifts handled by the CS step
-constexpr int kMaxCand = 8;   // pruned candidates (min(2 a, R, d) <= 8)
 
 template <typename T>
 struct V2;

@@ -1,8 +1,665 @@
-// Learned order predictor (filled in with the MLP kernels).
+// Learned order predictor: a small MLP that maps an active bin's syndromes to
+// its number of aliased frequencies (0..4), replacing the rank test of the
+// order estimate; the rank test stays as the fallback and the residual check
+// as the judge.  (A project addition; its analogue in the paper is the order
+// estimate of Pruning Step 1, Sec. III-C.)
+//
+// Network 32 -> 128 -> 128 -> 5 with GELU, BF16 weights, FP32 accumulation on
+// v_mfma_f32_16x16x16_bf16.  A block holds 64 rows (bins) in LDS; each of its
+// 4 waves owns 16 rows in the forward pass and in the input-side backward pass;
+// weight gradients reduce over the block's rows with MFMA and are added to a
+// global FP32 buffer.  Adam updates FP32 master weights and refreshes the BF16
+// copies.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "algebra.h"
 #include "plan_host.h"
 
-sft_status sft_mlp_enqueue_orders(sft_plan_t plan, const signed char** orders) {
-    (void)plan;
-    *orders = nullptr;
-    return SFT_E_INVALID;
+namespace sft {
+
+constexpr int kNF = 32, kNH = 128, kNC = 5, kNCp = 16;
+constexpr int kOffW1 = 0, kOffB1 = 4096, kOffW2 = 4224, kOffB2 = 20608, kOffW3 = 20736, kOffB3 = 21376;
+constexpr int kNParams = 21381;
+constexpr int kLdX = 36, kLdH = 132, kLdC = 20;   // padded LDS row strides (bf16 / float elements)
+constexpr int kRows = 64;                          // rows per block tile
+// BF16 weight image (same padded layout in global memory and LDS)
+constexpr int kW1Elems = kNH * kLdX, kW2Elems = kNH * kLdH, kW3Elems = kNCp * kLdH;
+constexpr int kWElems = kW1Elems + kW2Elems + kW3Elems;
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef unsigned short bf16;
+
+__host__ __device__ inline bf16 to_bf16(float f) {
+    union {
+        float f;
+        unsigned u;
+    } v;
+    v.f = f;
+    unsigned u = v.u;
+    u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest, ties to even
+    return (bf16)(u >> 16);
 }
+__device__ inline float from_bf16(bf16 h) { return __uint_as_float(((unsigned)h) << 16); }
+__device__ inline float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ inline float gelu_grad(float x) {
+    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+__device__ inline v4f mfma16(v4s a, v4s b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
+__device__ inline v4s ld4(const bf16* p) { return *reinterpret_cast<const v4s*>(p); }
+__device__ inline v4s gather4(const bf16* p, int stride) {
+    v4s r;
+    r.x = (short)p[0];
+    r.y = (short)p[stride];
+    r.z = (short)p[2 * stride];
+    r.w = (short)p[3 * stride];
+    return r;
+}
+
+struct alignas(16) WeightsLds {
+    bf16 w[kWElems];                   // W1 [128][36], W2 [128][132], W3 [16][132]
+    float b1[kNH], b2[kNH], b3[kNCp];
+};
+
+// Copy the BF16 image and the FP32 biases into LDS (whole block).
+__device__ inline void load_weights(WeightsLds& W, const bf16* __restrict__ wimg, const float* __restrict__ theta) {
+    const uint4* src = reinterpret_cast<const uint4*>(wimg);
+    uint4* dst = reinterpret_cast<uint4*>(W.w);
+    for (int i = threadIdx.x; i < kWElems / 8; i += blockDim.x) dst[i] = src[i];
+    for (int i = threadIdx.x; i < kNH; i += blockDim.x) {
+        W.b1[i] = theta[kOffB1 + i];
+        W.b2[i] = theta[kOffB2 + i];
+    }
+    for (int i = threadIdx.x; i < kNCp; i += blockDim.x) W.b3[i] = i < kNC ? theta[kOffB3 + i] : 0.0f;
+}
+
+// Forward pass of the wave's 16 rows (r0 .. r0+15): H1, H2 (BF16, LDS) and the
+// pre-activations Z1, Z2 (FP32, registers, MFMA output layout: element j of
+// tile t of lane l is row r0 + 4 (l / 16) + j, column 16 t + l % 16); returns
+// the logits tile (columns 0..15, valid 0..4).
+struct Fwd {
+    v4f z1[8], z2[8], z3;
+};
+__device__ inline void forward_rows(const WeightsLds& W, const bf16* X, bf16* H1, bf16* H2, int r0, Fwd& f) {
+    const int l = __lane_id(), li = l & 15, lq = l >> 4;
+    const bf16* w1 = W.w;
+    const bf16* w2 = W.w + kW1Elems;
+    const bf16* w3 = W.w + kW1Elems + kW2Elems;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) f.z1[t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < kNF / 16; ++kk) {
+        v4s a = ld4(X + (r0 + li) * kLdX + kk * 16 + lq * 4);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) f.z1[t] = mfma16(a, ld4(w1 + (t * 16 + li) * kLdX + kk * 16 + lq * 4), f.z1[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float z = f.z1[t][j] + W.b1[t * 16 + li];
+            f.z1[t][j] = z;
+            H1[(r0 + lq * 4 + j) * kLdH + t * 16 + li] = to_bf16(gelu(z));
+        }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 8; ++t) f.z2[t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < kNH / 16; ++kk) {
+        v4s a = ld4(H1 + (r0 + li) * kLdH + kk * 16 + lq * 4);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) f.z2[t] = mfma16(a, ld4(w2 + (t * 16 + li) * kLdH + kk * 16 + lq * 4), f.z2[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float z = f.z2[t][j] + W.b2[t * 16 + li];
+            f.z2[t][j] = z;
+            H2[(r0 + lq * 4 + j) * kLdH + t * 16 + li] = to_bf16(gelu(z));
+        }
+    __syncthreads();
+    f.z3 = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < kNH / 16; ++kk)
+        f.z3 = mfma16(ld4(H2 + (r0 + li) * kLdH + kk * 16 + lq * 4), ld4(w3 + li * kLdH + kk * 16 + lq * 4), f.z3);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) f.z3[j] += W.b3[li];
+}
+
+// Features of one bin (see the module comment of the reference network):
+// de-rotated syndromes rotated so that mt_0 is real positive and scaled to
+// unit mean square, their magnitudes, and log(E / E_ref).
+__device__ inline void bin_features(const zd* mt, double eref, float* f) {
+    double e = 0.0;
+#pragma unroll
+    for (int l = 0; l < 8; ++l) e += norm2(mt[l]);
+    const double rms = sqrt(e / 8.0);
+    const double a0 = cabs(mt[0]);
+    zd ph = a0 > 0.0 ? zd{mt[0].x / a0, -mt[0].y / a0} : zd{1.0, 0.0};
+#pragma unroll
+    for (int l = 0; l < 8; ++l) {
+        zd u = mt[l] * ph;
+        f[2 * l] = (float)(u.x / rms);
+        f[2 * l + 1] = (float)(u.y / rms);
+        f[16 + l] = (float)(cabs(mt[l]) / rms);
+    }
+    f[24] = (float)log(e / eref);
+#pragma unroll
+    for (int i = 25; i < kNF; ++i) f[i] = 0.0f;
+}
+
+template <typename T>
+struct VT;
+template <>
+struct VT<float> {
+    using type = float2;
+};
+template <>
+struct VT<double> {
+    using type = double2;
+};
+
+// Features of the active-list entry `item` (exact mode, L = 4).
+template <typename T>
+__device__ inline void list_features(const LaunchCtx& c, const typename VT<T>::type* synd, int item, float* f,
+                                     int& s_out, int64_t& k_out) {
+    const int2 en = c.active_list[item];
+    const SigDev& sg = c.sigs[en.x];
+    const int64_t k = en.y >> 3;
+    zd mt[8];
+#pragma unroll
+    for (int l = 0; l < 8; ++l) {
+        auto v = synd[sg.synd_off + ((int64_t)l << sg.log2m) + k];
+        mt[l] = cmul_conj(unit_root((k * l) & (sg.n - 1), sg.n), zd{(double)v.x, (double)v.y});
+    }
+    double eref = 0.0;
+#pragma unroll
+    for (int l = 0; l < 8; ++l) eref += c.epart[sg.epart_off + l];
+    eref /= (double)sg.m;
+    bin_features(mt, eref, f);
+    s_out = en.x;
+    k_out = k;
+}
+
+// Learned orders for every entry of the active list (features fused in).
+template <typename T>
+__global__ __launch_bounds__(256) void infer_kernel(LaunchCtx c, const bf16* __restrict__ wimg,
+                                                    const float* __restrict__ theta, signed char* __restrict__ orders) {
+    __shared__ WeightsLds W;
+    __shared__ __attribute__((aligned(16))) bf16 X[kRows * kLdX];
+    __shared__ __attribute__((aligned(16))) bf16 H1[kRows * kLdH];
+    __shared__ __attribute__((aligned(16))) bf16 H2[kRows * kLdH];
+    __shared__ float Z[kRows * kLdC];
+    __shared__ int sig_of[kRows];
+    __shared__ int bin_of[kRows];
+    load_weights(W, wimg, theta);
+    const int total = c.work->n_active;
+    const typename VT<T>::type* synd = (const typename VT<T>::type*)c.synd;
+    const int w = threadIdx.x >> 6;
+    for (int base = blockIdx.x * kRows; base < total; base += gridDim.x * kRows) {
+        __syncthreads();
+        if (threadIdx.x < kRows) {
+            float f[kNF];
+            const int item = base + threadIdx.x;
+            int s = -1;
+            int64_t k = 0;
+            if (item < total) list_features<T>(c, synd, item, f, s, k);
+            else
+                for (int i = 0; i < kNF; ++i) f[i] = 0.0f;
+            for (int i = 0; i < kNF; ++i) X[threadIdx.x * kLdX + i] = to_bf16(f[i]);
+            sig_of[threadIdx.x] = s;
+            bin_of[threadIdx.x] = (int)k;
+        }
+        __syncthreads();
+        Fwd fw;
+        forward_rows(W, X, H1, H2, w * 16, fw);
+        const int l = __lane_id(), li = l & 15, lq = l >> 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Z[(w * 16 + lq * 4 + j) * kLdC + li] = fw.z3[j];
+        __syncthreads();
+        if (threadIdx.x < kRows && sig_of[threadIdx.x] >= 0) {
+            int best = 0;
+            float bv = Z[threadIdx.x * kLdC];
+            for (int cl = 1; cl < kNC; ++cl)
+                if (Z[threadIdx.x * kLdC + cl] > bv) {
+                    bv = Z[threadIdx.x * kLdC + cl];
+                    best = cl;
+                }
+            const SigDev& sg = c.sigs[sig_of[threadIdx.x]];
+            orders[sg.bin_off + bin_of[threadIdx.x]] = (signed char)best;
+        }
+    }
+}
+
+// Features of the active bins of a single-signal plan, for training data.
+template <typename T>
+__global__ __launch_bounds__(256) void features_kernel(LaunchCtx c, float* __restrict__ feat, int64_t* __restrict__ bins,
+                                                       int64_t cap) {
+    const int total = c.work->n_active;
+    const typename VT<T>::type* synd = (const typename VT<T>::type*)c.synd;
+    for (int item = blockIdx.x * blockDim.x + threadIdx.x; item < total; item += gridDim.x * blockDim.x) {
+        if (item >= cap) continue;
+        float f[kNF];
+        int s;
+        int64_t k;
+        list_features<T>(c, synd, item, f, s, k);
+        for (int i = 0; i < kNF; ++i) feat[(int64_t)item * kNF + i] = f[i];
+        bins[item] = k;
+    }
+}
+
+// Logits of given feature rows (forward pass only).
+__global__ __launch_bounds__(256) void forward_kernel(const float* __restrict__ feat, int rows,
+                                                      const bf16* __restrict__ wimg, const float* __restrict__ theta,
+                                                      float* __restrict__ logits) {
+    __shared__ WeightsLds W;
+    __shared__ __attribute__((aligned(16))) bf16 X[kRows * kLdX];
+    __shared__ __attribute__((aligned(16))) bf16 H1[kRows * kLdH];
+    __shared__ __attribute__((aligned(16))) bf16 H2[kRows * kLdH];
+    load_weights(W, wimg, theta);
+    const int w = threadIdx.x >> 6;
+    for (int base = blockIdx.x * kRows; base < rows; base += gridDim.x * kRows) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < kRows * kNF; i += blockDim.x) {
+            const int r = i / kNF, col = i % kNF;
+            X[r * kLdX + col] = (base + r < rows) ? to_bf16(feat[(int64_t)(base + r) * kNF + col]) : (bf16)0;
+        }
+        __syncthreads();
+        Fwd fw;
+        forward_rows(W, X, H1, H2, w * 16, fw);
+        const int l = __lane_id(), li = l & 15, lq = l >> 4;
+        if (li < kNC)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = base + w * 16 + lq * 4 + j;
+                if (r < rows) logits[(int64_t)r * kNC + li] = fw.z3[j];
+            }
+    }
+}
+
+// Gradient of the mean cross-entropy over `rows` labelled feature rows, added
+// into grad (FP32 [kNParams]); the loss is added into *loss.
+__global__ __launch_bounds__(256) void grad_kernel(const float* __restrict__ feat, const int* __restrict__ labels,
+                                                   int rows, const bf16* __restrict__ wimg,
+                                                   const float* __restrict__ theta, float* __restrict__ grad,
+                                                   float* __restrict__ loss) {
+    __shared__ WeightsLds W;
+    __shared__ __attribute__((aligned(16))) bf16 X[kRows * kLdX];
+    __shared__ __attribute__((aligned(16))) bf16 H1[kRows * kLdH];
+    __shared__ __attribute__((aligned(16))) bf16 H2[kRows * kLdH];
+    __shared__ __attribute__((aligned(16))) bf16 D1[kRows * kLdH];   // dZ1
+    __shared__ __attribute__((aligned(16))) bf16 D2[kRows * kLdH];   // dZ2
+    __shared__ __attribute__((aligned(16))) bf16 D3[kRows * kLdC];   // dZ3 (16 columns used)
+    __shared__ float Z[kRows * kLdC];   // logits, then dZ3 in FP32
+    __shared__ float red[256];
+    load_weights(W, wimg, theta);
+    const bf16* w2 = W.w + kW1Elems;
+    const bf16* w3 = W.w + kW1Elems + kW2Elems;
+    const int w = threadIdx.x >> 6;
+    const int l = __lane_id(), li = l & 15, lq = l >> 4;
+    const float inv_n = 1.0f / (float)rows;
+    for (int base = blockIdx.x * kRows; base < rows; base += gridDim.x * kRows) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < kRows * kNF; i += blockDim.x) {
+            const int r = i / kNF, col = i % kNF;
+            X[r * kLdX + col] = (base + r < rows) ? to_bf16(feat[(int64_t)(base + r) * kNF + col]) : (bf16)0;
+        }
+        __syncthreads();
+        Fwd fw;
+        forward_rows(W, X, H1, H2, w * 16, fw);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Z[(w * 16 + lq * 4 + j) * kLdC + li] = fw.z3[j];
+        __syncthreads();
+        // softmax, loss and dZ3 = (p - onehot) / n per row; padding rows get 0
+        float my_loss = 0.0f;
+        if (threadIdx.x < kRows) {
+            const int r = threadIdx.x;
+            const bool valid = base + r < rows;
+            float zmax = Z[r * kLdC];
+            for (int cl = 1; cl < kNC; ++cl) zmax = fmaxf(zmax, Z[r * kLdC + cl]);
+            float p[kNC], sum = 0.0f;
+            for (int cl = 0; cl < kNC; ++cl) {
+                p[cl] = expf(Z[r * kLdC + cl] - zmax);
+                sum += p[cl];
+            }
+            const int y = valid ? labels[base + r] : 0;
+            for (int cl = 0; cl < kNCp; ++cl) {
+                float g = 0.0f;
+                if (valid && cl < kNC) g = (p[cl] / sum - (cl == y ? 1.0f : 0.0f)) * inv_n;
+                Z[r * kLdC + cl] = g;
+                D3[r * kLdC + cl] = to_bf16(g);
+            }
+            if (valid) my_loss = -logf(p[y] / sum);
+        }
+        red[threadIdx.x] = my_loss;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) atomicAdd(loss, red[0] * inv_n);
+        // dH2 = dZ3 W3 (own rows), dZ2 = dH2 * gelu'(Z2)
+        {
+            v4f acc[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+            v4s a = ld4(D3 + (w * 16 + li) * kLdC + lq * 4);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) acc[t] = mfma16(a, gather4(w3 + (lq * 4) * kLdH + t * 16 + li, kLdH), acc[t]);
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    D2[(w * 16 + lq * 4 + j) * kLdH + t * 16 + li] = to_bf16(acc[t][j] * gelu_grad(fw.z2[t][j]));
+        }
+        __syncthreads();
+        // dH1 = dZ2 W2 (own rows), dZ1 = dH1 * gelu'(Z1)
+        {
+            v4f acc[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kk = 0; kk < kNH / 16; ++kk) {
+                v4s a = ld4(D2 + (w * 16 + li) * kLdH + kk * 16 + lq * 4);
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    acc[t] = mfma16(a, gather4(w2 + (kk * 16 + lq * 4) * kLdH + t * 16 + li, kLdH), acc[t]);
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    D1[(w * 16 + lq * 4 + j) * kLdH + t * 16 + li] = to_bf16(acc[t][j] * gelu_grad(fw.z1[t][j]));
+        }
+        __syncthreads();
+        // weight gradients, reduced over the 64 rows: dW = dZ^T H (MFMA, K = rows)
+        // dW2 [128][128]: 64 tiles, 16 per wave
+        for (int tile = w; tile < 64; tile += 4) {
+            const int tm = tile >> 3, tn = tile & 7;
+            v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kk = 0; kk < kRows / 16; ++kk) {
+                v4s a = gather4(D2 + (kk * 16 + lq * 4) * kLdH + tm * 16 + li, kLdH);
+                v4s b = gather4(H1 + (kk * 16 + lq * 4) * kLdH + tn * 16 + li, kLdH);
+                acc = mfma16(a, b, acc);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                atomicAdd(&grad[kOffW2 + (tm * 16 + lq * 4 + j) * kNH + tn * 16 + li], acc[j]);
+        }
+        // dW1 [128][32]: 16 tiles, 4 per wave
+        for (int tile = w; tile < 16; tile += 4) {
+            const int tm = tile >> 1, tn = tile & 1;
+            v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kk = 0; kk < kRows / 16; ++kk) {
+                v4s a = gather4(D1 + (kk * 16 + lq * 4) * kLdH + tm * 16 + li, kLdH);
+                v4s b = gather4(X + (kk * 16 + lq * 4) * kLdX + tn * 16 + li, kLdX);
+                acc = mfma16(a, b, acc);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                atomicAdd(&grad[kOffW1 + (tm * 16 + lq * 4 + j) * kNF + tn * 16 + li], acc[j]);
+        }
+        // dW3 [5][128]: 8 tiles (rows 0..15, 5 valid), 2 per wave
+        for (int tn = w; tn < 8; tn += 4) {
+            v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kk = 0; kk < kRows / 16; ++kk) {
+                v4s a = gather4(D3 + (kk * 16 + lq * 4) * kLdC + li, kLdC);
+                v4s b = gather4(H2 + (kk * 16 + lq * 4) * kLdH + tn * 16 + li, kLdH);
+                acc = mfma16(a, b, acc);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (lq * 4 + j < kNC) atomicAdd(&grad[kOffW3 + (lq * 4 + j) * kNH + tn * 16 + li], acc[j]);
+        }
+        // bias gradients: column sums of dZ1, dZ2 (BF16 copies) and dZ3 (FP32)
+        for (int col = threadIdx.x; col < 2 * kNH + kNC; col += blockDim.x) {
+            float sacc = 0.0f;
+            if (col < kNH) {
+                for (int r = 0; r < kRows; ++r) sacc += from_bf16(D1[r * kLdH + col]);
+                atomicAdd(&grad[kOffB1 + col], sacc);
+            } else if (col < 2 * kNH) {
+                for (int r = 0; r < kRows; ++r) sacc += from_bf16(D2[r * kLdH + col - kNH]);
+                atomicAdd(&grad[kOffB2 + col - kNH], sacc);
+            } else {
+                for (int r = 0; r < kRows; ++r) sacc += Z[r * kLdC + col - 2 * kNH];
+                atomicAdd(&grad[kOffB3 + col - 2 * kNH], sacc);
+            }
+        }
+    }
+}
+
+__global__ void zero_kernel(float* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+__global__ void count_kernel(const WorkCounters* work, int64_t* count) { *count = work->n_active; }
+
+// Adam on the FP32 master weights; refreshes the BF16 image and clears grad.
+__global__ void adam_kernel(float* __restrict__ theta, float* __restrict__ grad, float* __restrict__ m1,
+                            float* __restrict__ m2, bf16* __restrict__ wimg, float lr, float b1c, float b2c) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kNParams) return;
+    const float g = grad[i];
+    const float a = 0.9f * m1[i] + 0.1f * g;
+    const float b = 0.999f * m2[i] + 0.001f * g * g;
+    m1[i] = a;
+    m2[i] = b;
+    const float p = theta[i] - lr * (a / b1c) / (sqrtf(b / b2c) + 1e-8f);
+    theta[i] = p;
+    grad[i] = 0.0f;
+    // position in the BF16 image
+    int pos = -1;
+    if (i < kOffB1) pos = (i / kNF) * kLdX + (i % kNF);
+    else if (i >= kOffW2 && i < kOffB2) pos = kW1Elems + ((i - kOffW2) / kNH) * kLdH + ((i - kOffW2) % kNH);
+    else if (i >= kOffW3 && i < kOffB3) pos = kW1Elems + kW2Elems + ((i - kOffW3) / kNH) * kLdH + ((i - kOffW3) % kNH);
+    if (pos >= 0) wimg[pos] = to_bf16(p);
+}
+
+}  // namespace sft
+
+using namespace sft;
+
+struct sft_mlp_s {
+    hipStream_t stream = nullptr;
+    float* theta = nullptr;   // FP32 master [kNParams]
+    float* grad = nullptr;
+    float* m1 = nullptr;
+    float* m2 = nullptr;
+    bf16* wimg = nullptr;     // BF16 image [kWElems]
+    float* scratch_loss = nullptr;
+    int64_t step = 0;
+};
+
+namespace {
+
+thread_local std::string g_mlp_err;
+
+sft_status mfail(sft_status s, const std::string& m) {
+    g_mlp_err = m;
+    return s;
+}
+
+#define MHIP(call)                                                                                    \
+    do {                                                                                              \
+        hipError_t e_ = (call);                                                                       \
+        if (e_ != hipSuccess) return mfail(SFT_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+std::vector<bf16> host_image(const std::vector<float>& th) {
+    std::vector<bf16> img((size_t)kWElems, 0);
+    for (int i = 0; i < kNH * kNF; ++i) img[(size_t)((i / kNF) * kLdX + i % kNF)] = to_bf16(th[(size_t)(kOffW1 + i)]);
+    for (int i = 0; i < kNH * kNH; ++i)
+        img[(size_t)(kW1Elems + (i / kNH) * kLdH + i % kNH)] = to_bf16(th[(size_t)(kOffW2 + i)]);
+    for (int i = 0; i < kNC * kNH; ++i)
+        img[(size_t)(kW1Elems + kW2Elems + (i / kNH) * kLdH + i % kNH)] = to_bf16(th[(size_t)(kOffW3 + i)]);
+    return img;
+}
+
+sft_status upload(sft_mlp_t m, const std::vector<float>& th) {
+    std::vector<bf16> img = host_image(th);
+    MHIP(hipMemcpy(m->theta, th.data(), th.size() * sizeof(float), hipMemcpyHostToDevice));
+    MHIP(hipMemcpy(m->wimg, img.data(), img.size() * sizeof(bf16), hipMemcpyHostToDevice));
+    MHIP(hipMemset(m->grad, 0, kNParams * sizeof(float)));
+    MHIP(hipMemset(m->m1, 0, kNParams * sizeof(float)));
+    MHIP(hipMemset(m->m2, 0, kNParams * sizeof(float)));
+    m->step = 0;
+    return SFT_OK;
+}
+
+int grid_for(int64_t rows) {
+    int64_t b = (rows + kRows - 1) / kRows;
+    return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+
+}  // namespace
+
+// Learned mode hook: run the predictor over the active list (after the
+// activity pass, before the decoder).
+sft_status sft_mlp_launch_infer(sft_mlp_t m, const LaunchCtx& c, signed char* orders) {
+    if (!m) return SFT_OK;
+    if (c.fp64)
+        hipLaunchKernelGGL(infer_kernel<double>, dim3(c.n_work_blocks), dim3(256), 0, c.stream, c, m->wimg, m->theta,
+                           orders);
+    else
+        hipLaunchKernelGGL(infer_kernel<float>, dim3(c.n_work_blocks), dim3(256), 0, c.stream, c, m->wimg, m->theta,
+                           orders);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SFT_OK : mfail(SFT_E_DEVICE, hipGetErrorString(e));
+}
+
+sft_status sft_features_enqueue(const LaunchCtx& c, float* feat, int64_t* bins, int64_t cap, int64_t* count) {
+    hipLaunchKernelGGL(count_kernel, dim3(1), dim3(1), 0, c.stream, c.work, count);
+    if (c.fp64)
+        hipLaunchKernelGGL(features_kernel<double>, dim3(c.n_work_blocks), dim3(256), 0, c.stream, c, feat, bins, cap);
+    else
+        hipLaunchKernelGGL(features_kernel<float>, dim3(c.n_work_blocks), dim3(256), 0, c.stream, c, feat, bins, cap);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SFT_OK : mfail(SFT_E_DEVICE, hipGetErrorString(e));
+}
+
+hipStream_t sft_mlp_stream(sft_mlp_t m) { return m->stream; }
+
+extern "C" {
+
+sft_status sft_mlp_create(sft_mlp_t* out, uint64_t seed, void* hip_stream) {
+    if (!out) return mfail(SFT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    sft_mlp_s* m = new sft_mlp_s();
+    m->stream = (hipStream_t)hip_stream;
+    bool ok = hipMalloc(&m->theta, kNParams * sizeof(float)) == hipSuccess &&
+              hipMalloc(&m->grad, kNParams * sizeof(float)) == hipSuccess &&
+              hipMalloc(&m->m1, kNParams * sizeof(float)) == hipSuccess &&
+              hipMalloc(&m->m2, kNParams * sizeof(float)) == hipSuccess &&
+              hipMalloc(&m->wimg, kWElems * sizeof(bf16)) == hipSuccess &&
+              hipMalloc(&m->scratch_loss, sizeof(float)) == hipSuccess;
+    if (!ok) {
+        sft_mlp_destroy(m);
+        return mfail(SFT_E_NOMEM, "hipMalloc failed");
+    }
+    // uniform initialisation, bound sqrt(6 / fan_in) (He uniform), biases 0
+    std::vector<float> th((size_t)kNParams, 0.0f);
+    uint64_t st = seed ^ 0x6a09e667f3bcc909ull;
+    auto next = [&st]() {
+        uint64_t z = (st += 0x9e3779b97f4a7c15ull);
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        z ^= z >> 31;
+        return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+    };
+    auto fill = [&](int off, int count, int fan_in) {
+        const double bound = std::sqrt(6.0 / fan_in);
+        for (int i = 0; i < count; ++i) th[(size_t)(off + i)] = (float)((2.0 * next() - 1.0) * bound);
+    };
+    fill(kOffW1, kNH * kNF, kNF);
+    fill(kOffW2, kNH * kNH, kNH);
+    fill(kOffW3, kNC * kNH, kNH);
+    sft_status s = upload(m, th);
+    if (s != SFT_OK) {
+        sft_mlp_destroy(m);
+        return s;
+    }
+    *out = m;
+    return SFT_OK;
+}
+
+void sft_mlp_destroy(sft_mlp_t m) {
+    if (!m) return;
+    (void)hipStreamSynchronize(m->stream);
+    if (m->theta) (void)hipFree(m->theta);
+    if (m->grad) (void)hipFree(m->grad);
+    if (m->m1) (void)hipFree(m->m1);
+    if (m->m2) (void)hipFree(m->m2);
+    if (m->wimg) (void)hipFree(m->wimg);
+    if (m->scratch_loss) (void)hipFree(m->scratch_loss);
+    delete m;
+}
+
+sft_status sft_mlp_get_params(sft_mlp_t m, float* host, int64_t n) {
+    if (!m || !host) return mfail(SFT_E_INVALID, "NULL argument");
+    if (n != kNParams) return mfail(SFT_E_INVALID, "need exactly SFT_MLP_PARAMS values");
+    MHIP(hipStreamSynchronize(m->stream));
+    MHIP(hipMemcpy(host, m->theta, kNParams * sizeof(float), hipMemcpyDeviceToHost));
+    return SFT_OK;
+}
+
+sft_status sft_mlp_set_params(sft_mlp_t m, const float* host, int64_t n) {
+    if (!m || !host) return mfail(SFT_E_INVALID, "NULL argument");
+    if (n != kNParams) return mfail(SFT_E_INVALID, "need exactly SFT_MLP_PARAMS values");
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(host[i])) return mfail(SFT_E_INVALID, "non-finite parameter");
+    MHIP(hipStreamSynchronize(m->stream));
+    return upload(m, std::vector<float>(host, host + n));
+}
+
+sft_status sft_mlp_forward(sft_mlp_t m, const float* feat_dev, int64_t rows, float* logits_dev) {
+    if (!m || !feat_dev || !logits_dev || rows < 0) return mfail(SFT_E_INVALID, "bad argument");
+    if (rows > (int64_t(1) << 30)) return mfail(SFT_E_UNSUPPORTED, "too many rows");
+    if (rows == 0) return SFT_OK;
+    hipLaunchKernelGGL(forward_kernel, dim3(grid_for(rows)), dim3(256), 0, m->stream, feat_dev, (int)rows, m->wimg,
+                       m->theta, logits_dev);
+    MHIP(hipGetLastError());
+    return SFT_OK;
+}
+
+sft_status sft_mlp_grad(sft_mlp_t m, const float* feat_dev, const int32_t* labels_dev, int64_t rows, float* grad_dev,
+                        float* loss_dev) {
+    if (!m || !feat_dev || !labels_dev || !grad_dev || !loss_dev || rows < 1)
+        return mfail(SFT_E_INVALID, "bad argument");
+    if (rows > (int64_t(1) << 30)) return mfail(SFT_E_UNSUPPORTED, "too many rows");
+    hipLaunchKernelGGL(zero_kernel, dim3((kNParams + 255) / 256), dim3(256), 0, m->stream, grad_dev, kNParams);
+    hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(256), 0, m->stream, loss_dev, 1);
+    hipLaunchKernelGGL(grad_kernel, dim3(grid_for(rows)), dim3(256), 0, m->stream, feat_dev, labels_dev, (int)rows,
+                       m->wimg, m->theta, grad_dev, loss_dev);
+    MHIP(hipGetLastError());
+    return SFT_OK;
+}
+
+sft_status sft_mlp_train_step(sft_mlp_t m, const float* feat_dev, const int32_t* labels_dev, int64_t rows, float lr,
+                              float* loss_dev) {
+    if (!m || !feat_dev || !labels_dev || rows < 1 || !(lr > 0.0f)) return mfail(SFT_E_INVALID, "bad argument");
+    if (rows > (int64_t(1) << 30)) return mfail(SFT_E_UNSUPPORTED, "too many rows");
+    float* loss = loss_dev ? loss_dev : m->scratch_loss;
+    hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(256), 0, m->stream, loss, 1);
+    hipLaunchKernelGGL(grad_kernel, dim3(grid_for(rows)), dim3(256), 0, m->stream, feat_dev, labels_dev, (int)rows,
+                       m->wimg, m->theta, m->grad, loss);
+    MHIP(hipGetLastError());
+    m->step += 1;
+    const float b1c = 1.0f - std::pow(0.9f, (float)m->step);
+    const float b2c = 1.0f - std::pow(0.999f, (float)m->step);
+    hipLaunchKernelGGL(adam_kernel, dim3((kNParams + 255) / 256), dim3(256), 0, m->stream, m->theta, m->grad, m->m1,
+                       m->m2, m->wimg, lr, b1c, b2c);
+    MHIP(hipGetLastError());
+    return SFT_OK;
+}
+
+const char* sft_mlp_last_error(void) { return g_mlp_err.c_str(); }
+
+}  // extern "C"

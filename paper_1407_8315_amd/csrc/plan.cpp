@@ -79,8 +79,8 @@ sft_status resolve_params(const sft_params& in, bool batch, SigHost* g, std::str
         *msg = "unknown flag bits";
         return SFT_E_INVALID;
     }
-    if ((in.flags & SFT_FLAG_LEARNED) && in.mode != SFT_MODE_EXACT) {
-        *msg = "the learned order predictor applies to SFT_MODE_EXACT";
+    if ((in.flags & SFT_FLAG_LEARNED) && (in.mode != SFT_MODE_EXACT || !(in.l == 0 || in.l == 4))) {
+        *msg = "the learned order predictor applies to SFT_MODE_EXACT with L = 4";
         return SFT_E_UNSUPPORTED;
     }
     g->n = in.n;

@@ -55,11 +55,7 @@ void omega_table(int log2n, std::vector<double2>* out);         // e^{+2 pi i q 
 
 }  // namespace sft
 
-// Enqueue the path of a plan (learned orders first when a predictor is attached).
-sft_status sft_enqueue_learned(sft_plan_t plan, hipEvent_t* events);
-// Learned mode: run the predictor over the plan's bins and return the order array.
-sft_status sft_mlp_enqueue_orders(sft_plan_t plan, const signed char** orders);
-// Plan accessors for other translation units.
-sft_mlp_t& sft_plan_mlp_slot(sft_plan_t plan);
-signed char* sft_plan_orders(sft_plan_t plan);
-sft::LaunchCtx sft_plan_ctx(sft_plan_t plan);
+// Learned mode: run the predictor over the active list, writing per-bin orders.
+sft_status sft_mlp_launch_infer(sft_mlp_t mlp, const sft::LaunchCtx& c, signed char* orders);
+// Features of the active bins (training data) and their count.
+sft_status sft_features_enqueue(const sft::LaunchCtx& c, float* feat, int64_t* bins, int64_t cap, int64_t* count);

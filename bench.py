@@ -42,7 +42,62 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for counter calibration)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain comparison")
     return ap.parse_args()
+
+
+WEIGHTS = os.path.join(ROOT, "paper_1407_8315_amd", "data", "order_mlp.npy")
+
+
+def learned_vs_plain(steps, warmup, B=1024):
+    """Exact-input batch (N = 2^20, K = 1000, M = 4096, L = 4), plain rank-test
+    order estimate against the learned predictor (trained weights shipped in
+    paper_1407_8315_amd/data), same signals, graph-replayed steps."""
+    import numpy as np
+    import torch
+
+    import sftgen
+    from paper_1407_8315_amd import SFT_FLAG_LEARNED, Mlp, Plan
+
+    if not os.path.exists(WEIGHTS):
+        return None
+    n, k, m, L = 1 << 20, 1000, 4096, 4
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.Stream(device=dev)
+    out = {}
+    with torch.cuda.stream(stream):
+        xs, truth = [], []
+        for i in range(B):
+            x, locs, _ = sftgen.torch_signal(n, k, sftgen.BASE_SEED + 20000 + i, dev, amp="unit")
+            xs.append(x)
+            truth.append(locs)
+        net = Mlp(seed=0, stream=stream)
+        net.load(WEIGHTS)
+        for name, flags in (("plain", 0), ("learned", SFT_FLAG_LEARNED)):
+            plan = Plan([dict(n=n, k=k, m=m, l=L, flags=flags)] * B, stream=stream)
+            if flags:
+                plan.attach(net)
+            outs = [plan.new_output(m * L, dev) for _ in range(B)]
+            for _ in range(warmup):
+                plan.batch(xs, outs)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                plan.batch(xs, outs)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            found = sum(len(np.intersect1d(o.loc[:int(o.count.item())].cpu().numpy(), t)) for o, t in zip(outs, truth))
+            st = plan.batch(xs, outs, stats=True)[0].stats
+            out[name] = {"ms_per_step": round(ms, 4), "signals_per_s": round(B / ms * 1e3, 1),
+                         "freqs_per_s": round(found / ms * 1e3, 1), "support_recovery": round(found / (B * k), 5),
+                         "stage_ms": [round(v, 4) for v in st["stage_ms"]], "mlp_fallbacks": st["mlp_fallbacks"],
+                         "active_bins": st["active_bins"]}
+            plan.close()
+        net.close()
+    out["speedup_learned_over_plain"] = round(out["plain"]["ms_per_step"] / out["learned"]["ms_per_step"], 4)
+    out["workload"] = f"exact, N=2^20, K=1000, M=4096, L=4, unit amplitudes, complex64, batch {B}"
+    return out
 
 
 def main():
@@ -129,6 +184,9 @@ def main():
     if not a.no_cpu:
         cpu = cpu_baseline(n, k, m, L, R, mode, plan, a.cpu_seconds, snrs)
     plan.close()
+    del xs, outs
+    torch.cuda.empty_cache()
+    lvp = None if a.no_learned else learned_vs_plain(a.steps, a.warmup)
     out = {
         "metric": "recovered freqs/s at N=2^20, K=1000 (general mode, SNR 10/20/30/40 dB)"
         if mode == "general" else "recovered freqs/s at N=2^20, K=1000 (exact mode)",
@@ -144,6 +202,7 @@ def main():
         "stats_last_step": {kk: v for kk, v in st.items() if kk != "stage_ms"} if st else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "learned_vs_plain": lvp,
         "input_generation_s": round(gen_s, 2),
     }
     print(json.dumps(out))

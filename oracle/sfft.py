@@ -66,10 +66,13 @@ def syndromes(x, n: int, m: int, shifts, fft_dtype=np.complex128) -> np.ndarray:
     d; Alg. 2, Part 1, for the random shifts n_j.  Indices wrap mod N, which
     only matters when d < 2L.  Returns an array [len(shifts), M] in FP64.
 
-    fft_dtype=np.complex64 runs the FFTs in single precision (the precision
-    of the fast path for complex64 input), so that decisions which depend on
-    that precision (e.g. clusters whose smallest Hankel singular value is
-    below single-precision resolution) are taken at the same precision.
+    fft_dtype=np.complex64 returns the transforms rounded to single
+    precision (numpy evaluates them more accurately than single-precision
+    arithmetic would), i.e. the syndromes a correctly rounded single-precision
+    FFT would store, so that decisions which depend on that resolution (e.g.
+    clusters whose smallest Hankel singular value is below it) are taken at
+    the same resolution.  A single-precision FFT adds its own rounding error,
+    about u sqrt(log2 M) of the line's rms, on top of this.
     """
     x = np.asarray(x).astype(fft_dtype)
     if n % m:

@@ -56,6 +56,10 @@ struct sft_plan_s {
     void* d_tw = nullptr;
     double2* d_om = nullptr;
     int4* d_synd_items = nullptr;
+    int4* d_synd2_items = nullptr;
+    int2* d_line_items = nullptr;
+    void* d_ybuf = nullptr;
+    int n_synd2_items = 0, n_line_items = 0;
     int2* d_bin_items = nullptr;
     int2* d_out_items = nullptr;
     int2* d_act_items = nullptr;
@@ -132,6 +136,11 @@ LaunchCtx make_ctx(const sft_plan_s* p) {
     c.om_log2 = p->om_log2;
     c.synd_items = p->d_synd_items;
     c.n_synd_items = p->n_synd_items;
+    c.synd2_items = p->d_synd2_items;
+    c.n_synd2_items = p->n_synd2_items;
+    c.ybuf = p->d_ybuf;
+    c.line_items = p->d_line_items;
+    c.n_line_items = p->n_line_items;
     c.bin_items = p->d_bin_items;
     c.n_bin_items = p->n_bin_items;
     c.out_items = p->d_out_items;
@@ -308,6 +317,8 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     p->tw_log2 = lay.tw_log2;
     p->om_log2 = lay.om_log2;
     p->n_synd_items = (int)lay.synd_items.size();
+    p->n_synd2_items = (int)lay.synd2_items.size();
+    p->n_line_items = (int)lay.line_items.size();
     p->n_bin_items = (int)lay.bin_items.size();
     p->n_out_items = (int)lay.out_items.size();
     p->n_act_items = (int)lay.act_items.size();
@@ -328,6 +339,9 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
         double2* t = nullptr;
         TRY(dalloc(p, &t, (size_t)lay.synd_elems));
         p->d_synd = t;
+        double2* yb = nullptr;
+        TRY(dalloc(p, &yb, (size_t)lay.y_elems));
+        p->d_ybuf = yb;
         double2* tw = nullptr;
         TRY(dalloc(p, &tw, (size_t)1 << lay.tw_log2));
         p->d_tw = tw;
@@ -335,6 +349,9 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
         float2* t = nullptr;
         TRY(dalloc(p, &t, (size_t)lay.synd_elems));
         p->d_synd = t;
+        float2* yb = nullptr;
+        TRY(dalloc(p, &yb, (size_t)lay.y_elems));
+        p->d_ybuf = yb;
         float2* tw = nullptr;
         TRY(dalloc(p, &tw, (size_t)1 << lay.tw_log2));
         p->d_tw = tw;
@@ -350,6 +367,8 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     TRY(dalloc(p, &p->d_shifts, lay.shifts.size()));
     TRY(dalloc(p, &p->d_om, (size_t)1 << lay.om_log2));
     TRY(dalloc(p, &p->d_synd_items, lay.synd_items.size()));
+    TRY(dalloc(p, &p->d_synd2_items, lay.synd2_items.size()));
+    TRY(dalloc(p, &p->d_line_items, lay.line_items.size()));
     TRY(dalloc(p, &p->d_bin_items, lay.bin_items.size()));
     TRY(dalloc(p, &p->d_out_items, lay.out_items.size()));
     TRY(dalloc(p, &p->d_act_items, lay.act_items.size()));
@@ -391,6 +410,12 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
         HIPTRY(hipMemcpy(p->d_om, om.data(), om.size() * sizeof(double2), hipMemcpyHostToDevice));
     }
     HIPTRY(hipMemcpy(p->d_synd_items, lay.synd_items.data(), lay.synd_items.size() * sizeof(int4), hipMemcpyHostToDevice));
+    if (!lay.synd2_items.empty())
+        HIPTRY(hipMemcpy(p->d_synd2_items, lay.synd2_items.data(), lay.synd2_items.size() * sizeof(int4),
+                         hipMemcpyHostToDevice));
+    if (!lay.line_items.empty())
+        HIPTRY(hipMemcpy(p->d_line_items, lay.line_items.data(), lay.line_items.size() * sizeof(int2),
+                         hipMemcpyHostToDevice));
     HIPTRY(hipMemcpy(p->d_bin_items, lay.bin_items.data(), lay.bin_items.size() * sizeof(int2), hipMemcpyHostToDevice));
     HIPTRY(hipMemcpy(p->d_out_items, lay.out_items.data(), lay.out_items.size() * sizeof(int2), hipMemcpyHostToDevice));
     HIPTRY(hipMemcpy(p->d_act_items, lay.act_items.data(), lay.act_items.size() * sizeof(int2), hipMemcpyHostToDevice));

@@ -41,7 +41,8 @@ struct SigDev {
     int32_t stage_cap;       // = M * L
     int32_t shift_off;       // offset of the S shift values in the shift table
     int32_t tab_stride;      // omega table stride: w_d^q = tab[q * tab_stride]
-    int32_t pad0;
+    int32_t log2m1;          // two-pass FFT (M above one block): M = M1 * M2, log2 M1 (0: one pass)
+    int64_t y_off;           // two-pass FFT: offset of the [S][M2][M1] intermediate
     double tau_zero2, tau_rank, tau_res2, tau_amp, c_res, delta_grid, delta_mag;
 };
 
@@ -139,8 +140,13 @@ struct LaunchCtx {
     int tw_log2;
     const double2* omega;    // e^{+2 pi i q / 2^om_log2}, FP64
     int om_log2;
-    const int4* synd_items;  // (sig, line0, nlines, 0)
+    const int4* synd_items;  // (sig, line0, nlines, pass): pass 0 one-pass, 1 first of two
     int n_synd_items;
+    const int4* synd2_items; // second pass of two-pass signals (pass 2)
+    int n_synd2_items;
+    void* ybuf;              // two-pass intermediate (float2* / double2*)
+    const int2* line_items;  // (sig, line) of two-pass signals, for the line energies
+    int n_line_items;
     const int2* bin_items;   // (sig, bin0): tiles of kBlock bins
     int n_bin_items;
     const int2* out_items;   // (sig, entry0): tiles of kBlock staging entries

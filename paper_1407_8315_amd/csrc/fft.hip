@@ -130,74 +130,149 @@ __device__ inline void stockham_pass(typename C2<T>::type* buf, int log2m, int n
     __syncthreads();
 }
 
+// One block = `nl` lines of one signal held in LDS, transformed in place.
+// pass 0 (M fits one block): line = shift s, gathered from x at stride d,
+//   output m_s[k] = d * X[k] -> syndromes [s][k], plus the line energy.
+// pass 1 (first of two, M = M1 * M2): line = (s, n1), the M2 samples
+//   x[(d (n1 + M1 n2) + shift_s) mod N]; output Y[s][k2][n1] = X[k2] w_M^{-n1 k2}.
+// pass 2: line = (s, k2), the M1 values Y[s][k2][.]; output
+//   m_s[k2 + M2 k1] = d * X[k1] -> syndromes.
 template <typename T, int PMAX>
 __global__ __launch_bounds__(kBlock) void syndrome_kernel(const SigDev* __restrict__ sigs, const IoDev* __restrict__ io,
                                                           const int4* __restrict__ items, const int64_t* __restrict__ shifts,
                                                           const typename C2<T>::type* __restrict__ tw, int tw_log2,
                                                           typename C2<T>::type* __restrict__ synd,
+                                                          typename C2<T>::type* __restrict__ ybuf,
                                                           double* __restrict__ epart, SigCounters* __restrict__ cnt) {
     using V = typename C2<T>::type;
     __shared__ V buf[PMAX];
     __shared__ double red[kBlock];
     const int4 it = items[blockIdx.x];
     if (it.x < 0) return;   // padding item
-    const int s = it.x, line0 = it.y, nl = it.z;
+    const int s = it.x, line0 = it.y, nl = it.z, pass = it.w;
     const SigDev sg = sigs[s];
     const V* __restrict__ x = reinterpret_cast<const V*>(io[s].x);
     const int log2m = sg.log2m;
-    const int mmask = (1 << log2m) - 1;
+    const int log2m1 = sg.log2m1, log2m2 = log2m - log2m1;
+    const int log2len = pass == 0 ? log2m : (pass == 1 ? log2m2 : log2m1);
+    const int len = 1 << log2len;
     const int64_t nmask = sg.n - 1;
-    const int64_t* sh = shifts + sg.shift_off + line0;
+    const int64_t* sh = shifts + sg.shift_off;
 
-    // gather: point p -> (line = p % nl, k' = p / nl), stored line-major
+    // gather into LDS, line-major [line][j]
     int bad = 0;
-    const int P = nl << log2m;
-    for (int p = threadIdx.x; p < P; p += kBlock) {
-        int line = p % nl, kp = p / nl;
-        int64_t idx = (sg.d * (int64_t)kp + sh[line]) & nmask;
-        V v = x[idx];
-        if (sg.flags & 4) bad += !(isfinite(v.x) && isfinite(v.y));
-        buf[(line << log2m) + kp] = v;
-    }
-    if (sg.flags & 4) {
-        if (bad) atomicAdd(&cnt[s].nonfinite, bad);
+    const int P = nl << log2len;
+    if (pass == 2) {
+        // contiguous rows of the intermediate: position fastest
+        const V* y = ybuf + sg.y_off;
+        for (int p = threadIdx.x; p < P; p += kBlock) {
+            const int line = p >> log2len, j = p & (len - 1);
+            buf[p] = y[((int64_t)(line0 + line) << log2m1) + j];
+        }
+    } else {
+        // strided samples of x: line fastest, so consecutive shifts read adjacent samples
+        for (int p = threadIdx.x; p < P; p += kBlock) {
+            const int line = p % nl, j = p / nl;
+            const int g = line0 + line;
+            int64_t idx;
+            if (pass == 0) {
+                idx = (sg.d * (int64_t)j + sh[g]) & nmask;
+            } else {
+                const int l = g >> log2m1, n1 = g & ((1 << log2m1) - 1);
+                idx = (sg.d * ((int64_t)n1 + ((int64_t)j << log2m1)) + sh[l]) & nmask;
+            }
+            V v = x[idx];
+            if (sg.flags & 4) bad += !(isfinite(v.x) && isfinite(v.y));
+            buf[(line << log2len) + j] = v;
+        }
+        if ((sg.flags & 4) && bad) atomicAdd(&cnt[s].nonfinite, bad);
     }
     __syncthreads();
 
     // Stockham passes: radix 16 while >= 4 bits remain, then 8, 4 or 2
     int log2ns = 0;
-    while (log2m - log2ns >= 4) {
-        stockham_pass<T, 16, PMAX>(buf, log2m, nl, log2ns, tw, tw_log2);
+    while (log2len - log2ns >= 4) {
+        stockham_pass<T, 16, PMAX>(buf, log2len, nl, log2ns, tw, tw_log2);
         log2ns += 4;
     }
-    switch (log2m - log2ns) {
-        case 3: stockham_pass<T, 8, PMAX>(buf, log2m, nl, log2ns, tw, tw_log2); break;
-        case 2: stockham_pass<T, 4, PMAX>(buf, log2m, nl, log2ns, tw, tw_log2); break;
-        case 1: stockham_pass<T, 2, PMAX>(buf, log2m, nl, log2ns, tw, tw_log2); break;
+    switch (log2len - log2ns) {
+        case 3: stockham_pass<T, 8, PMAX>(buf, log2len, nl, log2ns, tw, tw_log2); break;
+        case 2: stockham_pass<T, 4, PMAX>(buf, log2len, nl, log2ns, tw, tw_log2); break;
+        case 1: stockham_pass<T, 2, PMAX>(buf, log2len, nl, log2ns, tw, tw_log2); break;
         default: break;
     }
 
-    // epilogue: scale by d, store shift-major, per-line energy (FP64, fixed-order tree)
     const T dscale = (T)sg.d;
-    V* out = synd + sg.synd_off + ((int64_t)line0 << log2m);
-    for (int line = 0; line < nl; ++line) {
-        double acc = 0.0;
-        for (int k = threadIdx.x; k <= mmask; k += kBlock) {
-            V v = buf[(line << log2m) + k];
-            v.x *= dscale;
-            v.y *= dscale;
-            out[((int64_t)line << log2m) + k] = v;
-            acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
-        }
-        red[threadIdx.x] = acc;
-        __syncthreads();
-        for (int w = kBlock / 2; w > 0; w >>= 1) {
-            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if (pass == 0) {
+        // scale by d, store shift-major, per-line energy (FP64, fixed-order tree)
+        V* out = synd + sg.synd_off + ((int64_t)line0 << log2m);
+        for (int line = 0; line < nl; ++line) {
+            double acc = 0.0;
+            for (int k = threadIdx.x; k < len; k += kBlock) {
+                V v = buf[(line << log2m) + k];
+                v.x *= dscale;
+                v.y *= dscale;
+                out[((int64_t)line << log2m) + k] = v;
+                acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+            }
+            red[threadIdx.x] = acc;
+            __syncthreads();
+            for (int w = kBlock / 2; w > 0; w >>= 1) {
+                if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) epart[sg.epart_off + line0 + line] = red[0];
             __syncthreads();
         }
-        if (threadIdx.x == 0) epart[sg.epart_off + line0 + line] = red[0];
+    } else if (pass == 1) {
+        // twiddle w_M^{-n1 k2}, store Y[l][k2][n1] (lines = consecutive n1: contiguous)
+        V* y = ybuf + sg.y_off;
+        const int mtw = tw_log2 - log2m;
+        for (int q = threadIdx.x; q < P; q += kBlock) {
+            const int line = q % nl, k2 = q / nl;
+            const int g = line0 + line;
+            const int l = g >> log2m1, n1 = g & ((1 << log2m1) - 1);
+            V v = buf[(line << log2len) + k2];
+            const int64_t e = ((int64_t)n1 * k2) & ((1ll << log2m) - 1);
+            v = cmulv(v, tw[e << mtw]);
+            y[((((int64_t)l << log2m2) + k2) << log2m1) + n1] = v;
+        }
+    } else {
+        // m_l[k2 + M2 k1] = d X[k1] (lines = consecutive k2: contiguous)
+        for (int q = threadIdx.x; q < P; q += kBlock) {
+            const int line = q % nl, k1 = q / nl;
+            const int g = line0 + line;
+            const int l = g >> log2m2, k2 = g & ((1 << log2m2) - 1);
+            V v = buf[(line << log2len) + k1];
+            v.x *= dscale;
+            v.y *= dscale;
+            synd[sg.synd_off + ((int64_t)l << log2m) + k2 + ((int64_t)k1 << log2m2)] = v;
+        }
+    }
+}
+
+// Line energies of two-pass signals: one block per (signal, line), fixed-order
+// FP64 reduction (the one-pass kernel computes them in its epilogue).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void line_energy_kernel(const SigDev* __restrict__ sigs, const int2* __restrict__ items,
+                                                             const typename C2<T>::type* __restrict__ synd,
+                                                             double* __restrict__ epart) {
+    __shared__ double red[kBlock];
+    const int2 it = items[blockIdx.x];
+    const SigDev& sg = sigs[it.x];
+    const typename C2<T>::type* row = synd + sg.synd_off + ((int64_t)it.y << sg.log2m);
+    double acc = 0.0;
+    for (int64_t k = threadIdx.x; k < sg.m; k += kBlock) {
+        auto v = row[k];
+        acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
+    if (threadIdx.x == 0) epart[sg.epart_off + it.y] = red[0];
 }
 
 __global__ void zero_counters_kernel(SigCounters* cnt, int n, WorkCounters* work) {
@@ -213,15 +288,30 @@ hipError_t launch_zero_counters(const LaunchCtx& c) {
 }
 
 hipError_t launch_syndromes(const LaunchCtx& c) {
-    if (c.n_synd_items == 0) return hipSuccess;
     if (c.fp64) {
-        hipLaunchKernelGGL((syndrome_kernel<double, kFftPointsF64>), dim3(c.n_synd_items), dim3(kBlock), 0, c.stream,
-                           c.sigs, c.io, c.synd_items, c.shifts, (const double2*)c.twiddle, c.tw_log2,
-                           (double2*)c.synd, c.epart, c.cnt);
+        if (c.n_synd_items)
+            hipLaunchKernelGGL((syndrome_kernel<double, kFftPointsF64>), dim3(c.n_synd_items), dim3(kBlock), 0, c.stream,
+                               c.sigs, c.io, c.synd_items, c.shifts, (const double2*)c.twiddle, c.tw_log2,
+                               (double2*)c.synd, (double2*)c.ybuf, c.epart, c.cnt);
+        if (c.n_synd2_items)
+            hipLaunchKernelGGL((syndrome_kernel<double, kFftPointsF64>), dim3(c.n_synd2_items), dim3(kBlock), 0,
+                               c.stream, c.sigs, c.io, c.synd2_items, c.shifts, (const double2*)c.twiddle, c.tw_log2,
+                               (double2*)c.synd, (double2*)c.ybuf, c.epart, c.cnt);
+        if (c.n_line_items)
+            hipLaunchKernelGGL(line_energy_kernel<double>, dim3(c.n_line_items), dim3(kBlock), 0, c.stream, c.sigs,
+                               c.line_items, (const double2*)c.synd, c.epart);
     } else {
-        hipLaunchKernelGGL((syndrome_kernel<float, kFftPointsF32>), dim3(c.n_synd_items), dim3(kBlock), 0, c.stream,
-                           c.sigs, c.io, c.synd_items, c.shifts, (const float2*)c.twiddle, c.tw_log2,
-                           (float2*)c.synd, c.epart, c.cnt);
+        if (c.n_synd_items)
+            hipLaunchKernelGGL((syndrome_kernel<float, kFftPointsF32>), dim3(c.n_synd_items), dim3(kBlock), 0, c.stream,
+                               c.sigs, c.io, c.synd_items, c.shifts, (const float2*)c.twiddle, c.tw_log2,
+                               (float2*)c.synd, (float2*)c.ybuf, c.epart, c.cnt);
+        if (c.n_synd2_items)
+            hipLaunchKernelGGL((syndrome_kernel<float, kFftPointsF32>), dim3(c.n_synd2_items), dim3(kBlock), 0,
+                               c.stream, c.sigs, c.io, c.synd2_items, c.shifts, (const float2*)c.twiddle, c.tw_log2,
+                               (float2*)c.synd, (float2*)c.ybuf, c.epart, c.cnt);
+        if (c.n_line_items)
+            hipLaunchKernelGGL(line_energy_kernel<float>, dim3(c.n_line_items), dim3(kBlock), 0, c.stream, c.sigs,
+                               c.line_items, (const float2*)c.synd, c.epart);
     }
     return hipGetLastError();
 }

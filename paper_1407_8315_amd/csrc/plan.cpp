@@ -29,7 +29,14 @@ constexpr int64_t kMaxD = int64_t(1) << 22;   // omega table bound
 
 }  // namespace
 
-int64_t max_m(int dtype) { return dtype == SFT_C128 ? kFftPointsF64 : kFftPointsF32; }
+// M up to one block's LDS runs as one FFT pass; above that, as two passes of
+// M1 x M2 (each at most one block), up to 2^22.
+int64_t max_m(int dtype) {
+    (void)dtype;
+    return int64_t(1) << 22;
+}
+
+int64_t one_pass_m(int dtype) { return dtype == SFT_C128 ? kFftPointsF64 : kFftPointsF32; }
 
 int64_t default_m(int64_t n, int64_t k, int dtype) {
     int64_t m = 1;
@@ -184,7 +191,7 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
         for (auto& v : lane_sigs) std::sort(v.begin(), v.end());
     }
 
-    int64_t synd = 0, ep = 0, bins = 0, stage = 0;
+    int64_t synd = 0, ep = 0, bins = 0, stage = 0, ybuf = 0;
     lay->sigdev.resize(sigs.size());
     for (size_t i = 0; i < sigs.size(); ++i) {
         const SigHost& g = sigs[i];
@@ -207,6 +214,9 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
         s.stage_cap = (int32_t)(g.m * g.L);
         s.shift_off = (int32_t)lay->shifts.size();
         s.tab_stride = (int32_t)(dmax / g.d);
+        s.log2m1 = g.m > pmax ? (ilog2(g.m) + 1) / 2 : 0;   // M1 = 2^ceil(log2 M / 2)
+        s.y_off = ybuf;
+        if (g.m > pmax) ybuf += (int64_t)g.S * g.m;
         s.tau_zero2 = g.tau_zero * g.tau_zero;
         s.tau_rank = g.tau_rank;
         s.tau_res2 = g.tau_res * g.tau_res;
@@ -227,6 +237,7 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
     lay->bin_elems = bins;
     lay->sigma_elems = bins * kMaxL;
     lay->stage_elems = stage;
+    lay->y_elems = ybuf;
     lay->n_general = (int)lay->general_sigs.size();
 
     // Work items per lane, then interleaved so that item id % 8 == lane: the
@@ -255,10 +266,32 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
     interleave(
         [&](int s, std::vector<int4>& v) {
             const SigHost& g = sigs[s];
-            int nl = (int)std::max<int64_t>(1, std::min<int64_t>(g.S, pmax / g.m));
-            for (int l0 = 0; l0 < g.S; l0 += nl) v.push_back(int4{s, l0, std::min(nl, g.S - l0), 0});
+            if (g.m <= pmax) {
+                int nl = (int)std::max<int64_t>(1, std::min<int64_t>(g.S, pmax / g.m));
+                for (int l0 = 0; l0 < g.S; l0 += nl) v.push_back(int4{s, l0, std::min(nl, g.S - l0), 0});
+            } else {
+                // first of two passes: S * M1 lines of length M2
+                const int lm1 = lay->sigdev[s].log2m1, lm2 = ilog2(g.m) - lm1;
+                const int64_t lines = (int64_t)g.S << lm1;
+                const int nl = (int)std::min<int64_t>(lines, pmax >> lm2);
+                for (int64_t l0 = 0; l0 < lines; l0 += nl) v.push_back(int4{s, (int)l0, (int)std::min<int64_t>(nl, lines - l0), 1});
+            }
         },
         int4{-1, 0, 0, 0}, lay->synd_items);
+    interleave(
+        [&](int s, std::vector<int4>& v) {
+            const SigHost& g = sigs[s];
+            if (g.m <= pmax) return;
+            // second pass: S * M2 lines of length M1
+            const int lm1 = lay->sigdev[s].log2m1, lm2 = ilog2(g.m) - lm1;
+            const int64_t lines = (int64_t)g.S << lm2;
+            const int nl = (int)std::min<int64_t>(lines, pmax >> lm1);
+            for (int64_t l0 = 0; l0 < lines; l0 += nl) v.push_back(int4{s, (int)l0, (int)std::min<int64_t>(nl, lines - l0), 2});
+        },
+        int4{-1, 0, 0, 0}, lay->synd2_items);
+    for (size_t s = 0; s < sigs.size(); ++s)
+        if (sigs[s].m > pmax)
+            for (int l = 0; l < sigs[s].S; ++l) lay->line_items.push_back(int2{(int)s, l});
     interleave(
         [&](int s, std::vector<int2>& v) {
             for (int64_t b = 0; b < sigs[s].m; b += kBlock) v.push_back(int2{s, (int)b});

@@ -24,18 +24,21 @@ struct SigHost {
 struct PlanLayout {
     std::vector<SigDev> sigdev;
     std::vector<int64_t> shifts;          // per signal: 0..2L-1, then n_j
-    std::vector<int4> synd_items;         // (sig, line0, nlines, 0); sig < 0 = padding
+    std::vector<int4> synd_items;         // (sig, line0, nlines, pass 0|1); sig < 0 = padding
+    std::vector<int4> synd2_items;        // (sig, line0, nlines, 2): second FFT pass
+    std::vector<int2> line_items;         // (sig, line) of two-pass signals
     std::vector<int2> bin_items;          // (sig, bin0)
     std::vector<int2> out_items;          // (sig, entry0)
     std::vector<int2> act_items;          // (sig, bin0), tiles of kActivityTile
     std::vector<int> general_sigs;
-    int64_t synd_elems = 0, epart_elems = 0, sigma_elems = 0, bin_elems = 0, stage_elems = 0;
+    int64_t synd_elems = 0, epart_elems = 0, sigma_elems = 0, bin_elems = 0, stage_elems = 0, y_elems = 0;
     int tw_log2 = 0, om_log2 = 0;
     int n_general = 0;
 };
 
-// Largest supported downsampled length per input type (one block's LDS).
+// Largest supported downsampled length, and the largest one-pass length.
 int64_t max_m(int dtype);
+int64_t one_pass_m(int dtype);
 
 // Fill defaults and validate one parameter set.
 sft_status resolve_params(const sft_params& in, bool batch, SigHost* out, std::string* msg);

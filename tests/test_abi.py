@@ -87,7 +87,7 @@ def _plan_status(lib, **kw):
     (dict(n=1 << 14, k=50, m=100), "SFT_E_UNSUPPORTED"),       # M not a power of two
     (dict(n=1 << 14, k=50, m=1 << 15), "SFT_E_UNSUPPORTED"),   # M does not divide N
     (dict(n=1 << 14, k=50, l=5), "SFT_E_UNSUPPORTED"),         # L outside 1..4
-    (dict(n=1 << 20, k=50, m=1 << 14), "SFT_E_UNSUPPORTED"),   # M above one block's LDS
+    (dict(n=1 << 24, k=50, m=1 << 23), "SFT_E_UNSUPPORTED"),   # M above 2^22
     (dict(n=1 << 14, k=50, r=3), "SFT_E_INVALID"),             # R in exact mode
     (dict(n=1 << 14, k=50, mode="general", r=40), "SFT_E_UNSUPPORTED"),
     (dict(n=1 << 14, k=50, flags=64), "SFT_E_INVALID"),        # unknown flag

@@ -81,10 +81,47 @@ __host__ __device__ inline int rank_order(const double* sv, int L, double tau_ra
     return a < 1 ? 1 : a;
 }
 
+// Exact shortcut of the rank test for bins of numerical rank one (most bins
+// hold one frequency), which then skip the Jacobi sweeps.  R_ij = mt_i mt_j /
+// mt_0 is a rank-one matrix, so sigma_2(H) <= ||H - R||_2 <= ||H - R||_F = dd
+// (Eckart-Young) and sigma_1(H) >= sigma_1(R) - ||H - R||_2 >= rr - dd with
+// rr = ||R||_F = ||R||_2.  dd (1 + tau) <= tau rr thus proves sigma_2 <=
+// tau sigma_1, i.e. the rank test gives a0 = 1.  The margins cover the
+// rounding of dd and rr and that of an SVD the decision is compared with.
+// True only when a0 = 1 is certain (an all-zero bin also has a0 = 1); false
+// means: run the SVD.
+__host__ __device__ __attribute__((always_inline)) inline bool rank_one_certified(const zd* mt, int L, double tau_rank) {
+    if (L == 1) return true;
+    const double n0 = norm2(mt[0]);
+    double e = 0.0;
+#pragma unroll
+    for (int l = 0; l < 2 * kMaxL - 1; ++l)
+        if (l <= 2 * L - 2) e += norm2(mt[l]);
+    if (e == 0.0) return true;
+    if (!(n0 > 0.0) || !__builtin_isfinite(e)) return false;
+    const zd inv0 = (1.0 / n0) * conj(mt[0]);
+    zd u[kMaxL];
+    double colsq = 0.0;
+#pragma unroll
+    for (int i = 0; i < kMaxL; ++i) {
+        u[i] = mt[i] * inv0;
+        if (i < L) colsq += norm2(mt[i]);
+    }
+    double dd2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < kMaxL; ++i)
+#pragma unroll
+        for (int j = 0; j < kMaxL; ++j)
+            if (i < L && j < L) dd2 += norm2(mt[i + j] - mt[i] * u[j]);
+    const double rr = colsq / sqrt(n0), dd = sqrt(dd2);
+    const double eps = 2.220446049250313e-16;
+    return __builtin_isfinite(rr) && dd * (1.0 + tau_rank) * (1.0 + 1e-9) + 64.0 * eps * rr <= tau_rank * rr;
+}
+
 // Step (i): solve sum_j c_j mt_{i+j} = -mt_{a+i}, i < a (Eq. (5)), by Gaussian
 // elimination with partial pivoting.  False when a pivot is zero or the
 // solution is not finite.
-__host__ __device__ inline bool locator(const zd* mt, int a, zd* c) {
+__host__ __device__ __attribute__((always_inline)) inline bool locator(const zd* mt, int a, zd* c) {
     // Register arrays are only indexed by unrolled constants (a runtime index
     // would send them to scratch memory): the right-hand side and the pivot
     // row swap are written as predicated selections.
@@ -144,7 +181,7 @@ __host__ __device__ inline bool locator(const zd* mt, int a, zd* c) {
 }
 
 // P(z) = z^a + sum_j c_j z^j and P'(z) by Horner.
-__host__ __device__ inline void poly_eval(const zd* c, int a, zd z, zd& p, zd& dp) {
+__host__ __device__ __attribute__((always_inline)) inline void poly_eval(const zd* c, int a, zd z, zd& p, zd& dp) {
     p = zd{1.0, 0.0};
     dp = zd{0.0, 0.0};
 #pragma unroll
@@ -160,7 +197,7 @@ __host__ __device__ inline void poly_eval(const zd* c, int a, zd z, zd& p, zd& d
 // its cancellation-free form.  a = 3, 4: Aberth-Ehrlich simultaneous
 // iterations from points spread on the unit circle (the roots of a decodable
 // bin lie on it).  False if an iteration does not converge.
-__host__ __device__ inline bool poly_roots(const zd* c, int a, zd* z) {
+__host__ __device__ __attribute__((always_inline)) inline bool poly_roots(const zd* c, int a, zd* z) {
     if (a == 1) {
         z[0] = -c[0];
         return cfinite(z[0]);
@@ -199,12 +236,18 @@ __host__ __device__ inline bool poly_roots(const zd* c, int a, zd* z) {
             zd p, dp;
             poly_eval(c, a, z[j], p, dp);
             if (norm2(p) == 0.0) continue;
-            zd ratio = cdiv(p, dp);
+            // Aberth correction (p/p') / (1 - (p/p') sum_k 1/(z_j - z_k)),
+            // written as p / (p' - p sum_k 1/(z_j - z_k)): one division per
+            // term (the magnitudes here stay far from overflow).
             zd sum{0.0, 0.0};
 #pragma unroll
             for (int k = 0; k < kMaxL; ++k)
-                if (k < a && k != j) sum = sum + cdiv(zd{1.0, 0.0}, z[j] - z[k]);
-            zd w = cdiv(ratio, zd{1.0, 0.0} - ratio * sum);
+                if (k < a && k != j) {
+                    const zd dz = z[j] - z[k];
+                    sum = sum + (1.0 / norm2(dz)) * conj(dz);
+                }
+            const zd den = dp - p * sum;
+            zd w = (1.0 / norm2(den)) * (p * conj(den));
             bad |= !cfinite(w);
             z[j] = z[j] - w;
             step = fmax(step, norm2(w));
@@ -219,7 +262,7 @@ __host__ __device__ inline bool poly_roots(const zd* c, int a, zd* z) {
 // Alg. 1 grid check on de-rotated roots: z_j must lie within delta_mag of the
 // unit circle and within delta_grid grid spacings of w_d^{t_j}; the t_j must be
 // distinct.  Writes t_j in [0, d).
-__host__ __device__ inline bool roots_to_grid(const zd* z, int a, int64_t d, double delta_grid, double delta_mag,
+__host__ __device__ __attribute__((always_inline)) inline bool roots_to_grid(const zd* z, int a, int64_t d, double delta_grid, double delta_mag,
                                      int64_t* t) {
     bool ok = true;
 #pragma unroll
@@ -243,7 +286,7 @@ __host__ __device__ inline bool roots_to_grid(const zd* z, int a, int64_t d, dou
 // Solve the Hermitian positive definite system G x = b (n <= NMAX) in place by
 // Cholesky on the packed lower triangle.  False when not positive definite.
 template <int NMAX>
-__host__ __device__ inline bool chol_solve(zd (&g)[NMAX * (NMAX + 1) / 2], zd* b, int n) {
+__host__ __device__ __attribute__((always_inline)) inline bool chol_solve(zd (&g)[NMAX * (NMAX + 1) / 2], zd* b, int n) {
     // g holds rows i >= j at index i*(i+1)/2 + j
 #pragma unroll
     for (int j = 0; j < NMAX; ++j) {
@@ -289,7 +332,7 @@ __host__ __device__ inline bool chol_solve(zd (&g)[NMAX * (NMAX + 1) / 2], zd* b
 }
 
 // w_d^q from the plan's FP64 table (q reduced mod d by the caller).
-__host__ __device__ inline zd omega(const double2* tab, int stride, int64_t q) {
+__host__ __device__ __attribute__((always_inline)) inline zd omega(const double2* tab, int stride, int64_t q) {
     double2 v = tab[q * stride];
     return zd{v.x, v.y};
 }
@@ -298,7 +341,7 @@ __host__ __device__ inline zd omega(const double2* tab, int stride, int64_t q) {
 // V_lj = w_j^l, w_j = w_d^{t_j}, by the normal equations; returns the residual
 // energy.  Columns are generated as running powers (rows <= 8 products each),
 // so V is never stored.  mt has 2 kMaxL entries (zero beyond `rows`).
-__host__ __device__ inline bool vandermonde_ls(const zd* mt, int rows, const int64_t* t, int a, int64_t d,
+__host__ __device__ __attribute__((always_inline)) inline bool vandermonde_ls(const zd* mt, int rows, const int64_t* t, int a, int64_t d,
                                       const double2* tab, int stride, zd* p, double& r2) {
     (void)d;
     zd w[kMaxL], pw[kMaxL];
@@ -315,6 +358,7 @@ __host__ __device__ inline bool vandermonde_ls(const zd* mt, int rows, const int
         if (l >= rows) break;
 #pragma unroll
         for (int j = 0; j < kMaxL; ++j) {
+            if (j >= a) continue;
             p[j] = p[j] + cmul_conj(pw[j], mt[l]);
             pw[j] = pw[j] * w[j];
         }
@@ -324,6 +368,7 @@ __host__ __device__ inline bool vandermonde_ls(const zd* mt, int rows, const int
     for (int i = 0; i < kMaxL; ++i)
 #pragma unroll
         for (int j = 0; j <= i; ++j) {
+            if (i >= a) continue;
             zd q = cmul_conj(w[i], w[j]), acc{0.0, 0.0}, pq{1.0, 0.0};
 #pragma unroll
             for (int l = 0; l < 2 * kMaxL; ++l) {
@@ -343,7 +388,8 @@ __host__ __device__ inline bool vandermonde_ls(const zd* mt, int rows, const int
         zd e = mt[l];
 #pragma unroll
         for (int j = 0; j < kMaxL; ++j) {
-            if (j < a) e = e - pw[j] * p[j];
+            if (j >= a) continue;
+            e = e - pw[j] * p[j];
             pw[j] = pw[j] * w[j];
         }
         r2 += norm2(e);

@@ -64,10 +64,10 @@ struct sft_plan_s {
     int2* d_out_items = nullptr;
     int2* d_act_items = nullptr;
     int* d_gsigs = nullptr;
-    signed char* d_orders = nullptr;
     WorkCounters* d_work = nullptr;
     int2* d_active = nullptr;
-    int2* d_cslist = nullptr;
+    int2* d_qlist = nullptr;
+    int max_l = 1;
     int64_t list_cap = 0;
     int n_work_blocks = 0;
     int n_synd_items = 0, n_bin_items = 0, n_out_items = 0, n_act_items = 0, n_general = 0;
@@ -149,12 +149,12 @@ LaunchCtx make_ctx(const sft_plan_s* p) {
     c.n_act_items = p->n_act_items;
     c.n_general = p->n_general;
     c.general_sigs = p->d_gsigs;
-    c.orders = nullptr;
     c.any_general = p->any_general ? 1 : 0;
+    c.max_l = p->max_l;
     c.keep = p->d_keep;
     c.work = p->d_work;
     c.active_list = p->d_active;
-    c.cs_list = p->d_cslist;
+    c.qlist = p->d_qlist;
     c.list_cap = p->list_cap;
     c.n_work_blocks = p->n_work_blocks;
     return c;
@@ -171,7 +171,7 @@ bool learned(const sft_plan_s* p) {
 sft_status enqueue(const sft_plan_s* p, hipEvent_t* events) {
     LaunchCtx c = make_ctx(p);
     const bool use_mlp = learned(p) && p->mlp;
-    c.orders = use_mlp ? p->d_orders : nullptr;
+    const bool any_exact = p->n_general < (int)p->sig.size();
     if (events) HIPCHK(hipEventRecord(events[0], p->stream));
     HIPCHK(launch_zero_counters(c));
     HIPCHK(launch_syndromes(c));
@@ -179,12 +179,25 @@ sft_status enqueue(const sft_plan_s* p, hipEvent_t* events) {
     HIPCHK(launch_singular_values(c));
     HIPCHK(launch_select(c));
     HIPCHK(launch_activity(c));
-    if (use_mlp) {
-        sft_status s = sft_mlp_launch_infer(p->mlp, c, p->d_orders);
-        if (s != SFT_OK) return s;
+    // Round-0 queues: general-mode bins come from the vote (activity pass);
+    // exact-mode bins from the rank test, or from the predictor with the rank
+    // test for the bins it gives no order.
+    if (any_exact) {
+        if (use_mlp) {
+            sft_status s = sft_mlp_launch_infer(p->mlp, c);
+            if (s != SFT_OK) return s;
+            HIPCHK(launch_rank(c, q_round(0, 0), 0, true));
+        } else {
+            HIPCHK(launch_rank(c, -1, 0, true));
+        }
     }
     if (events) HIPCHK(hipEventRecord(events[2], p->stream));
-    HIPCHK(launch_decode(c));
+    for (int r = 0; r < p->max_l; ++r) {
+        if (r >= 1) HIPCHK(launch_zero_set(c, (r + 1) & 1));
+        HIPCHK(launch_round(c, r));
+        // bins whose learned order failed: rank test, then on with round 1
+        if (r == 0 && use_mlp && p->max_l > 1) HIPCHK(launch_rank(c, q_round(1, 0), 1, false));
+    }
     HIPCHK(launch_cs(c));
     if (events) HIPCHK(hipEventRecord(events[3], p->stream));
     HIPCHK(launch_output(c));
@@ -373,11 +386,11 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     TRY(dalloc(p, &p->d_out_items, lay.out_items.size()));
     TRY(dalloc(p, &p->d_act_items, lay.act_items.size()));
     TRY(dalloc(p, &p->d_gsigs, lay.general_sigs.size()));
-    TRY(dalloc(p, &p->d_orders, (size_t)lay.bin_elems));
     TRY(dalloc(p, &p->d_work, 1));
     TRY(dalloc(p, &p->d_active, (size_t)lay.bin_elems));
-    TRY(dalloc(p, &p->d_cslist, lay.n_general ? (size_t)lay.bin_elems * kMaxL : 1));
+    TRY(dalloc(p, &p->d_qlist, (size_t)lay.bin_elems * kQueues));
     p->list_cap = lay.bin_elems;
+    for (auto& g : p->sig) p->max_l = std::max(p->max_l, g.L);
     {
         // grid of the list-driven kernels: enough blocks to fill every CU a few
         // times over, never more than the bins themselves need
@@ -421,7 +434,6 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     HIPTRY(hipMemcpy(p->d_act_items, lay.act_items.data(), lay.act_items.size() * sizeof(int2), hipMemcpyHostToDevice));
     if (!lay.general_sigs.empty())
         HIPTRY(hipMemcpy(p->d_gsigs, lay.general_sigs.data(), lay.general_sigs.size() * sizeof(int), hipMemcpyHostToDevice));
-    HIPTRY(hipMemset(p->d_orders, 0, (size_t)lay.bin_elems));
     HIPTRY(hipMemset(p->d_cnt, 0, ns * sizeof(SigCounters)));
     HIPTRY(hipHostMalloc((void**)&p->h_io, ns * sizeof(IoDev), hipHostMallocDefault));
     HIPTRY(hipHostMalloc((void**)&p->h_cnt, ns * sizeof(SigCounters), hipHostMallocDefault));

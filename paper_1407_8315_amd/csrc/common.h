@@ -59,20 +59,69 @@ struct SigCounters {
     int stage_count, active, flagged, cs, mlp_fb, nonfinite, kept, pad;
 };
 
-// Plan-wide work lists, rebuilt by every call: the active bins (decoder input)
-// and, per vote order a0 = 1..kMaxL, the flagged bins of the CS step.
-// Entries are (signal, k << 3 | a0).
+// Plan-wide work lists, rebuilt by every call.  The decoder runs in rounds:
+// round r tries the r-th hypothesis of every bin still open, with one kernel
+// per order a, so that each kernel carries the code of one order only.  Two
+// sets of round queues alternate (round r reads set r % 2 and fills set
+// (r + 1) % 2); slot 0 of a set holds bins waiting for the rank test, slot a
+// the bins whose next hypothesis has order a.  Flagged bins of general-mode
+// signals end in the CS queue of their vote order.  Besides these, the active
+// list holds the active bins of exact-mode signals (rank test or predictor
+// input).
+constexpr int kRoundSlots = kMaxL + 1;
+constexpr int kQueues = 2 * kRoundSlots + kMaxL;
+__host__ __device__ constexpr int q_round(int set, int slot) { return set * kRoundSlots + slot; }
+__host__ __device__ constexpr int q_cs(int a0) { return 2 * kRoundSlots + a0 - 1; }
+
 struct WorkCounters {
     int n_active;
-    int n_cs[kMaxL];
-    int pad[3];
+    int q[kQueues];   // lengths of the queues above
+    int pad[16 - 1 - kQueues];
 };
+
+// A list entry is (signal, code): code = k << 9 | step << 6 | ap << 3 | a0 with
+// bin k (< 2^22), index `step` of the bin's next hypothesis in its order
+// sequence, learned order ap (0: none) and rank-test or vote order a0 (0: not
+// known yet).  CS queue entries are (signal, k).
+__host__ __device__ inline int pack_code(int64_t k, int step, int ap, int a0) {
+    return (int)(k << 9) | (step << 6) | (ap << 3) | a0;
+}
+__host__ __device__ inline int code_k(int c) { return c >> 9; }
+__host__ __device__ inline int code_step(int c) { return (c >> 6) & 7; }
+__host__ __device__ inline int code_ap(int c) { return (c >> 3) & 7; }
+__host__ __device__ inline int code_a0(int c) { return c & 7; }
 
 struct SelDev {             // per-signal results of the selection pass (general mode)
     unsigned long long thr_key;   // K-th largest singular value (as ordered bits)
     long long thr_idx;            // ties at thr_key vote when flat index <= thr_idx
     double nu;                    // noise floor
     double pad;
+};
+
+// Queue kQueues is the active list; the others are the round and CS queues.
+__device__ inline int* queue_counter(WorkCounters* w, int q) { return q == kQueues ? &w->n_active : &w->q[q]; }
+__device__ inline int2* queue_list(int2* active, int2* qlist, int64_t cap, int q) {
+    return q == kQueues ? active : qlist + (int64_t)q * cap;
+}
+
+// Block-aggregated appends: in each trip of a block-uniform loop every thread
+// calls reserve() with its target queue (or -1), then commit() writes the
+// entries with one global atomic per non-empty queue and block.
+struct BlockQueues {
+    int cnt[kQueues + 1];
+    int base[kQueues + 1];
+    __device__ void reset() {
+        if (threadIdx.x <= kQueues) cnt[threadIdx.x] = 0;
+        __syncthreads();
+    }
+    __device__ int reserve(int q) { return q >= 0 ? atomicAdd(&cnt[q], 1) : 0; }
+    __device__ void commit(WorkCounters* w, int2* active, int2* qlist, int64_t cap, int q, int slot, int2 ent) {
+        __syncthreads();
+        if (threadIdx.x <= kQueues && cnt[threadIdx.x] > 0) base[threadIdx.x] = atomicAdd(queue_counter(w, threadIdx.x), cnt[threadIdx.x]);
+        __syncthreads();
+        if (q >= 0) queue_list(active, qlist, cap, q)[base[q] + slot] = ent;
+        __syncthreads();
+    }
 };
 
 // ---------------------------------------------------------------- complex FP64
@@ -155,12 +204,12 @@ struct LaunchCtx {
     int n_act_items;
     int n_general;           // signals in general mode
     const int* general_sigs; // their indices
-    const signed char* orders;   // learned order per bin (nullable), indexed by bin_off + k
     int any_general;
+    int max_l;               // largest L of the plan's signals
     unsigned char* keep;     // per staging entry: kept in the output
     WorkCounters* work;      // list lengths
     int2* active_list;       // [list_cap]
-    int2* cs_list;           // [kMaxL][list_cap]
+    int2* qlist;             // [kQueues][list_cap]: round queues, then CS queues
     int64_t list_cap;        // total bins of the plan
     int n_work_blocks;       // grid of the list-driven kernels
 };
@@ -170,7 +219,9 @@ hipError_t launch_syndromes(const LaunchCtx& c);
 hipError_t launch_singular_values(const LaunchCtx& c);
 hipError_t launch_select(const LaunchCtx& c);
 hipError_t launch_activity(const LaunchCtx& c);
-hipError_t launch_decode(const LaunchCtx& c);
+hipError_t launch_rank(const LaunchCtx& c, int q_in, int set_out, bool fuse);   // q_in < 0: the active list
+hipError_t launch_zero_set(const LaunchCtx& c, int set);
+hipError_t launch_round(const LaunchCtx& c, int round);
 hipError_t launch_cs(const LaunchCtx& c);
 hipError_t launch_output(const LaunchCtx& c);
 

@@ -38,7 +38,7 @@ __device__ inline void load_derotated(const typename V2<T>::type* __restrict__ s
 
 // Raw syndromes m_l[k] of the lines [0, cnt) (no de-rotation), FP64.
 template <typename T, int MAXC>
-__device__ inline void load_raw(const typename V2<T>::type* __restrict__ syn, int log2m, int64_t k, int cnt, zd* out) {
+__device__ __attribute__((always_inline)) inline void load_raw(const typename V2<T>::type* __restrict__ syn, int log2m, int64_t k, int cnt, zd* out) {
 #pragma unroll
     for (int l = 0; l < MAXC; ++l) {
         out[l] = zd{0.0, 0.0};
@@ -49,9 +49,24 @@ __device__ inline void load_raw(const typename V2<T>::type* __restrict__ syn, in
     }
 }
 
+// In place, for the 2L consecutive shifts l = 0 .. cnt-1:
+// m_l <- e^{-i 2 pi k l / N} m_l, with the phase factors as running powers of
+// e^{-i 2 pi k / N} (a few ulps after 2L - 1 products; one sincospi per bin
+// instead of one per line keeps the lane's registers low).
+template <int MAXC>
+__device__ __attribute__((always_inline)) inline void derotate_consecutive(zd* m, int64_t k, int64_t n, int cnt) {
+    const zd w1 = unit_root(k & (n - 1), n);
+    zd w{1.0, 0.0};
+#pragma unroll
+    for (int l = 0; l < MAXC; ++l) {
+        if (l < cnt) m[l] = cmul_conj(w, m[l]);
+        w = w * w1;
+    }
+}
+
 // In place: m_l <- e^{-i 2 pi (k sh_l mod N) / N} m_l.
 template <int MAXC>
-__device__ inline void derotate(zd* m, int64_t k, int64_t n, const int64_t* sh, int cnt) {
+__device__ __attribute__((always_inline)) inline void derotate(zd* m, int64_t k, int64_t n, const int64_t* sh, int cnt) {
 #pragma unroll
     for (int l = 0; l < MAXC; ++l)
         if (l < cnt) m[l] = cmul_conj(unit_root((k * sh[l]) & (n - 1), n), m[l]);
@@ -71,29 +86,26 @@ __device__ inline int wave_append(int* counter, bool pred) {
     return base + __popcll(mask & ((1ull << lane) - 1ull));
 }
 
-// Add n (>= 0) to *addr for every running lane of the wave and return each
-// lane's previous value plus the sum over lower lanes with the same address:
-// one atomic per wave when all lanes share the address (the common case: a
-// wave's bins belong to one signal), one per lane otherwise.
+// Add n (0 <= n < 8) to *addr for every running lane of the wave and return
+// each lane's previous value plus the sum over lower running lanes with the
+// same address: one atomic per wave when all lanes share the address (the
+// common case: a wave's bins belong to one signal), one per lane otherwise.
+// The prefix sums come from one ballot per bit of n, so any subset of the
+// wave's lanes may be running.
 __device__ inline int wave_add(int* addr, int n) {
     const unsigned long long run = __ballot(true);
     const int lane = __lane_id();
     const int leader = __ffsll((long long)run) - 1;
     const unsigned long long a_lead = __shfl((unsigned long long)addr, leader);
     if (__ballot((unsigned long long)addr != a_lead) != 0ull) return atomicAdd(addr, n);
-    // inclusive prefix sum of n over the running lanes
-    int incl = n;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        int v = __shfl_up(incl, off);
-        if (lane >= off && ((run >> (lane - off)) & 1ull)) incl += v;
-    }
-    const int last = 63 - __clzll((long long)run);
-    const int total = __shfl(incl, last);
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    const unsigned long long b0 = __ballot(n & 1), b1 = __ballot(n & 2), b2 = __ballot(n & 4);
+    const int before = __popcll(b0 & lt) + 2 * __popcll(b1 & lt) + 4 * __popcll(b2 & lt);
+    const int total = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2);
     int base = 0;
     if (lane == leader && total > 0) base = atomicAdd(addr, total);
     base = __shfl(base, leader);
-    return base + incl - n;
+    return base + before;
 }
 
 // Count pred over the wave into *addr: one atomic per wave when every running
@@ -130,7 +142,8 @@ __global__ __launch_bounds__(kBlock) void singular_values_kernel(const SigDev* _
     const int64_t k = it.y + threadIdx.x;
     if (k >= sg.m) return;
     zd mt[2 * kMaxL];
-    load_derotated<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, sg.n, shifts + sg.shift_off, 2 * sg.L, mt);
+    load_raw<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, 2 * sg.L, mt);
+    derotate_consecutive<2 * kMaxL>(mt, k, sg.n, 2 * sg.L);
     double e = 0.0;
 #pragma unroll
     for (int l = 0; l < 2 * kMaxL; ++l) e += norm2(mt[l]);   // zero beyond 2L
@@ -237,7 +250,7 @@ struct BinOut {
 
 // One hypothesis of order a: locator, roots, grid check, least squares,
 // residual judge; on acceptance drops |p_j| < tau_amp max|p|.
-__device__ inline bool try_order(const zd* mt, int L, int a, double e, double nu, const SigDev& sg,
+__device__ __attribute__((always_inline)) inline bool try_order(const zd* mt, int L, int a, double e, double nu, const SigDev& sg,
                                  const double2* tab, BinOut& o) {
     zd c[kMaxL], z[kMaxL], p[kMaxL];
     int64_t t[kMaxL];
@@ -277,7 +290,7 @@ __device__ inline bool try_order(const zd* mt, int L, int a, double e, double nu
 }
 
 // Canonical order of hypotheses: a0, a0+1 .. L, then a0-1 .. 1.
-__device__ inline int order_at(int a0, int L, int step) {
+__device__ __attribute__((always_inline)) inline int order_at(int a0, int L, int step) {
     return (step <= L - a0) ? a0 + step : a0 - (step - (L - a0));
 }
 
@@ -505,7 +518,7 @@ __device__ inline bool cs_recover(const zd* mt, const zd* y, int R, const int64_
 
 // Append the kept entries of a bin to its signal's staging list.  Every
 // running lane of the wave calls this (with o.n = 0 when it has nothing).
-__device__ inline void emit(const SigDev& sg, SigCounters* cnt, int64_t k, const BinOut& o, int64_t* st_loc,
+__device__ __attribute__((always_inline)) inline void emit(const SigDev& sg, SigCounters* cnt, int64_t k, const BinOut& o, int64_t* st_loc,
                             double2* st_val) {
     int pos = wave_add(&cnt->stage_count, o.n);
 #pragma unroll
@@ -520,12 +533,29 @@ __device__ inline void emit(const SigDev& sg, SigCounters* cnt, int64_t k, const
     }
 }
 
-// Activity pass: exact mode tests E_k > tau_zero^2 mean E, general mode counts
-// the bin's votes.  One block per tile of up to kActivityTile bins of a signal
-// stages its active bins in LDS and reserves room in the plan-wide work list
-// with a single atomic (the order of the list does not matter: the output is
-// sorted at the end).
+// ------------------------------------------------------------ work queues
 
+// Order sequence of a bin: the learned order ap first (when given), then the
+// canonical order from a0 without ap.  Returns the i-th order (i < L).
+__device__ __attribute__((always_inline)) inline int seq_order(int a0, int ap, int L, int i) {
+    if (ap < 1) return order_at(a0, L, i);
+    if (i == 0) return ap;
+    int n = 0, a = 0;
+#pragma unroll
+    for (int st = 0; st < kMaxL; ++st) {
+        if (st >= L) break;
+        const int b = order_at(a0, L, st);
+        if (b == ap) continue;
+        if (n == i - 1 && a == 0) a = b;
+        ++n;
+    }
+    return a;
+}
+
+// Activity pass: exact mode tests E_k > tau_zero^2 mean E and lists the bin
+// in the active list; general mode counts the bin's votes a0 and queues it for
+// round 0 at order a0.  One block per tile of up to kActivityTile bins of a
+// signal stages its bins in LDS and reserves room with one atomic per queue.
 __global__ __launch_bounds__(kBlock) void activity_kernel(const SigDev* __restrict__ sigs,
                                                           const int2* __restrict__ items,
                                                           const float2* __restrict__ synd32,
@@ -533,10 +563,13 @@ __global__ __launch_bounds__(kBlock) void activity_kernel(const SigDev* __restri
                                                           const double* __restrict__ epart,
                                                           const double* __restrict__ sigma,
                                                           const SelDev* __restrict__ sel,
-                                                          WorkCounters* __restrict__ work, int2* __restrict__ list,
+                                                          WorkCounters* __restrict__ work, int2* __restrict__ active,
+                                                          int2* __restrict__ qlist, int64_t list_cap,
                                                           SigCounters* __restrict__ cnt) {
-    __shared__ int stage[kActivityTile];
-    __shared__ int n_here, base;
+    __shared__ int st_code[kActivityTile];
+    __shared__ int st_qs[kActivityTile];   // queue << 16 | slot within the queue
+    __shared__ int n_here;
+    __shared__ BlockQueues bq;
     const int2 it = items[blockIdx.x];
     if (it.x < 0) return;   // padding item
     const int s = it.x;
@@ -545,15 +578,15 @@ __global__ __launch_bounds__(kBlock) void activity_kernel(const SigDev* __restri
     const int64_t k0 = it.y;
     const int64_t k1 = (k0 + kActivityTile < sg.m) ? k0 + kActivityTile : sg.m;
     if (threadIdx.x == 0) n_here = 0;
+    bq.reset();
     double eref = 0.0;
     for (int l = 0; l < 2 * L; ++l) eref += epart[sg.epart_off + l];
     eref /= (double)sg.m;
     SelDev sd{};
     if (sg.mode != kExact) sd = sel[s];
-    __syncthreads();
     for (int64_t k = k0 + threadIdx.x; k < k1; k += kBlock) {
         int a0 = 0;
-        bool active;
+        bool act;
         if (sg.mode == kExact) {
             double e = 0.0;
             for (int l = 0; l < 2 * L; ++l) {
@@ -570,106 +603,167 @@ __global__ __launch_bounds__(kBlock) void activity_kernel(const SigDev* __restri
                 }
                 e += re * re + im * im;
             }
-            active = e > sg.tau_zero2 * eref;
+            act = e > sg.tau_zero2 * eref;
         } else {
             for (int i = 0; i < L; ++i) {
                 int64_t flat = k * L + i;
                 unsigned long long kv = sv_key(sigma[(sg.bin_off + k) * L + i]);
                 a0 += (kv > sd.thr_key || (kv == sd.thr_key && flat <= sd.thr_idx)) ? 1 : 0;
             }
-            active = a0 > 0;
+            act = a0 > 0;
         }
-        if (active) stage[atomicAdd(&n_here, 1)] = (int)(k << 3) | a0;
+        if (act) {
+            const int q = sg.mode == kExact ? kQueues : q_round(0, a0);
+            const int pos = atomicAdd(&n_here, 1);
+            st_code[pos] = pack_code(k, 0, 0, a0);
+            st_qs[pos] = (q << 16) | bq.reserve(q);
+        }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        base = atomicAdd(&work->n_active, n_here);
-        atomicAdd(&cnt[s].active, n_here);
-    }
+    if (threadIdx.x <= kQueues && bq.cnt[threadIdx.x] > 0)
+        bq.base[threadIdx.x] = atomicAdd(queue_counter(work, threadIdx.x), bq.cnt[threadIdx.x]);
+    if (threadIdx.x == 0) atomicAdd(&cnt[s].active, n_here);
     __syncthreads();
-    for (int i = threadIdx.x; i < n_here; i += kBlock) list[base + i] = int2{s, stage[i]};
+    for (int i = threadIdx.x; i < n_here; i += kBlock) {
+        const int q = st_qs[i] >> 16, slot = st_qs[i] & 0xffff;
+        queue_list(active, qlist, list_cap, q)[bq.base[q] + slot] = int2{s, st_code[i]};
+    }
 }
 
-// MODES: bit 0 = the plan has exact-mode signals, bit 1 = general-mode ones;
-// each instantiation carries only the code its modes need.  One lane per
-// active bin, grid-stride over the compacted work list.
-template <typename T, int MODES>
-__global__ __launch_bounds__(kBlock) void decode_kernel(const SigDev* __restrict__ sigs,
-                                                        const int64_t* __restrict__ shifts,
-                                                        const typename V2<T>::type* __restrict__ synd,
-                                                        const SelDev* __restrict__ sel,
-                                                        const double2* __restrict__ tab,
-                                                        const signed char* __restrict__ orders,
-                                                        SigCounters* __restrict__ cnt, int64_t* __restrict__ st_loc,
-                                                        double2* __restrict__ st_val, WorkCounters* __restrict__ work,
-                                                        const int2* __restrict__ list, int2* __restrict__ cs_list,
-                                                        int64_t list_cap) {
-    __shared__ int q_cnt[kMaxL], q_base[kMaxL];
-    const int total = work->n_active;
+// Rank test of exact-mode bins (Pruning Step 1 analogue of the exact case):
+// a0 = #{sigma_i > tau_rank sigma_1} of the L x L Hankel matrix, through the
+// rank-one certificate when it applies and the Jacobi SVD otherwise.  The bin
+// is queued in set `set_out` at its next order.  With `fuse`, a bin whose
+// next order is 1 (the common case) is tried here at once; a rejected one
+// goes to the next round's set.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void rank_kernel(const SigDev* __restrict__ sigs, const int64_t* __restrict__ shifts,
+                                                      const typename V2<T>::type* __restrict__ synd,
+                                                      const double2* __restrict__ tab, SigCounters* __restrict__ cnt,
+                                                      int64_t* __restrict__ st_loc, double2* __restrict__ st_val,
+                                                      WorkCounters* __restrict__ work, int2* __restrict__ active,
+                                                      int2* __restrict__ qlist, int64_t list_cap, int q_in, int set_out,
+                                                      int fuse) {
+    __shared__ BlockQueues bq;
+    const int total = *queue_counter(work, q_in);
+    const int2* in = queue_list(active, qlist, list_cap, q_in);
     for (int base0 = blockIdx.x * kBlock; base0 < total; base0 += gridDim.x * kBlock) {
+        bq.reset();
         const int item = base0 + threadIdx.x;
-        if (threadIdx.x < kMaxL) q_cnt[threadIdx.x] = 0;
-        __syncthreads();
-        int q_slot = -1, q_a = 0;
+        int q = -1;
+        int2 ent{0, 0};
         if (item < total) {
-        const int2 en = list[item];
-        const int s = en.x;
-        const int64_t k = en.y >> 3;
-        int a0 = en.y & 7;   // general mode: votes; exact mode: 0 (rank test when needed)
-        const SigDev& sg = sigs[s];
-        const int L = sg.L;
-        const bool exact = (MODES == 1) || (MODES == 3 && sg.mode == kExact);
-        zd mt[2 * kMaxL];
-        const int64_t* sh = shifts + sg.shift_off;
-        load_raw<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, 2 * L, mt);
-        double e = 0.0;   // E_k (de-rotation keeps magnitudes)
+            const int2 en = in[item];
+            const int s = en.x;
+            const int code = en.y;
+            const int64_t k = code_k(code);
+            const int step = code_step(code), ap = code_ap(code);
+            const SigDev& sg = sigs[s];
+            const int L = sg.L;
+            zd mt[2 * kMaxL];
+            load_raw<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, 2 * L, mt);
+            double e = 0.0;
 #pragma unroll
-        for (int l = 0; l < 2 * kMaxL; ++l) e += norm2(mt[l]);   // zero beyond 2L
-        const double nu = exact ? 0.0 : sel[s].nu;
-        const int a_pred = (exact && orders) ? (int)orders[sg.bin_off + k] : 0;
-        derotate<2 * kMaxL>(mt, k, sg.n, sh, 2 * L);
-
-        // Hypotheses: the learned order first (when given), then the canonical
-        // order from a0 (rank test in exact mode, votes in general mode).
-        BinOut o;
-        o.n = 0;
-        bool done = false, fallback = false;
-        const bool has_pred = a_pred >= 1 && a_pred <= L;
-        for (int step = has_pred ? -1 : 0; step < L && !done; ++step) {
-            int a;
-            if (step < 0) {
-                a = a_pred;
-            } else {
-                if ((MODES & 1) && a0 == 0) {
-                    double sv[kMaxL];
-                    hankel_singular_values(mt, L, sv);
-                    a0 = rank_order(sv, L, sg.tau_rank);
-                }
-                a = order_at(a0, L, step);
-                if (has_pred && a == a_pred) continue;
+            for (int l = 0; l < 2 * kMaxL; ++l) e += norm2(mt[l]);   // zero beyond 2L
+            derotate_consecutive<2 * kMaxL>(mt, k, sg.n, 2 * L);
+            int a0 = 1;
+            if (!rank_one_certified(mt, L, sg.tau_rank)) {
+                double sv[kMaxL];
+                hankel_singular_values(mt, L, sv);
+                a0 = rank_order(sv, L, sg.tau_rank);
             }
-            done = try_order(mt, L, a, e, nu, sg, tab, o);
-            if (step < 0 && !done) fallback = true;
+            const int a = seq_order(a0, ap, L, step);
+            if (fuse && a == 1) {
+                BinOut o;
+                o.n = 0;
+                if (try_order(mt, L, 1, e, 0.0, sg, tab, o)) {
+                    emit(sg, &cnt[s], k, o, st_loc, st_val);
+                } else if (step + 1 < L) {
+                    q = q_round(set_out ^ 1, seq_order(a0, ap, L, step + 1));
+                    ent = int2{s, pack_code(k, step + 1, ap, a0)};
+                } else {
+                    wave_count(&cnt[s].flagged, true);
+                }
+            } else {
+                q = q_round(set_out, a);
+                ent = int2{s, pack_code(k, step, ap, a0)};
+            }
         }
-        if (!done) o.n = 0;
-        wave_count(&cnt[s].flagged, !done);
-        if (MODES & 1) wave_count(&cnt[s].mlp_fb, fallback);
-        emit(sg, &cnt[s], k, o, st_loc, st_val);
-        // general mode: queue flagged bins for the CS step, by a0
-        if ((MODES & 2) && !done && !exact) {
-            q_a = a0;
-            q_slot = atomicAdd(&q_cnt[a0 - 1], 1);
-        }
-        }
-        __syncthreads();
-        if (threadIdx.x < kMaxL) q_base[threadIdx.x] = q_cnt[threadIdx.x] ? atomicAdd(&work->n_cs[threadIdx.x], q_cnt[threadIdx.x]) : 0;
-        __syncthreads();
-        if (q_slot >= 0) {
-            const int2 en = list[item];
-            cs_list[(int64_t)(q_a - 1) * list_cap + q_base[q_a - 1] + q_slot] = int2{en.x, en.y >> 3};
-        }
-        __syncthreads();
+        const int slot = bq.reserve(q);
+        bq.commit(work, active, qlist, list_cap, q, slot, ent);
     }
+}
+
+// One round of the decoder for the bins whose next hypothesis has order A
+// (round r reads set r % 2): locator, roots, grid check, least squares and
+// judge for that order only.  Accepted bins are emitted; rejected ones move
+// to the next round at their next order (or to the rank test, for a bin whose
+// learned order failed), and a bin with no order left is flagged: counted,
+// and in general mode queued for the CS step by its vote order.
+template <typename T, int A>
+__global__ __launch_bounds__(kBlock) void round_kernel(const SigDev* __restrict__ sigs, const int64_t* __restrict__ shifts,
+                                                       const typename V2<T>::type* __restrict__ synd,
+                                                       const SelDev* __restrict__ sel, const double2* __restrict__ tab,
+                                                       SigCounters* __restrict__ cnt, int64_t* __restrict__ st_loc,
+                                                       double2* __restrict__ st_val, WorkCounters* __restrict__ work,
+                                                       int2* __restrict__ active, int2* __restrict__ qlist,
+                                                       int64_t list_cap, int round) {
+    __shared__ BlockQueues bq;
+    const int set_in = round & 1;
+    const int total = work->q[q_round(set_in, A)];
+    const int2* in = qlist + (int64_t)q_round(set_in, A) * list_cap;
+    for (int base0 = blockIdx.x * kBlock; base0 < total; base0 += gridDim.x * kBlock) {
+        bq.reset();
+        const int item = base0 + threadIdx.x;
+        int q = -1;
+        int2 ent{0, 0};
+        if (item < total) {
+            const int2 en = in[item];
+            const int s = en.x;
+            const int code = en.y;
+            const int64_t k = code_k(code);
+            const int step = code_step(code), ap = code_ap(code), a0 = code_a0(code);
+            const SigDev& sg = sigs[s];
+            const int L = sg.L;
+            const bool exact = sg.mode == kExact;
+            zd mt[2 * kMaxL];
+            load_raw<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, 2 * L, mt);
+            double e = 0.0;
+#pragma unroll
+            for (int l = 0; l < 2 * kMaxL; ++l) e += norm2(mt[l]);
+            derotate_consecutive<2 * kMaxL>(mt, k, sg.n, 2 * L);
+            const double nu = exact ? 0.0 : sel[s].nu;
+            BinOut o;
+            o.n = 0;
+            if (try_order(mt, L, A, e, nu, sg, tab, o)) {
+                emit(sg, &cnt[s], k, o, st_loc, st_val);
+            } else {
+                if (step == 0 && ap > 0) wave_count(&cnt[s].mlp_fb, true);
+                const int nx = step + 1;
+                if (nx < L) {
+                    if (ap > 0 && a0 == 0) {
+                        q = q_round(set_in ^ 1, 0);
+                        ent = int2{s, pack_code(k, nx, ap, 0)};
+                    } else {
+                        q = q_round(set_in ^ 1, seq_order(a0, ap, L, nx));
+                        ent = int2{s, pack_code(k, nx, ap, a0)};
+                    }
+                } else {
+                    wave_count(&cnt[s].flagged, true);
+                    if (!exact) {
+                        q = q_cs(a0);
+                        ent = int2{s, (int)k};
+                    }
+                }
+            }
+        }
+        const int slot = bq.reserve(q);
+        bq.commit(work, active, qlist, list_cap, q, slot, ent);
+    }
+}
+
+__global__ void zero_set_kernel(WorkCounters* work, int set) {
+    if (threadIdx.x < kRoundSlots) work->q[q_round(set, threadIdx.x)] = 0;
 }
 
 // CS step for the bins the decoder queued (general mode), one lane per bin;
@@ -681,17 +775,19 @@ __global__ __launch_bounds__(kBlock) void cs_kernel(const SigDev* __restrict__ s
                                                     const double2* __restrict__ tab, SigCounters* __restrict__ cnt,
                                                     int64_t* __restrict__ st_loc, double2* __restrict__ st_val,
                                                     const WorkCounters* __restrict__ work,
-                                                    const int2* __restrict__ cs_list, int64_t list_cap) {
-    const int total = work->n_cs[A0 - 1];
+                                                    const int2* __restrict__ qlist, int64_t list_cap) {
+    const int total = work->q[q_cs(A0)];
+    const int2* in = qlist + (int64_t)q_cs(A0) * list_cap;
     for (int item = blockIdx.x * kBlock + threadIdx.x; item < total; item += gridDim.x * kBlock) {
-        const int2 en = cs_list[(int64_t)(A0 - 1) * list_cap + item];
+        const int2 en = in[item];
         const int s = en.x;
         const int64_t k = en.y;
         const SigDev& sg = sigs[s];
         const int L = sg.L;
         const int64_t* sh = shifts + sg.shift_off;
         zd mt[2 * kMaxL];
-        load_derotated<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, sg.n, sh, 2 * L, mt);
+        load_raw<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, 2 * L, mt);
+        derotate_consecutive<2 * kMaxL>(mt, k, sg.n, 2 * L);
         zd y[kMaxR];
         const int R = sg.R;
         load_derotated<T, kMaxR>(synd + sg.synd_off + ((int64_t)(2 * L) << sg.log2m), sg.log2m, k, sg.n, sh + 2 * L,
@@ -827,30 +923,49 @@ hipError_t launch_activity(const LaunchCtx& c) {
     if (c.n_act_items == 0) return hipSuccess;
     hipLaunchKernelGGL(activity_kernel, dim3(c.n_act_items), dim3(kBlock), 0, c.stream, c.sigs, c.act_items,
                        c.fp64 ? nullptr : (const float2*)c.synd, c.fp64 ? (const double2*)c.synd : nullptr, c.epart,
-                       c.sigma, c.sel, c.work, c.active_list, c.cnt);
+                       c.sigma, c.sel, c.work, c.active_list, c.qlist, c.list_cap, c.cnt);
     return hipGetLastError();
 }
 
-template <typename T, int MODES>
-static void launch_decode_t(const LaunchCtx& c) {
-    using V = typename V2<T>::type;
-    hipLaunchKernelGGL((decode_kernel<T, MODES>), dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs, c.shifts,
-                       (const V*)c.synd, c.sel, c.omega, c.orders, c.cnt, c.st_loc, c.st_val, c.work, c.active_list,
-                       c.cs_list, c.list_cap);
+hipError_t launch_rank(const LaunchCtx& c, int q_in, int set_out, bool fuse) {
+    if (c.n_bin_items == 0) return hipSuccess;
+    const int q = q_in < 0 ? kQueues : q_in;
+    if (c.fp64)
+        hipLaunchKernelGGL(rank_kernel<double>, dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs, c.shifts,
+                           (const double2*)c.synd, c.omega, c.cnt, c.st_loc, c.st_val, c.work, c.active_list, c.qlist,
+                           c.list_cap, q, set_out, (int)fuse);
+    else
+        hipLaunchKernelGGL(rank_kernel<float>, dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs, c.shifts,
+                           (const float2*)c.synd, c.omega, c.cnt, c.st_loc, c.st_val, c.work, c.active_list, c.qlist,
+                           c.list_cap, q, set_out, (int)fuse);
+    return hipGetLastError();
 }
 
-hipError_t launch_decode(const LaunchCtx& c) {
+hipError_t launch_zero_set(const LaunchCtx& c, int set) {
+    hipLaunchKernelGGL(zero_set_kernel, dim3(1), dim3(64), 0, c.stream, c.work, set);
+    return hipGetLastError();
+}
+
+template <typename T, int A>
+static void launch_round_one(const LaunchCtx& c, int round) {
+    using V = typename V2<T>::type;
+    hipLaunchKernelGGL((round_kernel<T, A>), dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs, c.shifts,
+                       (const V*)c.synd, c.sel, c.omega, c.cnt, c.st_loc, c.st_val, c.work, c.active_list, c.qlist,
+                       c.list_cap, round);
+}
+
+template <typename T>
+static void launch_round_t(const LaunchCtx& c, int round) {
+    launch_round_one<T, 1>(c, round);
+    if (c.max_l >= 2) launch_round_one<T, 2>(c, round);
+    if (c.max_l >= 3) launch_round_one<T, 3>(c, round);
+    if (c.max_l >= 4) launch_round_one<T, 4>(c, round);
+}
+
+hipError_t launch_round(const LaunchCtx& c, int round) {
     if (c.n_bin_items == 0) return hipSuccess;
-    const int modes = (c.n_general < c.n_sigs ? 1 : 0) | (c.n_general > 0 ? 2 : 0);
-    if (c.fp64) {
-        if (modes == 1) launch_decode_t<double, 1>(c);
-        else if (modes == 2) launch_decode_t<double, 2>(c);
-        else launch_decode_t<double, 3>(c);
-    } else {
-        if (modes == 1) launch_decode_t<float, 1>(c);
-        else if (modes == 2) launch_decode_t<float, 2>(c);
-        else launch_decode_t<float, 3>(c);
-    }
+    if (c.fp64) launch_round_t<double>(c, round);
+    else launch_round_t<float>(c, round);
     return hipGetLastError();
 }
 
@@ -858,7 +973,7 @@ template <typename T, int A0>
 static void launch_cs_one(const LaunchCtx& c) {
     using V = typename V2<T>::type;
     hipLaunchKernelGGL((cs_kernel<T, A0>), dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs, c.shifts,
-                       (const V*)c.synd, c.omega, c.cnt, c.st_loc, c.st_val, c.work, c.cs_list, c.list_cap);
+                       (const V*)c.synd, c.omega, c.cnt, c.st_loc, c.st_val, c.work, c.qlist, c.list_cap);
 }
 
 template <typename T>

@@ -19,6 +19,8 @@
 
 namespace sft {
 
+constexpr int kGatherBatch = 16;   // strided loads in flight per thread
+
 template <typename T>
 struct C2;
 template <>
@@ -170,20 +172,39 @@ __global__ __launch_bounds__(kBlock) void syndrome_kernel(const SigDev* __restri
             buf[p] = y[((int64_t)(line0 + line) << log2m1) + j];
         }
     } else {
-        // strided samples of x: line fastest, so consecutive shifts read adjacent samples
-        for (int p = threadIdx.x; p < P; p += kBlock) {
-            const int line = p % nl, j = p / nl;
-            const int g = line0 + line;
-            int64_t idx;
-            if (pass == 0) {
-                idx = (sg.d * (int64_t)j + sh[g]) & nmask;
-            } else {
-                const int l = g >> log2m1, n1 = g & ((1 << log2m1) - 1);
-                idx = (sg.d * ((int64_t)n1 + ((int64_t)j << log2m1)) + sh[l]) & nmask;
+        // strided samples of x: line fastest, so consecutive shifts read adjacent
+        // samples.  kGatherBatch loads per thread are issued before any is
+        // stored, so that many requests are in flight per wave.
+        // p / nl by multiply-high: exact for p < 2^32 / nl (here p < 2^14, nl <= 2^7).
+        const unsigned long long inv = (0xFFFFFFFFull + (unsigned)nl) / (unsigned)nl;
+        for (int p0 = threadIdx.x; p0 < P; p0 += kGatherBatch * kBlock) {
+            V v[kGatherBatch];
+#pragma unroll
+            for (int u = 0; u < kGatherBatch; ++u) {
+                const int p = p0 + u * kBlock;
+                if (p < P) {
+                    const int j = (int)(((unsigned long long)p * inv) >> 32);
+                    const int g = line0 + (p - j * nl);
+                    int64_t idx;
+                    if (pass == 0) {
+                        idx = (sg.d * (int64_t)j + sh[g]) & nmask;
+                    } else {
+                        const int l = g >> log2m1, n1 = g & ((1 << log2m1) - 1);
+                        idx = (sg.d * ((int64_t)n1 + ((int64_t)j << log2m1)) + sh[l]) & nmask;
+                    }
+                    v[u] = x[idx];
+                }
             }
-            V v = x[idx];
-            if (sg.flags & 4) bad += !(isfinite(v.x) && isfinite(v.y));
-            buf[(line << log2len) + j] = v;
+#pragma unroll
+            for (int u = 0; u < kGatherBatch; ++u) {
+                const int p = p0 + u * kBlock;
+                if (p < P) {
+                    const int j = (int)(((unsigned long long)p * inv) >> 32);
+                    const int line = p - j * nl;
+                    if (sg.flags & 4) bad += !(isfinite(v[u].x) && isfinite(v[u].y));
+                    buf[(line << log2len) + j] = v[u];
+                }
+            }
         }
         if ((sg.flags & 4) && bad) atomicAdd(&cnt[s].nonfinite, bad);
     }
@@ -278,7 +299,7 @@ __global__ __launch_bounds__(kBlock) void line_energy_kernel(const SigDev* __res
 __global__ void zero_counters_kernel(SigCounters* cnt, int n, WorkCounters* work) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) cnt[i] = SigCounters{0, 0, 0, 0, 0, 0, 0, 0};
-    if (i == 0) *work = WorkCounters{0, {0, 0, 0, 0}, {0, 0, 0}};
+    if (i < (int)(sizeof(WorkCounters) / sizeof(int))) reinterpret_cast<int*>(work)[i] = 0;
 }
 
 hipError_t launch_zero_counters(const LaunchCtx& c) {

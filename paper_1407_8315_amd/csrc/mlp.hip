@@ -10,6 +10,7 @@
 // weight gradients reduce over the block's rows with MFMA and are added to a
 // global FP32 buffer.  Adam updates FP32 master weights and refreshes the BF16
 // copies.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -130,26 +131,43 @@ __device__ inline void forward_rows(const WeightsLds& W, const bf16* X, bf16* H1
     for (int j = 0; j < 4; ++j) f.z3[j] += W.b3[li];
 }
 
-// Features of one bin (see the module comment of the reference network):
-// de-rotated syndromes rotated so that mt_0 is real positive and scaled to
-// unit mean square, their magnitudes, and log(E / E_ref).
-__device__ inline void bin_features(const zd* mt, double eref, float* f) {
-    double e = 0.0;
-#pragma unroll
-    for (int l = 0; l < 8; ++l) e += norm2(mt[l]);
-    const double rms = sqrt(e / 8.0);
-    const double a0 = cabs(mt[0]);
-    zd ph = a0 > 0.0 ? zd{mt[0].x / a0, -mt[0].y / a0} : zd{1.0, 0.0};
+// Features of bin k of signal sg (see the module comment of the reference
+// network), from its 8 raw syndromes, in FP32 (they are rounded to BF16 for
+// the network; the de-rotation phase (k l mod N) / N is reduced exactly).
+template <typename V>
+__device__ inline void bin_features(const V* __restrict__ synd, const SigDev& sg, int64_t k, float eref, float* f) {
+    float2 mt[8];
+    float e = 0.0f;
 #pragma unroll
     for (int l = 0; l < 8; ++l) {
-        zd u = mt[l] * ph;
-        f[2 * l] = (float)(u.x / rms);
-        f[2 * l + 1] = (float)(u.y / rms);
-        f[16 + l] = (float)(cabs(mt[l]) / rms);
+        const auto v = synd[sg.synd_off + ((int64_t)l << sg.log2m) + k];
+        const int64_t q = (k * l) & (sg.n - 1);
+        float sn, cs;
+        sincospif((float)(2.0 * (double)q / (double)sg.n), &sn, &cs);
+        const float vx = (float)v.x, vy = (float)v.y;
+        mt[l] = float2{cs * vx + sn * vy, cs * vy - sn * vx};   // e^{-i 2 pi q / N} m_l
+        e += mt[l].x * mt[l].x + mt[l].y * mt[l].y;
     }
-    f[24] = (float)log(e / eref);
+    const float rms = sqrtf(e / 8.0f);
+    const float a0 = sqrtf(mt[0].x * mt[0].x + mt[0].y * mt[0].y);
+    const float px = a0 > 0.0f ? mt[0].x / a0 : 1.0f, py = a0 > 0.0f ? -mt[0].y / a0 : 0.0f;
+    const float ir = 1.0f / rms;
+#pragma unroll
+    for (int l = 0; l < 8; ++l) {
+        f[2 * l] = (mt[l].x * px - mt[l].y * py) * ir;
+        f[2 * l + 1] = (mt[l].x * py + mt[l].y * px) * ir;
+        f[16 + l] = sqrtf(mt[l].x * mt[l].x + mt[l].y * mt[l].y) * ir;
+    }
+    f[24] = logf(e / eref);
 #pragma unroll
     for (int i = 25; i < kNF; ++i) f[i] = 0.0f;
+}
+
+__device__ inline float mean_bin_energy(const LaunchCtx& c, const SigDev& sg) {
+    double eref = 0.0;
+#pragma unroll
+    for (int l = 0; l < 8; ++l) eref += c.epart[sg.epart_off + l];
+    return (float)(eref / (double)sg.m);
 }
 
 template <typename T>
@@ -163,75 +181,134 @@ struct VT<double> {
     using type = double2;
 };
 
-// Features of the active-list entry `item` (exact mode, L = 4).
-template <typename T>
-__device__ inline void list_features(const LaunchCtx& c, const typename VT<T>::type* synd, int item, float* f,
-                                     int& s_out, int64_t& k_out) {
-    const int2 en = c.active_list[item];
-    const SigDev& sg = c.sigs[en.x];
-    const int64_t k = en.y >> 3;
-    zd mt[8];
-#pragma unroll
-    for (int l = 0; l < 8; ++l) {
-        auto v = synd[sg.synd_off + ((int64_t)l << sg.log2m) + k];
-        mt[l] = cmul_conj(unit_root((k * l) & (sg.n - 1), sg.n), zd{(double)v.x, (double)v.y});
-    }
-    double eref = 0.0;
-#pragma unroll
-    for (int l = 0; l < 8; ++l) eref += c.epart[sg.epart_off + l];
-    eref /= (double)sg.m;
-    bin_features(mt, eref, f);
-    s_out = en.x;
-    k_out = k;
+// Orders the LDS traffic of one wave (its own rows only: no block barrier).
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Learned orders for every entry of the active list (features fused in).
+// Logits of the 16 rows X[r0 .. r0+15] by one wave, with Hw the wave's own
+// 16-row activation buffer (reused by both hidden layers).  Returns the
+// logits tile in the MFMA output layout (row 4 (lane / 16) + j, column lane % 16).
+__device__ inline v4f infer_rows(const WeightsLds& W, const bf16* X, int r0, bf16* Hw) {
+    const int l = __lane_id(), li = l & 15, lq = l >> 4;
+    const bf16* w1 = W.w;
+    const bf16* w2 = W.w + kW1Elems;
+    const bf16* w3 = W.w + kW1Elems + kW2Elems;
+    v4f z[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) z[t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < kNF / 16; ++kk) {
+        v4s a = ld4(X + (r0 + li) * kLdX + kk * 16 + lq * 4);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) z[t] = mfma16(a, ld4(w1 + (t * 16 + li) * kLdX + kk * 16 + lq * 4), z[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Hw[(lq * 4 + j) * kLdH + t * 16 + li] = to_bf16(gelu(z[t][j] + W.b1[t * 16 + li]));
+    wave_sync();
+    v4s a[kNH / 16];
+#pragma unroll
+    for (int kk = 0; kk < kNH / 16; ++kk) a[kk] = ld4(Hw + li * kLdH + kk * 16 + lq * 4);
+    wave_sync();
+#pragma unroll
+    for (int t = 0; t < 8; ++t) z[t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < kNH / 16; ++kk)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) z[t] = mfma16(a[kk], ld4(w2 + (t * 16 + li) * kLdH + kk * 16 + lq * 4), z[t]);
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Hw[(lq * 4 + j) * kLdH + t * 16 + li] = to_bf16(gelu(z[t][j] + W.b2[t * 16 + li]));
+    wave_sync();
+    v4f z3 = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < kNH / 16; ++kk)
+        z3 = mfma16(ld4(Hw + li * kLdH + kk * 16 + lq * 4), ld4(w3 + li * kLdH + kk * 16 + lq * 4), z3);
+    wave_sync();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) z3[j] += W.b3[li];
+    return z3;
+}
+
+constexpr int kInferWaves = 8;
+constexpr int kInferTile = 64 * kInferWaves;   // rows per block trip: one per thread
+
+// Learned orders for the active list (exact mode, L = 4): each thread builds
+// the features of one bin, each wave runs the network on 64 rows (4 MFMA row
+// tiles), and the bin is queued for round 0 at its predicted order (or for
+// the rank test when the prediction is 0, i.e. outside 1..L).
 template <typename T>
-__global__ __launch_bounds__(256) void infer_kernel(LaunchCtx c, const bf16* __restrict__ wimg,
-                                                    const float* __restrict__ theta, signed char* __restrict__ orders) {
+__global__ __launch_bounds__(kInferTile) void infer_kernel(LaunchCtx c, const bf16* __restrict__ wimg,
+                                                           const float* __restrict__ theta) {
     __shared__ WeightsLds W;
-    __shared__ __attribute__((aligned(16))) bf16 X[kRows * kLdX];
-    __shared__ __attribute__((aligned(16))) bf16 H1[kRows * kLdH];
-    __shared__ __attribute__((aligned(16))) bf16 H2[kRows * kLdH];
-    __shared__ float Z[kRows * kLdC];
-    __shared__ int sig_of[kRows];
-    __shared__ int bin_of[kRows];
+    __shared__ __attribute__((aligned(16))) bf16 X[kInferTile * kLdX];
+    __shared__ __attribute__((aligned(16))) bf16 H[kInferWaves * 16 * kLdH];
+    __shared__ float Zs[kInferWaves * 16 * 8];
+    __shared__ signed char pred[kInferTile];
+    __shared__ BlockQueues bq;
     load_weights(W, wimg, theta);
     const int total = c.work->n_active;
     const typename VT<T>::type* synd = (const typename VT<T>::type*)c.synd;
-    const int w = threadIdx.x >> 6;
-    for (int base = blockIdx.x * kRows; base < total; base += gridDim.x * kRows) {
-        __syncthreads();
-        if (threadIdx.x < kRows) {
-            float f[kNF];
-            const int item = base + threadIdx.x;
-            int s = -1;
-            int64_t k = 0;
-            if (item < total) list_features<T>(c, synd, item, f, s, k);
-            else
-                for (int i = 0; i < kNF; ++i) f[i] = 0.0f;
-            for (int i = 0; i < kNF; ++i) X[threadIdx.x * kLdX + i] = to_bf16(f[i]);
-            sig_of[threadIdx.x] = s;
-            bin_of[threadIdx.x] = (int)k;
-        }
-        __syncthreads();
-        Fwd fw;
-        forward_rows(W, X, H1, H2, w * 16, fw);
-        const int l = __lane_id(), li = l & 15, lq = l >> 4;
+    const int w = threadIdx.x >> 6, lane = __lane_id();
+    for (int base = blockIdx.x * kInferTile; base < total; base += gridDim.x * kInferTile) {
+        bq.reset();
+        const int item = base + threadIdx.x;
+        int s = -1;
+        int64_t k = 0;
+        float f[kNF];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) Z[(w * 16 + lq * 4 + j) * kLdC + li] = fw.z3[j];
-        __syncthreads();
-        if (threadIdx.x < kRows && sig_of[threadIdx.x] >= 0) {
-            int best = 0;
-            float bv = Z[threadIdx.x * kLdC];
-            for (int cl = 1; cl < kNC; ++cl)
-                if (Z[threadIdx.x * kLdC + cl] > bv) {
-                    bv = Z[threadIdx.x * kLdC + cl];
-                    best = cl;
-                }
-            const SigDev& sg = c.sigs[sig_of[threadIdx.x]];
-            orders[sg.bin_off + bin_of[threadIdx.x]] = (signed char)best;
+        for (int i = 0; i < kNF; ++i) f[i] = 0.0f;
+        if (item < total) {
+            const int2 en = c.active_list[item];
+            s = en.x;
+            k = code_k(en.y);
+            const SigDev& sg = c.sigs[s];
+            bin_features(synd, sg, k, mean_bin_energy(c, sg), f);
         }
+        uint2* xr = reinterpret_cast<uint2*>(X + threadIdx.x * kLdX);
+#pragma unroll
+        for (int i = 0; i < kNF / 4; ++i)
+            xr[i] = uint2{(unsigned)to_bf16(f[4 * i]) | ((unsigned)to_bf16(f[4 * i + 1]) << 16),
+                          (unsigned)to_bf16(f[4 * i + 2]) | ((unsigned)to_bf16(f[4 * i + 3]) << 16)};
+        __syncthreads();
+        bf16* Hw = H + w * 16 * kLdH;
+        float* Zw = Zs + w * 16 * 8;
+        for (int sub = 0; sub < 4; ++sub) {
+            const int r0 = w * 64 + sub * 16;
+            const v4f z3 = infer_rows(W, X, r0, Hw);
+            const int li = lane & 15, lq = lane >> 4;
+            if (li < kNC)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) Zw[(lq * 4 + j) * 8 + li] = z3[j];
+            wave_sync();
+            if (lane < 16) {
+                int best = 0;
+                float bv = Zw[lane * 8];
+                for (int cl = 1; cl < kNC; ++cl)
+                    if (Zw[lane * 8 + cl] > bv) {
+                        bv = Zw[lane * 8 + cl];
+                        best = cl;
+                    }
+                pred[r0 + lane] = (signed char)best;
+            }
+            wave_sync();
+        }
+        __syncthreads();
+        int q = -1;
+        int2 ent{0, 0};
+        if (s >= 0) {
+            int ap = pred[threadIdx.x];
+            if (ap < 1 || ap > c.sigs[s].L) ap = 0;
+            q = q_round(0, ap);
+            ent = int2{s, pack_code(k, 0, ap, 0)};
+        }
+        const int slot = bq.reserve(q);
+        bq.commit(c.work, c.active_list, c.qlist, c.list_cap, q, slot, ent);
     }
 }
 
@@ -243,10 +320,11 @@ __global__ __launch_bounds__(256) void features_kernel(LaunchCtx c, float* __res
     const typename VT<T>::type* synd = (const typename VT<T>::type*)c.synd;
     for (int item = blockIdx.x * blockDim.x + threadIdx.x; item < total; item += gridDim.x * blockDim.x) {
         if (item >= cap) continue;
+        const int2 en = c.active_list[item];
+        const SigDev& sg = c.sigs[en.x];
+        const int64_t k = code_k(en.y);
         float f[kNF];
-        int s;
-        int64_t k;
-        list_features<T>(c, synd, item, f, s, k);
+        bin_features(synd, sg, k, mean_bin_energy(c, sg), f);
         for (int i = 0; i < kNF; ++i) feat[(int64_t)item * kNF + i] = f[i];
         bins[item] = k;
     }
@@ -523,14 +601,14 @@ int grid_for(int64_t rows) {
 
 // Learned mode hook: run the predictor over the active list (after the
 // activity pass, before the decoder).
-sft_status sft_mlp_launch_infer(sft_mlp_t m, const LaunchCtx& c, signed char* orders) {
+sft_status sft_mlp_launch_infer(sft_mlp_t m, const LaunchCtx& c) {
     if (!m) return SFT_OK;
+    // one block of kInferTile rows per CU at a time (the block holds ~124 KiB of LDS)
+    const int grid = std::max(1, std::min(c.n_work_blocks, 512));
     if (c.fp64)
-        hipLaunchKernelGGL(infer_kernel<double>, dim3(c.n_work_blocks), dim3(256), 0, c.stream, c, m->wimg, m->theta,
-                           orders);
+        hipLaunchKernelGGL(infer_kernel<double>, dim3(grid), dim3(kInferTile), 0, c.stream, c, m->wimg, m->theta);
     else
-        hipLaunchKernelGGL(infer_kernel<float>, dim3(c.n_work_blocks), dim3(256), 0, c.stream, c, m->wimg, m->theta,
-                           orders);
+        hipLaunchKernelGGL(infer_kernel<float>, dim3(grid), dim3(kInferTile), 0, c.stream, c, m->wimg, m->theta);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SFT_OK : mfail(SFT_E_DEVICE, hipGetErrorString(e));
 }

@@ -59,6 +59,6 @@ void omega_table(int log2n, std::vector<double2>* out);         // e^{+2 pi i q 
 }  // namespace sft
 
 // Learned mode: run the predictor over the active list, writing per-bin orders.
-sft_status sft_mlp_launch_infer(sft_mlp_t mlp, const sft::LaunchCtx& c, signed char* orders);
+sft_status sft_mlp_launch_infer(sft_mlp_t mlp, const sft::LaunchCtx& c);
 // Features of the active bins (training data) and their count.
 sft_status sft_features_enqueue(const sft::LaunchCtx& c, float* feat, int64_t* bins, int64_t cap, int64_t* count);

@@ -36,13 +36,16 @@ __host__ __device__ inline void hankel_singular_values(const zd* mt, int L, doub
                     be += norm2(h[q][i]);
                     ga = ga + cmul_conj(h[p][i], h[q][i]);
                 }
-                double ag = cabs(ga);
-                if (!(ag > 1e-16 * sqrt(al * be)) || ag == 0.0) continue;
+                // rotate unless |ga| <= 1e-16 sqrt(al be) (columns orthogonal to
+                // working precision); squared test, one reciprocal for e and zeta
+                const double g2 = norm2(ga);
+                if (!(g2 > 1e-32 * (al * be)) || g2 == 0.0) continue;
                 rotated = true;
-                double zeta = (be - al) / (2.0 * ag);
-                double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-                zd e = zd{ga.x / ag, -ga.y / ag};   // e^{-i phi}, phi = arg(ga)
+                const double ag = sqrt(g2), rag = 1.0 / ag;
+                const double zeta = (be - al) * (0.5 * rag);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+                const zd e = zd{ga.x * rag, -ga.y * rag};   // e^{-i phi}, phi = arg(ga)
 #pragma unroll
                 for (int i = 0; i < kMaxL; ++i) {
                     zd hp = h[p][i], hq = e * h[q][i];

@@ -51,7 +51,11 @@ struct sft_plan_s {
     SigCounters* d_cnt = nullptr;
     int64_t* d_stloc = nullptr;
     double2* d_stval = nullptr;
-    unsigned char* d_keep = nullptr;
+    int* d_kidx = nullptr;
+    double* d_rk_a = nullptr;
+    long long* d_rk_b = nullptr;
+    int* d_rk_i = nullptr;
+    int* d_rk_r = nullptr;
     int64_t* d_shifts = nullptr;
     void* d_tw = nullptr;
     double2* d_om = nullptr;
@@ -61,7 +65,6 @@ struct sft_plan_s {
     void* d_ybuf = nullptr;
     int n_synd2_items = 0, n_line_items = 0;
     int2* d_bin_items = nullptr;
-    int2* d_out_items = nullptr;
     int2* d_act_items = nullptr;
     int* d_gsigs = nullptr;
     WorkCounters* d_work = nullptr;
@@ -70,7 +73,7 @@ struct sft_plan_s {
     int max_l = 1;
     int64_t list_cap = 0;
     int n_work_blocks = 0;
-    int n_synd_items = 0, n_bin_items = 0, n_out_items = 0, n_act_items = 0, n_general = 0;
+    int n_synd_items = 0, n_bin_items = 0, n_act_items = 0, n_general = 0;
     int tw_log2 = 0, om_log2 = 0;
     int64_t ws_bytes = 0;
     // host staging
@@ -143,15 +146,17 @@ LaunchCtx make_ctx(const sft_plan_s* p) {
     c.n_line_items = p->n_line_items;
     c.bin_items = p->d_bin_items;
     c.n_bin_items = p->n_bin_items;
-    c.out_items = p->d_out_items;
-    c.n_out_items = p->n_out_items;
     c.act_items = p->d_act_items;
     c.n_act_items = p->n_act_items;
     c.n_general = p->n_general;
     c.general_sigs = p->d_gsigs;
     c.any_general = p->any_general ? 1 : 0;
     c.max_l = p->max_l;
-    c.keep = p->d_keep;
+    c.kidx = p->d_kidx;
+    c.rk_a = p->d_rk_a;
+    c.rk_b = p->d_rk_b;
+    c.rk_i = p->d_rk_i;
+    c.rk_r = p->d_rk_r;
     c.work = p->d_work;
     c.active_list = p->d_active;
     c.qlist = p->d_qlist;
@@ -333,7 +338,6 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     p->n_synd2_items = (int)lay.synd2_items.size();
     p->n_line_items = (int)lay.line_items.size();
     p->n_bin_items = (int)lay.bin_items.size();
-    p->n_out_items = (int)lay.out_items.size();
     p->n_act_items = (int)lay.act_items.size();
 
     const size_t ns = p->sig.size();
@@ -376,14 +380,17 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     TRY(dalloc(p, &p->d_cnt, ns));
     TRY(dalloc(p, &p->d_stloc, (size_t)lay.stage_elems));
     TRY(dalloc(p, &p->d_stval, (size_t)lay.stage_elems));
-    TRY(dalloc(p, &p->d_keep, (size_t)lay.stage_elems));
+    TRY(dalloc(p, &p->d_kidx, (size_t)lay.stage_elems));
+    TRY(dalloc(p, &p->d_rk_a, (size_t)lay.stage_elems));
+    TRY(dalloc(p, &p->d_rk_b, (size_t)lay.stage_elems));
+    TRY(dalloc(p, &p->d_rk_i, (size_t)lay.stage_elems));
+    TRY(dalloc(p, &p->d_rk_r, (size_t)lay.stage_elems));
     TRY(dalloc(p, &p->d_shifts, lay.shifts.size()));
     TRY(dalloc(p, &p->d_om, (size_t)1 << lay.om_log2));
     TRY(dalloc(p, &p->d_synd_items, lay.synd_items.size()));
     TRY(dalloc(p, &p->d_synd2_items, lay.synd2_items.size()));
     TRY(dalloc(p, &p->d_line_items, lay.line_items.size()));
     TRY(dalloc(p, &p->d_bin_items, lay.bin_items.size()));
-    TRY(dalloc(p, &p->d_out_items, lay.out_items.size()));
     TRY(dalloc(p, &p->d_act_items, lay.act_items.size()));
     TRY(dalloc(p, &p->d_gsigs, lay.general_sigs.size()));
     TRY(dalloc(p, &p->d_work, 1));
@@ -392,10 +399,10 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     p->list_cap = lay.bin_elems;
     for (auto& g : p->sig) p->max_l = std::max(p->max_l, g.L);
     {
-        // grid of the list-driven kernels: enough blocks to fill every CU a few
-        // times over, never more than the bins themselves need
+        // grid of the list-driven kernels (grid-stride loops): a few blocks per
+        // CU, never more than the bins themselves need
         int64_t need = (lay.bin_elems + kBlock - 1) / kBlock;
-        p->n_work_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(need, 4096));
+        p->n_work_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(need, 1024));
     }
 
 #define HIPTRY(call)                                                                                   \
@@ -430,7 +437,6 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
         HIPTRY(hipMemcpy(p->d_line_items, lay.line_items.data(), lay.line_items.size() * sizeof(int2),
                          hipMemcpyHostToDevice));
     HIPTRY(hipMemcpy(p->d_bin_items, lay.bin_items.data(), lay.bin_items.size() * sizeof(int2), hipMemcpyHostToDevice));
-    HIPTRY(hipMemcpy(p->d_out_items, lay.out_items.data(), lay.out_items.size() * sizeof(int2), hipMemcpyHostToDevice));
     HIPTRY(hipMemcpy(p->d_act_items, lay.act_items.data(), lay.act_items.size() * sizeof(int2), hipMemcpyHostToDevice));
     if (!lay.general_sigs.empty())
         HIPTRY(hipMemcpy(p->d_gsigs, lay.general_sigs.data(), lay.general_sigs.size() * sizeof(int), hipMemcpyHostToDevice));

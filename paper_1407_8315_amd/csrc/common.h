@@ -198,15 +198,17 @@ struct LaunchCtx {
     int n_line_items;
     const int2* bin_items;   // (sig, bin0): tiles of kBlock bins
     int n_bin_items;
-    const int2* out_items;   // (sig, entry0): tiles of kBlock staging entries
-    int n_out_items;
     const int2* act_items;   // (sig, bin0): tiles of kActivityTile bins
     int n_act_items;
     int n_general;           // signals in general mode
     const int* general_sigs; // their indices
     int any_general;
     int max_l;               // largest L of the plan's signals
-    unsigned char* keep;     // per staging entry: kept in the output
+    int* kidx;               // per staging entry: kept entries (output pass)
+    double* rk_a;            // ranking scratch, one slot per staging entry
+    long long* rk_b;
+    int* rk_i;
+    int* rk_r;
     WorkCounters* work;      // list lengths
     int2* active_list;       // [list_cap]
     int2* qlist;             // [kQueues][list_cap]: round queues, then CS queues

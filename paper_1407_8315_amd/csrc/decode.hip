@@ -155,85 +155,255 @@ __global__ __launch_bounds__(kBlock) void singular_values_kernel(const SigDev* _
     ebin[sg.bin_off + k] = e;
 }
 
-// Block-wide selection of the r-th largest (0-based) 64-bit key by 8-bit
-// radix digits (deterministic: only counts are accumulated).
-template <typename KeyFn>
-__device__ unsigned long long select_rth_largest(KeyFn key, int64_t n, int64_t r, unsigned* hist,
-                                                 unsigned long long* sh_prefix, long long* sh_r) {
-    unsigned long long prefix = 0ull, mask = 0ull;
-    for (int shift = 56; shift >= 0; shift -= 8) {
-        for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0u;
-        __syncthreads();
-        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-            unsigned long long kv = key(i);
-            if ((kv & mask) == prefix) atomicAdd(&hist[(kv >> shift) & 255ull], 1u);
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            long long cum = 0;
-            int dg = 255;
-            for (; dg > 0; --dg) {
-                if (cum + (long long)hist[dg] > r) break;
-                cum += hist[dg];
+// ------------------------------------------------ block-wide ranking
+
+// Ranking and selection over n distinct keys (a, b), ascending in a, then b,
+// by one block of kRankThreads threads.  Up to kRankChunk keys are sorted at
+// once in LDS by a bitonic network.  block_rank() gives every key its rank
+// (several chunks: sorted chunks go to scratch and each key adds, per other
+// chunk, the count of that chunk's keys below it, by binary search);
+// block_select() finds the key of one rank by sorting only a window of keys
+// around it, bracketed by a sorted sample (falling back to block_rank when
+// the window misses or overflows).  Used for the vote threshold, the
+// noise-floor median, the top-K of general mode and the output order.
+constexpr int kRankThreads = 512;
+constexpr int kRankChunk = 2048;
+constexpr int kSelSample = 1024;
+
+struct RankKey {
+    double a;
+    long long b;
+};
+__device__ inline bool key_less(double a1, long long b1, double a2, long long b2) {
+    return a1 < a2 || (a1 == a2 && b1 < b2);
+}
+
+struct RankLds {
+    double a[kRankChunk];
+    long long b[kRankChunk];
+    int idx[kRankChunk];
+    int n_below, n_win, pick;
+};
+
+struct RankScratch {   // per-signal slices of the plan's ranking scratch
+    double* a;
+    long long* b;
+    int* idx;
+    int* rank;         // rank of key i
+};
+
+__device__ inline RankScratch rank_scratch(double* a, long long* b, int* idx, int* rank, int64_t off) {
+    return RankScratch{a + off, b + off, idx + off, rank + off};
+}
+
+// Sort S[0 .. P) ascending (P a power of two; entries beyond the data padded
+// with +inf keys).  Whole block; ends with a barrier.
+__device__ void lds_bitonic(RankLds& S, int P) {
+    for (int k = 2; k <= P; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P; i += blockDim.x) {
+                const int ij = i ^ j;
+                if (ij > i) {
+                    const bool up = (i & k) == 0;
+                    const bool lo_first = key_less(S.a[i], S.b[i], S.a[ij], S.b[ij]);
+                    if (up != lo_first) {
+                        const double ta = S.a[i];
+                        S.a[i] = S.a[ij];
+                        S.a[ij] = ta;
+                        const long long tb = S.b[i];
+                        S.b[i] = S.b[ij];
+                        S.b[ij] = tb;
+                        const int ti = S.idx[i];
+                        S.idx[i] = S.idx[ij];
+                        S.idx[ij] = ti;
+                    }
+                }
             }
-            r -= cum;
-            prefix |= (unsigned long long)dg << shift;
-            *sh_prefix = prefix;
-            *sh_r = r;
+            __syncthreads();
         }
+}
+
+__device__ inline int pow2_at_least(int n) {
+    int P = 1;
+    while (P < n) P <<= 1;
+    return P;
+}
+
+__device__ inline void pad_keys(RankLds& S, int from, int P) {
+    for (int i = from + threadIdx.x; i < P; i += blockDim.x) {
+        S.a[i] = __builtin_huge_val();
+        S.b[i] = 0x7fffffffffffffffll;
+        S.idx[i] = -1;
+    }
+}
+
+// g.rank[i] = position of key(i) in ascending order, i < n.  Whole block.
+template <typename KeyFn>
+__device__ void block_rank(KeyFn key, int n, RankLds& S, const RankScratch& g) {
+    const int nch = (n + kRankChunk - 1) / kRankChunk;
+    for (int c = 0; c < nch; ++c) {
+        const int c0 = c * kRankChunk, cn = min(kRankChunk, n - c0);
+        const int P = pow2_at_least(cn);
+        for (int i = threadIdx.x; i < cn; i += blockDim.x) {
+            const RankKey k = key(c0 + i);
+            S.a[i] = k.a;
+            S.b[i] = k.b;
+            S.idx[i] = c0 + i;
+        }
+        pad_keys(S, cn, P);
         __syncthreads();
-        prefix = *sh_prefix;
-        r = *sh_r;
-        mask |= 255ull << shift;
+        lds_bitonic(S, P);
+        for (int i = threadIdx.x; i < cn; i += blockDim.x) {
+            g.rank[S.idx[i]] = i;
+            if (nch > 1) {
+                g.a[c0 + i] = S.a[i];
+                g.b[c0 + i] = S.b[i];
+                g.idx[c0 + i] = S.idx[i];
+            }
+        }
         __syncthreads();
     }
-    return prefix;
+    if (nch == 1) return;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int c = i / kRankChunk;
+        const double a = g.a[i];
+        const long long b = g.b[i];
+        int r = i - c * kRankChunk;
+        for (int c2 = 0; c2 < nch; ++c2) {
+            if (c2 == c) continue;
+            int lo = c2 * kRankChunk, hi = min(n, lo + kRankChunk);
+            const int base = lo;
+            while (lo < hi) {   // first position whose key is not below (a, b)
+                const int mid = (lo + hi) >> 1;
+                if (key_less(g.a[mid], g.b[mid], a, b)) lo = mid + 1;
+                else hi = mid;
+            }
+            r += lo - base;
+        }
+        g.rank[g.idx[i]] = r;
+    }
+    __syncthreads();
+}
+
+// Index i of the key of ascending rank r (0 <= r < n).  Whole block.
+template <typename KeyFn>
+__device__ int block_select(KeyFn key, int n, int r, RankLds& S, const RankScratch& g) {
+    if (n <= kRankChunk) {
+        const int P = pow2_at_least(n);
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const RankKey k = key(i);
+            S.a[i] = k.a;
+            S.b[i] = k.b;
+            S.idx[i] = i;
+        }
+        pad_keys(S, n, P);
+        __syncthreads();
+        lds_bitonic(S, P);
+        const int out = S.idx[r];
+        __syncthreads();
+        return out;
+    }
+    // sorted sample at scattered positions (t times an odd constant mod n: no
+    // aliasing with a stride of the data, such as the L singular values of a
+    // bin), then a window of sample ranks about r's expected place, +- 3
+    // standard deviations and a margin
+    for (int t = threadIdx.x; t < kSelSample; t += blockDim.x) {
+        const int i = (int)(((unsigned long long)t * 2654435761ull) % (unsigned long long)n);
+        const RankKey k = key(i);
+        S.a[t] = k.a;
+        S.b[t] = k.b;
+        S.idx[t] = i;
+    }
+    if (threadIdx.x == 0) {
+        S.n_below = 0;
+        S.n_win = 0;
+    }
+    __syncthreads();
+    lds_bitonic(S, kSelSample);
+    const double q = ((double)r + 0.5) / (double)n;
+    const int rs = (int)(q * kSelSample);
+    const int w = (int)(3.0 * sqrt((double)kSelSample * q * (1.0 - q))) + 8;
+    const bool has_lo = rs - w >= 0, has_hi = rs + w < kSelSample;
+    const double lo_a = has_lo ? S.a[rs - w] : 0.0, hi_a = has_hi ? S.a[rs + w] : 0.0;
+    const long long lo_b = has_lo ? S.b[rs - w] : 0, hi_b = has_hi ? S.b[rs + w] : 0;
+    __syncthreads();
+    int below = 0, win = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const RankKey k = key(i);
+        if (has_lo && key_less(k.a, k.b, lo_a, lo_b)) ++below;
+        else if (!has_hi || !key_less(hi_a, hi_b, k.a, k.b)) ++win;
+    }
+    atomicAdd(&S.n_below, below);
+    atomicAdd(&S.n_win, win);
+    __syncthreads();
+    const int nb = S.n_below, nw = S.n_win;
+    __syncthreads();
+    if (nb <= r && r < nb + nw && nw <= kRankChunk) {
+        if (threadIdx.x == 0) S.n_win = 0;
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const RankKey k = key(i);
+            const bool in = !(has_lo && key_less(k.a, k.b, lo_a, lo_b)) && (!has_hi || !key_less(hi_a, hi_b, k.a, k.b));
+            if (in) {
+                const int pos = atomicAdd(&S.n_win, 1);
+                S.a[pos] = k.a;
+                S.b[pos] = k.b;
+                S.idx[pos] = i;
+            }
+        }
+        __syncthreads();
+        const int P = pow2_at_least(nw);
+        pad_keys(S, nw, P);
+        __syncthreads();
+        lds_bitonic(S, P);
+        const int out = S.idx[r - nb];
+        __syncthreads();
+        return out;
+    }
+    block_rank(key, n, S, g);
+    if (threadIdx.x == 0) S.pick = -1;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        if (g.rank[i] == r) S.pick = i;
+    __syncthreads();
+    const int out = S.pick;
+    __syncthreads();
+    return out;
 }
 
 // One block per general-mode signal: the vote threshold (the K-th largest of
 // all M L singular values, ties to the lower flat index k L + i) and the
 // noise floor nu = lower median of E_k / (2L - 1/3).
-__global__ __launch_bounds__(1024) void select_kernel(const SigDev* __restrict__ sigs, const int* __restrict__ gsigs,
-                                                      const double* __restrict__ sigma, const double* __restrict__ ebin,
-                                                      SelDev* __restrict__ sel) {
-    __shared__ unsigned hist[256];
-    __shared__ unsigned long long sh_prefix;
-    __shared__ long long sh_r;
-    __shared__ int sh_gt;
+__global__ __launch_bounds__(kRankThreads) void select_kernel(const SigDev* __restrict__ sigs, const int* __restrict__ gsigs,
+                                                              const double* __restrict__ sigma,
+                                                              const double* __restrict__ ebin, SelDev* __restrict__ sel,
+                                                              double* rk_a, long long* rk_b, int* rk_i, int* rk_r) {
+    __shared__ RankLds S;
     const int s = gsigs[blockIdx.x];
     const SigDev& sg = sigs[s];
-    const int64_t nv = (int64_t)sg.m * sg.L;
+    const int nv = sg.m * sg.L;
     const double* sgm = sigma + sg.bin_off * sg.L;
     const double* eb = ebin + sg.bin_off;
+    const RankScratch g = rank_scratch(rk_a, rk_b, rk_i, rk_r, sg.stage_off);
     unsigned long long thr = 0ull;
     long long thr_idx = nv;
-    if ((int64_t)sg.k_votes < nv) {
-        thr = select_rth_largest([&](int64_t i) { return sv_key(sgm[i]); }, nv, (int64_t)sg.k_votes - 1, hist,
-                                 &sh_prefix, &sh_r);
-        if (threadIdx.x == 0) sh_gt = 0;
-        __syncthreads();
-        int gt = 0, eq = 0;
-        for (int64_t i = threadIdx.x; i < nv; i += blockDim.x) {
-            unsigned long long kv = sv_key(sgm[i]);
-            gt += kv > thr;
-        }
-        atomicAdd(&sh_gt, gt);
-        __syncthreads();
-        const int64_t need = (int64_t)sg.k_votes - sh_gt;   // >= 1 votes among the ties
-        (void)eq;
-        unsigned long long idx = select_rth_largest(
-            [&](int64_t i) { return sv_key(sgm[i]) == thr ? (unsigned long long)i : ~0ull; }, nv, nv - need, hist,
-            &sh_prefix, &sh_r);
-        thr_idx = (long long)idx;
+    if (sg.k_votes < nv) {
+        // descending singular values (non-finite ones count as 0), ties to the lower index
+        const int i = block_select(
+            [&](int i) { return RankKey{-__longlong_as_double((long long)sv_key(sgm[i])), (long long)i}; }, nv,
+            sg.k_votes - 1, S, g);
+        thr = sv_key(sgm[i]);
+        thr_idx = i;
     }
-    const int64_t m = sg.m;
-    unsigned long long med = select_rth_largest([&](int64_t i) { return sv_key(eb[i]); }, m, m - 1 - (m - 1) / 2,
-                                                hist, &sh_prefix, &sh_r);
+    // lower median of E_k
+    const int im = block_select(
+        [&](int i) { return RankKey{__longlong_as_double((long long)sv_key(eb[i])), (long long)i}; }, sg.m,
+        (sg.m - 1) / 2, S, g);
     if (threadIdx.x == 0) {
         SelDev o;
         o.thr_key = thr;
         o.thr_idx = thr_idx;
-        o.nu = __longlong_as_double((long long)med) / (2.0 * sg.L - 1.0 / 3.0);
+        o.nu = __longlong_as_double((long long)sv_key(eb[im])) / (2.0 * sg.L - 1.0 / 3.0);
         o.pad = 0.0;
         sel[s] = o;
     }
@@ -803,90 +973,56 @@ __global__ __launch_bounds__(kBlock) void cs_kernel(const SigDev* __restrict__ s
 
 // ------------------------------------------------------------ output lists
 
-// keep[i] = 1 unless a general-mode signal found more than K entries, in which
-// case only the K largest |values| are kept (ties to the lower location).
-__global__ __launch_bounds__(kBlock) void keep_kernel(const SigDev* __restrict__ sigs, const int2* __restrict__ items,
-                                                      const SigCounters* __restrict__ cnt,
-                                                      const int64_t* __restrict__ st_loc,
-                                                      const double2* __restrict__ st_val,
-                                                      unsigned char* __restrict__ keep) {
-    __shared__ double smag[kBlock];
-    __shared__ int64_t sloc[kBlock];
-    const int2 it = items[blockIdx.x];
-    if (it.x < 0) return;   // padding item
-    const int s = it.x;
+// One block per signal.  General mode keeps the K entries of largest |value|
+// when more were found (ties to the lower location); the kept entries are
+// written sorted by location (locations within a signal are distinct).
+__global__ __launch_bounds__(kRankThreads) void output_kernel(const SigDev* __restrict__ sigs, const IoDev* __restrict__ io,
+                                                              SigCounters* __restrict__ cnt,
+                                                              const int64_t* __restrict__ st_loc,
+                                                              const double2* __restrict__ st_val, int* __restrict__ kidx,
+                                                              double* rk_a, long long* rk_b, int* rk_i, int* rk_r) {
+    __shared__ RankLds S;
+    __shared__ int n_kept;
+    const int s = blockIdx.x;
     const SigDev& sg = sigs[s];
-    int n = cnt[s].stage_count;
-    if (n > sg.stage_cap) n = sg.stage_cap;
-    if (it.y >= n) return;
-    const int i = it.y + threadIdx.x;
-    const bool valid = i < n;
-    if (!(sg.mode == kGeneral && n > sg.k_votes)) {
-        if (valid) keep[sg.stage_off + i] = 1;
-        return;
-    }
-    double my = 0.0;
-    int64_t myl = 0;
-    if (valid) {
-        double2 v = st_val[sg.stage_off + i];
-        my = v.x * v.x + v.y * v.y;
-        myl = st_loc[sg.stage_off + i];
-    }
-    int rank = 0;
-    for (int base = 0; base < n; base += kBlock) {
-        int j = base + threadIdx.x;
-        if (j < n) {
-            double2 v = st_val[sg.stage_off + j];
-            smag[threadIdx.x] = v.x * v.x + v.y * v.y;
-            sloc[threadIdx.x] = st_loc[sg.stage_off + j];
-        }
-        __syncthreads();
-        int lim = n - base < kBlock ? n - base : kBlock;
-        for (int q = 0; q < lim; ++q)
-            rank += (smag[q] > my || (smag[q] == my && sloc[q] < myl)) ? 1 : 0;
-        __syncthreads();
-    }
-    if (valid) keep[sg.stage_off + i] = rank < sg.k_votes ? 1 : 0;
-}
-
-// Kept entries, sorted by location (locations within a signal are distinct).
-__global__ __launch_bounds__(kBlock) void sort_kernel(const SigDev* __restrict__ sigs, const IoDev* __restrict__ io,
-                                                      const int2* __restrict__ items,
-                                                      SigCounters* __restrict__ cnt,
-                                                      const int64_t* __restrict__ st_loc,
-                                                      const double2* __restrict__ st_val,
-                                                      const unsigned char* __restrict__ keep) {
-    __shared__ int64_t sloc[kBlock];
-    const int2 it = items[blockIdx.x];
-    if (it.x < 0) return;   // padding item
-    const int s = it.x;
-    const SigDev& sg = sigs[s];
-    int n = cnt[s].stage_count;
-    if (n > sg.stage_cap) n = sg.stage_cap;
-    if (it.y > 0 && it.y >= n) return;
     const IoDev o = io[s];
-    const int i = it.y + threadIdx.x;
-    const bool mine = i < n && keep[sg.stage_off + i];
-    const int64_t myl = mine ? st_loc[sg.stage_off + i] : 0;
-    int rank = 0, kc = 0;
-    for (int base = 0; base < n; base += kBlock) {
-        int j = base + threadIdx.x;
-        __syncthreads();
-        sloc[threadIdx.x] = (j < n && keep[sg.stage_off + j]) ? st_loc[sg.stage_off + j] : INT64_MAX;
-        __syncthreads();
-        int lim = n - base < kBlock ? n - base : kBlock;
-        for (int q = 0; q < lim; ++q) {
-            rank += sloc[q] < myl ? 1 : 0;
-            kc += sloc[q] != INT64_MAX ? 1 : 0;
+    int n = cnt[s].stage_count;
+    if (n > sg.stage_cap) n = sg.stage_cap;
+    const int64_t* loc = st_loc + sg.stage_off;
+    const double2* val = st_val + sg.stage_off;
+    int* kx = kidx + sg.stage_off;
+    const RankScratch g = rank_scratch(rk_a, rk_b, rk_i, rk_r, sg.stage_off);
+    if (threadIdx.x == 0) n_kept = 0;
+    __syncthreads();
+    if (sg.mode == kGeneral && n > sg.k_votes) {
+        // the K-th entry in order of (|value| desc, location asc); keep it and all before it
+        auto key = [&](int i) {
+            const double2 v = val[i];
+            return RankKey{-(v.x * v.x + v.y * v.y), (long long)loc[i]};
+        };
+        const int ik = block_select(key, n, sg.k_votes - 1, S, g);
+        const RankKey kk = key(ik);
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const RankKey ki = key(i);
+            if (!key_less(kk.a, kk.b, ki.a, ki.b)) kx[atomicAdd(&n_kept, 1)] = i;
+        }
+    } else {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) kx[i] = i;
+        if (threadIdx.x == 0) n_kept = n;
+    }
+    __syncthreads();
+    const int nk = n_kept;
+    block_rank([&](int j) { return RankKey{0.0, (long long)loc[kx[j]]}; }, nk, S, g);
+    for (int j = threadIdx.x; j < nk; j += blockDim.x) {
+        const int r = g.rank[j];
+        if (r < o.cap) {
+            o.loc[r] = loc[kx[j]];
+            o.val[r] = val[kx[j]];
         }
     }
-    if (mine && rank < o.cap) {
-        o.loc[rank] = myl;
-        o.val[rank] = st_val[sg.stage_off + i];
-    }
-    if (it.y == 0 && threadIdx.x == 0) {
-        *o.count = kc;
-        cnt[s].kept = kc;
+    if (threadIdx.x == 0) {
+        *o.count = nk;
+        cnt[s].kept = nk;
     }
 }
 
@@ -905,17 +1041,15 @@ hipError_t launch_singular_values(const LaunchCtx& c) {
 
 hipError_t launch_select(const LaunchCtx& c) {
     if (c.n_general == 0) return hipSuccess;
-    hipLaunchKernelGGL(select_kernel, dim3(c.n_general), dim3(1024), 0, c.stream, c.sigs, c.general_sigs, c.sigma,
-                       c.ebin, c.sel);
+    hipLaunchKernelGGL(select_kernel, dim3(c.n_general), dim3(kRankThreads), 0, c.stream, c.sigs, c.general_sigs,
+                       c.sigma, c.ebin, c.sel, c.rk_a, c.rk_b, c.rk_i, c.rk_r);
     return hipGetLastError();
 }
 
 hipError_t launch_output(const LaunchCtx& c) {
-    if (c.n_out_items == 0) return hipSuccess;
-    hipLaunchKernelGGL(keep_kernel, dim3(c.n_out_items), dim3(kBlock), 0, c.stream, c.sigs, c.out_items, c.cnt,
-                       c.st_loc, c.st_val, c.keep);
-    hipLaunchKernelGGL(sort_kernel, dim3(c.n_out_items), dim3(kBlock), 0, c.stream, c.sigs, c.io, c.out_items, c.cnt,
-                       c.st_loc, c.st_val, c.keep);
+    if (c.n_sigs == 0) return hipSuccess;
+    hipLaunchKernelGGL(output_kernel, dim3(c.n_sigs), dim3(kRankThreads), 0, c.stream, c.sigs, c.io, c.cnt, c.st_loc,
+                       c.st_val, c.kidx, c.rk_a, c.rk_b, c.rk_i, c.rk_r);
     return hipGetLastError();
 }
 

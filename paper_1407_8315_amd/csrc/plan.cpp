@@ -299,11 +299,6 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
         int2{-1, 0}, lay->bin_items);
     interleave(
         [&](int s, std::vector<int2>& v) {
-            for (int64_t e = 0; e < sigs[s].m * sigs[s].L; e += kBlock) v.push_back(int2{s, (int)e});
-        },
-        int2{-1, 0}, lay->out_items);
-    interleave(
-        [&](int s, std::vector<int2>& v) {
             for (int64_t b = 0; b < sigs[s].m; b += kActivityTile) v.push_back(int2{s, (int)b});
         },
         int2{-1, 0}, lay->act_items);

@@ -28,7 +28,6 @@ struct PlanLayout {
     std::vector<int4> synd2_items;        // (sig, line0, nlines, 2): second FFT pass
     std::vector<int2> line_items;         // (sig, line) of two-pass signals
     std::vector<int2> bin_items;          // (sig, bin0)
-    std::vector<int2> out_items;          // (sig, entry0)
     std::vector<int2> act_items;          // (sig, bin0), tiles of kActivityTile
     std::vector<int> general_sigs;
     int64_t synd_elems = 0, epart_elems = 0, sigma_elems = 0, bin_elems = 0, stage_elems = 0, y_elems = 0;

@@ -184,16 +184,19 @@ sft_status enqueue(const sft_plan_s* p, hipEvent_t* events) {
     HIPCHK(launch_singular_values(c));
     HIPCHK(launch_select(c));
     HIPCHK(launch_activity(c));
-    // Round-0 queues: general-mode bins come from the vote (activity pass);
-    // exact-mode bins from the rank test, or from the predictor with the rank
-    // test for the bins it gives no order.
+    // Round-0 queues: general-mode bins come from the vote (activity pass).
+    // Exact-mode bins go through the rank test: the certificate pass settles
+    // the rank-one bins (and tries order 1 on them at once); the pending ones
+    // get the SVD pass, or in a learned plan the predictor, with the SVD pass
+    // for the bins it gives no order.
     if (any_exact) {
+        HIPCHK(launch_certify(c));
         if (use_mlp) {
             sft_status s = sft_mlp_launch_infer(p->mlp, c);
             if (s != SFT_OK) return s;
-            HIPCHK(launch_rank(c, q_round(0, 0), 0, true));
+            HIPCHK(launch_svd_rank(c, q_round(0, 0), 0));
         } else {
-            HIPCHK(launch_rank(c, -1, 0, true));
+            HIPCHK(launch_svd_rank(c, kQPending, 0));
         }
     }
     if (events) HIPCHK(hipEventRecord(events[2], p->stream));
@@ -201,7 +204,7 @@ sft_status enqueue(const sft_plan_s* p, hipEvent_t* events) {
         if (r >= 1) HIPCHK(launch_zero_set(c, (r + 1) & 1));
         HIPCHK(launch_round(c, r));
         // bins whose learned order failed: rank test, then on with round 1
-        if (r == 0 && use_mlp && p->max_l > 1) HIPCHK(launch_rank(c, q_round(1, 0), 1, false));
+        if (r == 0 && use_mlp && p->max_l > 1) HIPCHK(launch_svd_rank(c, q_round(1, 0), 1));
     }
     HIPCHK(launch_cs(c));
     if (events) HIPCHK(hipEventRecord(events[3], p->stream));

@@ -68,16 +68,20 @@ struct SigCounters {
 // signals end in the CS queue of their vote order.  Besides these, the active
 // list holds the active bins of exact-mode signals (rank test or predictor
 // input).
+// The rank test itself runs in two passes: a certificate pass settles the
+// rank-one bins (and tries their order 1 at once) and queues the others as
+// pending, for the SVD pass (or, in a learned plan, for the predictor).
 constexpr int kRoundSlots = kMaxL + 1;
-constexpr int kQueues = 2 * kRoundSlots + kMaxL;
+constexpr int kQueues = 2 * kRoundSlots + kMaxL + 1;
 __host__ __device__ constexpr int q_round(int set, int slot) { return set * kRoundSlots + slot; }
 __host__ __device__ constexpr int q_cs(int a0) { return 2 * kRoundSlots + a0 - 1; }
+constexpr int kQPending = 2 * kRoundSlots + kMaxL;
 
 struct WorkCounters {
     int n_active;
     int q[kQueues];   // lengths of the queues above
-    int pad[16 - 1 - kQueues];
 };
+static_assert(sizeof(WorkCounters) == 16 * sizeof(int), "WorkCounters holds 16 counters");
 
 // A list entry is (signal, code): code = k << 9 | step << 6 | ap << 3 | a0 with
 // bin k (< 2^22), index `step` of the bin's next hypothesis in its order
@@ -221,7 +225,8 @@ hipError_t launch_syndromes(const LaunchCtx& c);
 hipError_t launch_singular_values(const LaunchCtx& c);
 hipError_t launch_select(const LaunchCtx& c);
 hipError_t launch_activity(const LaunchCtx& c);
-hipError_t launch_rank(const LaunchCtx& c, int q_in, int set_out, bool fuse);   // q_in < 0: the active list
+hipError_t launch_certify(const LaunchCtx& c);                           // active list -> order 1 tried, or pending
+hipError_t launch_svd_rank(const LaunchCtx& c, int q_in, int set_out);   // rank test by SVD
 hipError_t launch_zero_set(const LaunchCtx& c, int set);
 hipError_t launch_round(const LaunchCtx& c, int round);
 hipError_t launch_cs(const LaunchCtx& c);

@@ -800,23 +800,72 @@ __global__ __launch_bounds__(kBlock) void activity_kernel(const SigDev* __restri
     }
 }
 
-// Rank test of exact-mode bins (Pruning Step 1 analogue of the exact case):
-// a0 = #{sigma_i > tau_rank sigma_1} of the L x L Hankel matrix, through the
-// rank-one certificate when it applies and the Jacobi SVD otherwise.  The bin
-// is queued in set `set_out` at its next order.  With `fuse`, a bin whose
-// next order is 1 (the common case) is tried here at once; a rejected one
-// goes to the next round's set.
+// Rank test of exact-mode bins (the exact-case analogue of Pruning Step 1):
+// a0 = #{sigma_i > tau_rank sigma_1} of the L x L Hankel matrix.
+//
+// Certificate pass, over the active list: a bin the rank-one certificate
+// settles (a0 = 1, so order 1 comes first) is tried at order 1 at once:
+// emitted, or queued for round 1 at its next order.  The other bins are
+// queued as pending: every lane of this pass runs the same short code.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void rank_kernel(const SigDev* __restrict__ sigs, const int64_t* __restrict__ shifts,
-                                                      const typename V2<T>::type* __restrict__ synd,
-                                                      const double2* __restrict__ tab, SigCounters* __restrict__ cnt,
-                                                      int64_t* __restrict__ st_loc, double2* __restrict__ st_val,
-                                                      WorkCounters* __restrict__ work, int2* __restrict__ active,
-                                                      int2* __restrict__ qlist, int64_t list_cap, int q_in, int set_out,
-                                                      int fuse) {
+__global__ __launch_bounds__(kBlock) void certify_kernel(const SigDev* __restrict__ sigs,
+                                                         const typename V2<T>::type* __restrict__ synd,
+                                                         const double2* __restrict__ tab, SigCounters* __restrict__ cnt,
+                                                         int64_t* __restrict__ st_loc, double2* __restrict__ st_val,
+                                                         WorkCounters* __restrict__ work, int2* __restrict__ active,
+                                                         int2* __restrict__ qlist, int64_t list_cap) {
     __shared__ BlockQueues bq;
-    const int total = *queue_counter(work, q_in);
-    const int2* in = queue_list(active, qlist, list_cap, q_in);
+    const int total = work->n_active;
+    for (int base0 = blockIdx.x * kBlock; base0 < total; base0 += gridDim.x * kBlock) {
+        bq.reset();
+        const int item = base0 + threadIdx.x;
+        int q = -1;
+        int2 ent{0, 0};
+        if (item < total) {
+            const int2 en = active[item];
+            const int s = en.x;
+            const int64_t k = code_k(en.y);
+            const SigDev& sg = sigs[s];
+            const int L = sg.L;
+            zd mt[2 * kMaxL];
+            load_raw<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, 2 * L, mt);
+            double e = 0.0;
+#pragma unroll
+            for (int l = 0; l < 2 * kMaxL; ++l) e += norm2(mt[l]);   // zero beyond 2L
+            derotate_consecutive<2 * kMaxL>(mt, k, sg.n, 2 * L);
+            if (rank_one_certified(mt, L, sg.tau_rank)) {
+                BinOut o;
+                o.n = 0;
+                if (try_order(mt, L, 1, e, 0.0, sg, tab, o)) {
+                    emit(sg, &cnt[s], k, o, st_loc, st_val);
+                } else if (L > 1) {
+                    q = q_round(1, order_at(1, L, 1));
+                    ent = int2{s, pack_code(k, 1, 0, 1)};
+                } else {
+                    wave_count(&cnt[s].flagged, true);
+                }
+            } else {
+                q = kQPending;
+                ent = int2{s, pack_code(k, 0, 0, 0)};
+            }
+        }
+        const int slot = bq.reserve(q);
+        bq.commit(work, active, qlist, list_cap, q, slot, ent);
+    }
+}
+
+// SVD pass: a0 from the Jacobi singular values, for the bins of queue q_in;
+// each bin goes to set `set_out` at the order of its current step (the
+// learned order, when given, stays first in its sequence).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void svd_rank_kernel(const SigDev* __restrict__ sigs,
+                                                          const typename V2<T>::type* __restrict__ synd,
+                                                          WorkCounters* __restrict__ work, int2* __restrict__ active,
+                                                          int2* __restrict__ qlist, int64_t list_cap, int q_in,
+                                                          int set_out) {
+    __shared__ BlockQueues bq;
+    const int total = work->q[q_in];
+    const int2* in = qlist + (int64_t)q_in * list_cap;
     for (int base0 = blockIdx.x * kBlock; base0 < total; base0 += gridDim.x * kBlock) {
         bq.reset();
         const int item = base0 + threadIdx.x;
@@ -832,32 +881,12 @@ __global__ __launch_bounds__(kBlock) void rank_kernel(const SigDev* __restrict__
             const int L = sg.L;
             zd mt[2 * kMaxL];
             load_raw<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, 2 * L, mt);
-            double e = 0.0;
-#pragma unroll
-            for (int l = 0; l < 2 * kMaxL; ++l) e += norm2(mt[l]);   // zero beyond 2L
             derotate_consecutive<2 * kMaxL>(mt, k, sg.n, 2 * L);
-            int a0 = 1;
-            if (!rank_one_certified(mt, L, sg.tau_rank)) {
-                double sv[kMaxL];
-                hankel_singular_values(mt, L, sv);
-                a0 = rank_order(sv, L, sg.tau_rank);
-            }
-            const int a = seq_order(a0, ap, L, step);
-            if (fuse && a == 1) {
-                BinOut o;
-                o.n = 0;
-                if (try_order(mt, L, 1, e, 0.0, sg, tab, o)) {
-                    emit(sg, &cnt[s], k, o, st_loc, st_val);
-                } else if (step + 1 < L) {
-                    q = q_round(set_out ^ 1, seq_order(a0, ap, L, step + 1));
-                    ent = int2{s, pack_code(k, step + 1, ap, a0)};
-                } else {
-                    wave_count(&cnt[s].flagged, true);
-                }
-            } else {
-                q = q_round(set_out, a);
-                ent = int2{s, pack_code(k, step, ap, a0)};
-            }
+            double sv[kMaxL];
+            hankel_singular_values(mt, L, sv);
+            const int a0 = rank_order(sv, L, sg.tau_rank);
+            q = q_round(set_out, seq_order(a0, ap, L, step));
+            ent = int2{s, pack_code(k, step, ap, a0)};
         }
         const int slot = bq.reserve(q);
         bq.commit(work, active, qlist, list_cap, q, slot, ent);
@@ -1061,17 +1090,27 @@ hipError_t launch_activity(const LaunchCtx& c) {
     return hipGetLastError();
 }
 
-hipError_t launch_rank(const LaunchCtx& c, int q_in, int set_out, bool fuse) {
+hipError_t launch_certify(const LaunchCtx& c) {
     if (c.n_bin_items == 0) return hipSuccess;
-    const int q = q_in < 0 ? kQueues : q_in;
     if (c.fp64)
-        hipLaunchKernelGGL(rank_kernel<double>, dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs, c.shifts,
+        hipLaunchKernelGGL(certify_kernel<double>, dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs,
                            (const double2*)c.synd, c.omega, c.cnt, c.st_loc, c.st_val, c.work, c.active_list, c.qlist,
-                           c.list_cap, q, set_out, (int)fuse);
+                           c.list_cap);
     else
-        hipLaunchKernelGGL(rank_kernel<float>, dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs, c.shifts,
+        hipLaunchKernelGGL(certify_kernel<float>, dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs,
                            (const float2*)c.synd, c.omega, c.cnt, c.st_loc, c.st_val, c.work, c.active_list, c.qlist,
-                           c.list_cap, q, set_out, (int)fuse);
+                           c.list_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_svd_rank(const LaunchCtx& c, int q_in, int set_out) {
+    if (c.n_bin_items == 0) return hipSuccess;
+    if (c.fp64)
+        hipLaunchKernelGGL(svd_rank_kernel<double>, dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs,
+                           (const double2*)c.synd, c.work, c.active_list, c.qlist, c.list_cap, q_in, set_out);
+    else
+        hipLaunchKernelGGL(svd_rank_kernel<float>, dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs,
+                           (const float2*)c.synd, c.work, c.active_list, c.qlist, c.list_cap, q_in, set_out);
     return hipGetLastError();
 }
 

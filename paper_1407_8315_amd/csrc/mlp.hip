@@ -256,10 +256,11 @@ __device__ inline v4f infer_rows(const WeightsLds& W, const bf16* X, int r0, bf1
 constexpr int kInferWaves = 8;
 constexpr int kInferTile = 64 * kInferWaves;   // rows per block trip: one per thread
 
-// Learned orders for the active list (exact mode, L = 4): each thread builds
-// the features of one bin, each wave runs the network on 64 rows (4 MFMA row
-// tiles), and the bin is queued for round 0 at its predicted order (or for
-// the rank test when the prediction is 0, i.e. outside 1..L).
+// Learned orders for the bins the rank-one certificate left pending (exact
+// mode, L = 4): each thread builds the features of one bin, each wave runs
+// the network on 64 rows (4 MFMA row tiles), and the bin is queued for round
+// 0 at its predicted order (or for the SVD rank test when the prediction is
+// 0, i.e. outside 1..L).
 template <typename T>
 __global__ __launch_bounds__(kInferTile) void infer_kernel(LaunchCtx c, const bf16* __restrict__ wimg,
                                                            const float* __restrict__ theta) {
@@ -270,7 +271,8 @@ __global__ __launch_bounds__(kInferTile) void infer_kernel(LaunchCtx c, const bf
     __shared__ signed char pred[kInferTile];
     __shared__ BlockQueues bq;
     load_weights(W, wimg, theta);
-    const int total = c.work->n_active;
+    const int total = c.work->q[kQPending];
+    const int2* in = c.qlist + (int64_t)kQPending * c.list_cap;
     const typename VT<T>::type* synd = (const typename VT<T>::type*)c.synd;
     const int w = threadIdx.x >> 6, lane = __lane_id();
     for (int base = blockIdx.x * kInferTile; base < total; base += gridDim.x * kInferTile) {
@@ -282,7 +284,7 @@ __global__ __launch_bounds__(kInferTile) void infer_kernel(LaunchCtx c, const bf
 #pragma unroll
         for (int i = 0; i < kNF; ++i) f[i] = 0.0f;
         if (item < total) {
-            const int2 en = c.active_list[item];
+            const int2 en = in[item];
             s = en.x;
             k = code_k(en.y);
             const SigDev& sg = c.sigs[s];

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define SFT_ABI_VERSION 1
+#define SFT_ABI_VERSION 2
 #define SFT_MAX_RSHIFTS 64
 
 typedef enum sft_status {
@@ -63,7 +63,8 @@ enum { SFT_MODE_EXACT = 0, SFT_MODE_GENERAL = 1 };  /* Sec. II (exactly K-sparse
 enum {
     SFT_FLAG_LEARNED = 1u,       /* order estimate from the attached MLP; rank test as fallback */
     SFT_FLAG_SYNC = 2u,          /* synchronise at the end of each call */
-    SFT_FLAG_CHECK_FINITE = 4u   /* count non-finite gathered samples; report SFT_E_NONFINITE (sync calls) */
+    SFT_FLAG_CHECK_FINITE = 4u,  /* count non-finite gathered samples; report SFT_E_NONFINITE (sync calls) */
+    SFT_FLAG_AUTOTUNE = 8u       /* exact mode: M and L chosen by sft_autotune (m and l must be 0) */
 };
 
 /* Parameters of one signal.  Zero means "default" for m, l, r and every
@@ -87,6 +88,8 @@ typedef struct sft_params {
     uint32_t reserved;  /* must be 0 */
     uint64_t seed;      /* seed of the random shifts n_j (general mode) */
     double tau_zero, tau_rank, tau_res, tau_amp, c_res, delta_grid, delta_mag;
+    double target_recovery;  /* SFT_FLAG_AUTOTUNE: expected fraction of the K frequencies
+                                recovered, in (0, 1); 0 = 0.999 */
 } sft_params;
 
 /* A sparse output list.  loc_dev: int64[capacity] locations in [0, N), sorted
@@ -214,6 +217,25 @@ sft_status sft_plan_attach_mlp(sft_plan_t plan, sft_mlp_t mlp);
  * written).  Rows come in no particular order.  Asynchronous. */
 sft_status sft_features(sft_plan_t plan, const void* x_dev, float* feat_dev, int64_t* bins_dev, int64_t capacity,
                         int64_t* count_dev);
+
+/* Choice of M and L for an exact-mode signal of length n with k frequencies
+ * (host only, no device needed; what SFT_FLAG_AUTOTUNE plans use).
+ *
+ * Model: a frequency is recovered when its bin holds at most L of the K
+ * frequencies (the decoder is exact there, the non-iterative case of Sec. II,
+ * with the aliasing probabilities of Theorem 1 and Lemma 2); the number of
+ * other frequencies in its bin is hypergeometric (K - 1 drawn from the N - 1
+ * other positions, d - 1 of which share the bin).
+ * Among L = 1..4 and M = N/d (power of two, 2L <= d, M within the supported
+ * range) it returns the pair of least modelled device time whose expected
+ * recovery reaches `target` (0 = 0.999), or, when none does, the pair of
+ * highest expected recovery.  The time model (gather + FFT per line sample,
+ * decoder per active and per aliased bin) carries constants measured on
+ * MI355X.  expected_recovery and model_us (nullable) receive the chosen
+ * pair's figures.  SFT_E_INVALID for n not a power of two >= 2, k outside
+ * 1..n, in_dtype not SFT_C64/SFT_C128 or target outside [0, 1). */
+sft_status sft_autotune(int64_t n, int64_t k, int32_t in_dtype, double target, int64_t* m_out, int32_t* l_out,
+                        double* expected_recovery, double* model_us);
 
 /* Parameters the plan chose for signal `index` (0-based). */
 sft_status sft_plan_get(sft_plan_t plan, int64_t index, sft_plan_info* info);

@@ -16,17 +16,30 @@ import dataclasses
 from . import _lib
 from ._lib import (  # noqa: F401
     SFT_C64, SFT_C128, SFT_MODE_EXACT, SFT_MODE_GENERAL,
-    SFT_FLAG_LEARNED, SFT_FLAG_SYNC, SFT_FLAG_CHECK_FINITE, SftError,
+    SFT_FLAG_LEARNED, SFT_FLAG_SYNC, SFT_FLAG_CHECK_FINITE, SFT_FLAG_AUTOTUNE, SftError,
 )
 
-__all__ = ["Plan", "Result", "SftError", "Mlp", "make_params", "library_path"]
+__all__ = ["Plan", "Result", "SftError", "Mlp", "make_params", "library_path", "autotune"]
 
 
 def library_path() -> str:
     return _lib.LIB_PATH
 
 
-def make_params(n, k, m=0, l=0, r=0, dtype="c64", mode="exact", flags=0, seed=0, **taus) -> _lib.Params:
+def autotune(n, k, dtype="c64", target=0.0):
+    """(M, L, expected recovery, modelled microseconds) chosen for an exact-mode
+    signal of length n with k frequencies (host only; see sft_autotune)."""
+    lib = _lib.load()
+    m, l = ctypes.c_int64(), ctypes.c_int32()
+    rec, us = ctypes.c_double(), ctypes.c_double()
+    _lib.check(lib.sft_autotune(int(n), int(k), {"c64": SFT_C64, "c128": SFT_C128}[dtype], float(target),
+                                ctypes.byref(m), ctypes.byref(l), ctypes.byref(rec), ctypes.byref(us)),
+               "sft_autotune")
+    return int(m.value), int(l.value), float(rec.value), float(us.value)
+
+
+def make_params(n, k, m=0, l=0, r=0, dtype="c64", mode="exact", flags=0, seed=0, target_recovery=0.0,
+                **taus) -> _lib.Params:
     p = _lib.Params()
     p.n, p.k, p.m, p.l, p.r = int(n), int(k), int(m), int(l), int(r)
     p.in_dtype = {"c64": SFT_C64, "c128": SFT_C128}[dtype]
@@ -34,6 +47,7 @@ def make_params(n, k, m=0, l=0, r=0, dtype="c64", mode="exact", flags=0, seed=0,
     p.flags = int(flags)
     p.reserved = 0
     p.seed = int(seed) & ((1 << 64) - 1)
+    p.target_recovery = float(target_recovery)
     for name in ("tau_zero", "tau_rank", "tau_res", "tau_amp", "c_res", "delta_grid", "delta_mag"):
         setattr(p, name, float(taus.pop(name, 0.0)))
     if taus:

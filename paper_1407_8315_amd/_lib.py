@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(_HERE, "libsft.so")
 SFT_OK, SFT_E_INVALID, SFT_E_UNSUPPORTED, SFT_E_NOMEM, SFT_E_DEVICE, SFT_E_CAPACITY, SFT_E_NONFINITE = range(7)
 SFT_C64, SFT_C128 = 1, 2
 SFT_MODE_EXACT, SFT_MODE_GENERAL = 0, 1
-SFT_FLAG_LEARNED, SFT_FLAG_SYNC, SFT_FLAG_CHECK_FINITE = 1, 2, 4
+SFT_FLAG_LEARNED, SFT_FLAG_SYNC, SFT_FLAG_CHECK_FINITE, SFT_FLAG_AUTOTUNE = 1, 2, 4, 8
 SFT_MAX_RSHIFTS = 64
 
 # Every symbol the header declares (checked by the CPU test suite).
@@ -20,6 +20,7 @@ EXPORTS = [
     "sft_status_str", "sft_last_error", "sft_abi_version",
     "sft_mlp_create", "sft_mlp_destroy", "sft_mlp_get_params", "sft_mlp_set_params", "sft_mlp_forward",
     "sft_mlp_grad", "sft_mlp_train_step", "sft_mlp_last_error", "sft_plan_attach_mlp", "sft_features",
+    "sft_autotune",
 ]
 MLP_FEATURES, MLP_CLASSES, MLP_PARAMS = 32, 5, 21381
 
@@ -31,7 +32,7 @@ class Params(ctypes.Structure):
         ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("seed", ctypes.c_uint64),
         ("tau_zero", ctypes.c_double), ("tau_rank", ctypes.c_double), ("tau_res", ctypes.c_double),
         ("tau_amp", ctypes.c_double), ("c_res", ctypes.c_double), ("delta_grid", ctypes.c_double),
-        ("delta_mag", ctypes.c_double),
+        ("delta_mag", ctypes.c_double), ("target_recovery", ctypes.c_double),
     ]
 
 
@@ -100,6 +101,10 @@ def load():
     lib.sft_last_error.restype = ctypes.c_char_p
     lib.sft_abi_version.argtypes = []
     lib.sft_abi_version.restype = ctypes.c_int32
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.sft_autotune.argtypes = [i64, i64, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(i64),
+                                 ctypes.POINTER(ctypes.c_int32), dp, dp]
+    lib.sft_autotune.restype = st
     fp = ctypes.POINTER(ctypes.c_float)
     lib.sft_mlp_create.argtypes = [ctypes.POINTER(vp), ctypes.c_uint64, vp]
     lib.sft_mlp_destroy.argtypes = [vp]

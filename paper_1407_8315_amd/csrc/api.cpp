@@ -294,6 +294,17 @@ extern "C" {
 
 int32_t sft_abi_version(void) { return SFT_ABI_VERSION; }
 
+sft_status sft_autotune(int64_t n, int64_t k, int32_t in_dtype, double target, int64_t* m_out, int32_t* l_out,
+                        double* expected_recovery, double* model_us) {
+    if (!m_out || !l_out) return fail(SFT_E_INVALID, "m_out and l_out must not be NULL");
+    std::string msg;
+    int l = 0;
+    sft_status st = autotune(n, k, in_dtype, target, m_out, &l, expected_recovery, model_us, &msg);
+    if (st != SFT_OK) return fail(st, msg);
+    *l_out = l;
+    return SFT_OK;
+}
+
 const char* sft_last_error(void) { return g_err.c_str(); }
 
 const char* sft_status_str(sft_status s) {

@@ -59,6 +59,89 @@ std::vector<int64_t> draw_shifts(uint64_t seed, int64_t d, int r) {
     return std::vector<int64_t>(got.begin(), got.end());
 }
 
+// ---------------------------------------------------------------- autotuner
+
+// Expected fraction of the K frequencies recovered in exact mode with
+// (M, L): it is recovered when at most L - 1 of the others share its bin.
+// Their number is hypergeometric: K - 1 drawn from the N - 1 other positions,
+// d - 1 of which lie in the bin.
+double expected_recovery(int64_t n, int64_t k, int64_t m, int l) {
+    const int64_t d = n / m;
+    const int64_t draws = k - 1, good = d - 1, pop = n - 1;
+    auto lchoose = [](double a, double b) { return std::lgamma(a + 1.0) - std::lgamma(b + 1.0) - std::lgamma(a - b + 1.0); };
+    const double ltot = lchoose((double)pop, (double)draws);
+    double sum = 0.0;
+    for (int64_t j = 0; j < l; ++j) {
+        if (j > good || j > draws || draws - j > pop - good) continue;
+        sum += std::exp(lchoose((double)good, (double)j) + lchoose((double)(pop - good), (double)(draws - j)) - ltot);
+    }
+    return std::min(1.0, sum);
+}
+
+// Modelled device time (microseconds) of one signal in a large batch on
+// MI355X.  Gather + FFT: per line sample (2L lines of M samples), twice that
+// when M needs two FFT passes through HBM, doubled again for complex128;
+// decoder: per active bin (certificate, order-1 try) and per bin holding two
+// or more frequencies (SVD rank test, higher orders).  The constants come from
+// the exact-mode batch (N = 2^20, K = 1000, M = 4096, L = 4, 1024 signals):
+// 0.39 ms for 33.5M line samples, 0.49 ms for 0.91M active bins.
+constexpr double kUsPerLineSample = 1.16e-5;
+constexpr double kUsPerActiveBin = 5.4e-4;
+constexpr double kUsPerAliasedBin = 2.0e-3;
+
+double model_us(int64_t n, int64_t k, int64_t m, int l, int dtype) {
+    (void)n;
+    double g = kUsPerLineSample * 2.0 * l * (double)m;
+    if (m > one_pass_m(dtype)) g *= 2.0;
+    if (dtype == SFT_C128) g *= 2.0;
+    const double lam = (double)k / (double)m;
+    const double active = (double)m * -std::expm1(-lam);
+    const double aliased = (double)m * (1.0 - std::exp(-lam) * (1.0 + lam));
+    return g + kUsPerActiveBin * active + kUsPerAliasedBin * aliased;
+}
+
+sft_status autotune(int64_t n, int64_t k, int dtype, double target, int64_t* m_out, int* l_out, double* rec_out,
+                    double* us_out, std::string* msg) {
+    if (n < 2 || !is_pow2(n) || n > (int64_t(1) << 40) || k < 1 || k > n || (dtype != SFT_C64 && dtype != SFT_C128) ||
+        !(target >= 0.0 && target < 1.0)) {
+        *msg = "autotune needs N a power of two >= 2, 1 <= K <= N, a known dtype and a target in [0, 1)";
+        return SFT_E_INVALID;
+    }
+    if (target == 0.0) target = 0.999;
+    int64_t best_m = 0, top_m = 0;
+    int best_l = 0, top_l = 0;
+    double best_us = 0.0, top_rec = -1.0;
+    for (int l = 1; l <= kMaxL; ++l)
+        for (int64_t m = 2; m <= n && m <= max_m(dtype); m <<= 1) {
+            const int64_t d = n / m;
+            if (d < 2 * l || d > kMaxD) continue;
+            const double rec = expected_recovery(n, k, m, l), us = model_us(n, k, m, l, dtype);
+            if (rec > top_rec || (rec == top_rec && us < model_us(n, k, top_m, top_l, dtype))) {
+                top_rec = rec;
+                top_m = m;
+                top_l = l;
+            }
+            if (rec >= target && (best_m == 0 || us < best_us)) {
+                best_us = us;
+                best_m = m;
+                best_l = l;
+            }
+        }
+    if (best_m == 0) {
+        if (top_m == 0) {
+            *msg = "no admissible (M, L) for this N";
+            return SFT_E_UNSUPPORTED;
+        }
+        best_m = top_m;
+        best_l = top_l;
+    }
+    *m_out = best_m;
+    *l_out = best_l;
+    if (rec_out) *rec_out = expected_recovery(n, k, best_m, best_l);
+    if (us_out) *us_out = model_us(n, k, best_m, best_l, dtype);
+    return SFT_OK;
+}
+
 sft_status resolve_params(const sft_params& in, bool batch, SigHost* g, std::string* msg) {
     (void)batch;
     if (in.reserved != 0) {
@@ -81,7 +164,7 @@ sft_status resolve_params(const sft_params& in, bool batch, SigHost* g, std::str
         *msg = "N must be a power of two (at most 2^40)";
         return SFT_E_UNSUPPORTED;
     }
-    const uint32_t known = SFT_FLAG_LEARNED | SFT_FLAG_SYNC | SFT_FLAG_CHECK_FINITE;
+    const uint32_t known = SFT_FLAG_LEARNED | SFT_FLAG_SYNC | SFT_FLAG_CHECK_FINITE | SFT_FLAG_AUTOTUNE;
     if (in.flags & ~known) {
         *msg = "unknown flag bits";
         return SFT_E_INVALID;
@@ -96,12 +179,25 @@ sft_status resolve_params(const sft_params& in, bool batch, SigHost* g, std::str
     g->mode = in.mode;
     g->flags = in.flags;
     g->seed = in.seed;
-    g->L = in.l == 0 ? 4 : in.l;
+    int64_t m_in = in.m;
+    int l_in = in.l;
+    if (in.flags & SFT_FLAG_AUTOTUNE) {
+        if (in.mode != SFT_MODE_EXACT || in.m != 0 || in.l != 0 || (in.flags & SFT_FLAG_LEARNED)) {
+            *msg = "SFT_FLAG_AUTOTUNE applies to SFT_MODE_EXACT plans with m = 0 and l = 0 (not learned)";
+            return SFT_E_INVALID;
+        }
+        sft_status st = autotune(in.n, in.k, in.in_dtype, in.target_recovery, &m_in, &l_in, nullptr, nullptr, msg);
+        if (st != SFT_OK) return st;
+    } else if (in.target_recovery != 0.0) {
+        *msg = "target_recovery applies to SFT_FLAG_AUTOTUNE plans only";
+        return SFT_E_INVALID;
+    }
+    g->L = l_in == 0 ? 4 : l_in;
     if (g->L < 1 || g->L > kMaxL) {
         *msg = "L must be in 1..4";
         return SFT_E_UNSUPPORTED;
     }
-    g->m = in.m == 0 ? default_m(in.n, in.k, in.in_dtype) : in.m;
+    g->m = m_in == 0 ? default_m(in.n, in.k, in.in_dtype) : m_in;
     if (!is_pow2(g->m) || g->m > in.n) {
         *msg = "M must be a power of two dividing N";
         return SFT_E_UNSUPPORTED;

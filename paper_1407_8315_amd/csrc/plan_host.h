@@ -40,6 +40,10 @@ int64_t max_m(int dtype);
 int64_t one_pass_m(int dtype);
 
 // Fill defaults and validate one parameter set.
+double expected_recovery(int64_t n, int64_t k, int64_t m, int l);
+double model_us(int64_t n, int64_t k, int64_t m, int l, int dtype);
+sft_status autotune(int64_t n, int64_t k, int dtype, double target, int64_t* m_out, int* l_out, double* rec_out,
+                    double* us_out, std::string* msg);
 sft_status resolve_params(const sft_params& in, bool batch, SigHost* out, std::string* msg);
 
 // Default M for K: 4K rounded up to a power of two, at most N (Sec. II-E's

@@ -41,7 +41,7 @@ def test_every_declared_function_is_exported(lib):
 def test_version_and_status_strings(lib):
     from paper_1407_8315_amd import _lib
 
-    assert lib.sft_abi_version() == 1
+    assert lib.sft_abi_version() == 2
     assert lib.sft_status_str(_lib.SFT_E_CAPACITY) == b"SFT_E_CAPACITY"
     assert lib.sft_status_str(99) == b"unknown status"
 
@@ -92,6 +92,10 @@ def _plan_status(lib, **kw):
     (dict(n=1 << 14, k=50, mode="general", r=40), "SFT_E_UNSUPPORTED"),
     (dict(n=1 << 14, k=50, flags=64), "SFT_E_INVALID"),        # unknown flag
     (dict(n=1 << 14, k=50, tau_res=-1.0), "SFT_E_INVALID"),
+    (dict(n=1 << 14, k=50, m=128, flags=8), "SFT_E_INVALID"),                 # autotune with a fixed M
+    (dict(n=1 << 14, k=50, mode="general", flags=8), "SFT_E_INVALID"),        # autotune in general mode
+    (dict(n=1 << 14, k=50, target_recovery=0.99), "SFT_E_INVALID"),           # target without autotune
+    (dict(n=1 << 14, k=50, flags=8, target_recovery=1.5), "SFT_E_INVALID"),   # target outside [0, 1)
 ])
 def test_parameter_validation(lib, kw, status):
     st, h = _plan_status(lib, **kw)

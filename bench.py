@@ -79,17 +79,19 @@ def learned_vs_plain(steps, warmup, B=1024):
             if flags:
                 plan.attach(net)
             outs = [plan.new_output(m * L, dev) for _ in range(B)]
+            run = plan.prepare_batch(xs, outs)
             for _ in range(warmup):
-                plan.batch(xs, outs)
+                run()
+            torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
             for _ in range(steps):
-                plan.batch(xs, outs)
+                run()
             e1.record(stream)
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / steps
             found = sum(len(np.intersect1d(o.loc[:int(o.count.item())].cpu().numpy(), t)) for o, t in zip(outs, truth))
-            st = plan.batch(xs, outs, stats=True)[0].stats
+            st = run(stats=True)
             out[name] = {"ms_per_step": round(ms, 4), "signals_per_s": round(B / ms * 1e3, 1),
                          "freqs_per_s": round(found / ms * 1e3, 1), "support_recovery": round(found / (B * k), 5),
                          "stage_ms": [round(v, 4) for v in st["stage_ms"]], "mlp_fallbacks": st["mlp_fallbacks"],
@@ -130,19 +132,21 @@ def uneven_batch(steps, warmup, count=4096):
         t_plan = time.time() - t1
         caps = [inf["m"] * inf["l"] for inf in plan.infos]
         outs = [plan.new_output(c, dev) for c in caps]
+        run = plan.prepare_batch(xs, outs, caps)
         for _ in range(warmup):
-            plan.batch(xs, outs)
+            run()
+        torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(steps):
-            plan.batch(xs, outs)
+            run()
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         found = 0
         for o, t in zip(outs, truth):
             found += len(np.intersect1d(o.loc[:int(o.count.item())].cpu().numpy(), t))
-        st = plan.batch(xs, outs, stats=True)[0].stats
+        st = run(stats=True)
         tune = [autotune(n, k) for n, k in zip(ns.tolist(), ks.tolist())]
         ms_choices = sorted({(inf["m"], inf["l"]) for inf in plan.infos})
         plan.close()
@@ -201,14 +205,15 @@ def main():
         plan = Plan(params, stream=stream)
         caps = [m * L] * B
         outs = [plan.new_output(c, dev) for c in caps]
+        run = plan.prepare_batch(xs, outs, caps)
         for _ in range(a.warmup):
-            plan.batch(xs, outs, caps)
+            run()
         torch.cuda.synchronize()
         # ---- timed region 1: graph-replayed steps
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
         for _ in range(a.steps):
-            plan.batch(xs, outs, caps)
+            run()
         ev1.record(stream)
         torch.cuda.synchronize()
         ms_step = ev0.elapsed_time(ev1) / a.steps
@@ -222,8 +227,7 @@ def main():
         stage = np.zeros(4)
         st = None
         for _ in range(a.steps):
-            r = plan.batch(xs, outs, caps, stats=True)
-            st = r[0].stats
+            st = run(stats=True)
             stage += np.array(st["stage_ms"])
         stage /= a.steps
     signals_per_s = B / (ms_step * 1e-3)

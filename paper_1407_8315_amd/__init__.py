@@ -180,6 +180,29 @@ class Plan:
         self._keep = (xarr, oarr)      # keep the argument arrays alive until the next call
         return outs
 
+    def prepare_batch(self, xs, outs, capacities=None):
+        """Bind fixed inputs and outputs once; returns run(stats=False), which
+        calls sft_batch on them (no per-call argument marshalling: for timing
+        loops over large batches)."""
+        if len(xs) != self.n_signals:
+            raise ValueError(f"expected {self.n_signals} signals")
+        for i, x in enumerate(xs):
+            self._check_input(x, i)
+        if capacities is None:
+            capacities = [self.default_capacity(i) for i in range(self.n_signals)]
+        xarr = (ctypes.c_void_p * len(xs))(*[x.data_ptr() for x in xs])
+        oarr = (_lib.SparseOut * len(xs))(*[self._out_struct(o, c) for o, c in zip(outs, capacities)])
+        keep = (xs, outs, xarr, oarr)
+
+        def run(stats=False):
+            st = _lib.Stats() if stats else None
+            status = self._lib.sft_batch(self._h, keep[2], keep[3], ctypes.byref(st) if st is not None else None)
+            if status != _lib.SFT_E_CAPACITY:
+                _lib.check(status, "sft_batch")
+            return st.as_dict() if st is not None else None
+
+        return run
+
     def syndromes(self, x):
         """Steps 1-2 only: the [S, M] syndromes of a single-signal plan (device tensor)."""
         torch = _torch()

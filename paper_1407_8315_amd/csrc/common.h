@@ -23,6 +23,7 @@ constexpr int kMaxLines = 2 * kMaxL + 64;   // 2L consecutive + up to 64 random 
 constexpr int kBlock = 256;                 // threads per block of every kernel but select
 constexpr int kFftPointsF32 = 8192;         // points per block in LDS (64 KiB)
 constexpr int kFftPointsF64 = 4096;
+constexpr int kFftPointsF32Small = 4096;     // blocks of FP32 signals with M <= this (32 KiB)
 constexpr int kActivityTile = 4096;         // bins per block of the activity pass
 
 enum Mode { kExact = 0, kGeneral = 1 };
@@ -195,6 +196,8 @@ struct LaunchCtx {
     int om_log2;
     const int4* synd_items;  // (sig, line0, nlines, pass): pass 0 one-pass, 1 first of two
     int n_synd_items;
+    const int4* synd_small_items;   // pass 0 items of FP32 signals with M <= kFftPointsF32Small
+    int n_synd_small_items;
     const int4* synd2_items; // second pass of two-pass signals (pass 2)
     int n_synd2_items;
     void* ybuf;              // two-pass intermediate (float2* / double2*)

@@ -264,25 +264,29 @@ __device__ void block_rank(KeyFn key, int n, RankLds& S, const RankScratch& g) {
         __syncthreads();
     }
     if (nch == 1) return;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int c = i / kRankChunk;
-        const double a = g.a[i];
-        const long long b = g.b[i];
-        int r = i - c * kRankChunk;
-        for (int c2 = 0; c2 < nch; ++c2) {
-            if (c2 == c) continue;
-            int lo = c2 * kRankChunk, hi = min(n, lo + kRankChunk);
-            const int base = lo;
+    // each sorted chunk in turn back in LDS; every key of the other chunks
+    // adds the count of that chunk's keys below it (binary search in LDS)
+    for (int c2 = 0; c2 < nch; ++c2) {
+        const int c0 = c2 * kRankChunk, cn = min(kRankChunk, n - c0);
+        for (int i = threadIdx.x; i < cn; i += blockDim.x) {
+            S.a[i] = g.a[c0 + i];
+            S.b[i] = g.b[c0 + i];
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            if (i / kRankChunk == c2) continue;
+            const double a = g.a[i];
+            const long long b = g.b[i];
+            int lo = 0, hi = cn;
             while (lo < hi) {   // first position whose key is not below (a, b)
                 const int mid = (lo + hi) >> 1;
-                if (key_less(g.a[mid], g.b[mid], a, b)) lo = mid + 1;
+                if (key_less(S.a[mid], S.b[mid], a, b)) lo = mid + 1;
                 else hi = mid;
             }
-            r += lo - base;
+            g.rank[g.idx[i]] += lo;
         }
-        g.rank[g.idx[i]] = r;
+        __syncthreads();
     }
-    __syncthreads();
 }
 
 // Index i of the key of ascending rank r (0 <= r < n).  Whole block.

@@ -322,6 +322,10 @@ hipError_t launch_syndromes(const LaunchCtx& c) {
             hipLaunchKernelGGL(line_energy_kernel<double>, dim3(c.n_line_items), dim3(kBlock), 0, c.stream, c.sigs,
                                c.line_items, (const double2*)c.synd, c.epart);
     } else {
+        if (c.n_synd_small_items)
+            hipLaunchKernelGGL((syndrome_kernel<float, kFftPointsF32Small>), dim3(c.n_synd_small_items), dim3(kBlock), 0,
+                               c.stream, c.sigs, c.io, c.synd_small_items, c.shifts, (const float2*)c.twiddle,
+                               c.tw_log2, (float2*)c.synd, (float2*)c.ybuf, c.epart, c.cnt);
         if (c.n_synd_items)
             hipLaunchKernelGGL((syndrome_kernel<float, kFftPointsF32>), dim3(c.n_synd_items), dim3(kBlock), 0, c.stream,
                                c.sigs, c.io, c.synd_items, c.shifts, (const float2*)c.twiddle, c.tw_log2,

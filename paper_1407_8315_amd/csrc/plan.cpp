@@ -359,9 +359,22 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
         for (size_t j = 0; j < len; ++j)
             for (int l = 0; l < kLanes; ++l) out.push_back(j < lanes[l].size() ? lanes[l][j] : pad);
     };
+    // FP32 signals with M <= kFftPointsF32Small: blocks of fewer points (one
+    // line of 4096, or more lines of fewer) and a smaller LDS footprint, so that
+    // more blocks share a CU and overlap their gathers
+    const auto small = [&](const SigHost& g) { return !fp64 && g.m <= kFftPointsF32Small; };
     interleave(
         [&](int s, std::vector<int4>& v) {
             const SigHost& g = sigs[s];
+            if (!small(g)) return;
+            const int nl = (int)std::max<int64_t>(1, std::min<int64_t>(g.S, kFftPointsF32Small / g.m));
+            for (int l0 = 0; l0 < g.S; l0 += nl) v.push_back(int4{s, l0, std::min(nl, g.S - l0), 0});
+        },
+        int4{-1, 0, 0, 0}, lay->synd_small_items);
+    interleave(
+        [&](int s, std::vector<int4>& v) {
+            const SigHost& g = sigs[s];
+            if (small(g)) return;
             if (g.m <= pmax) {
                 int nl = (int)std::max<int64_t>(1, std::min<int64_t>(g.S, pmax / g.m));
                 for (int l0 = 0; l0 < g.S; l0 += nl) v.push_back(int4{s, l0, std::min(nl, g.S - l0), 0});

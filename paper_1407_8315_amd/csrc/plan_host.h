@@ -25,6 +25,7 @@ struct PlanLayout {
     std::vector<SigDev> sigdev;
     std::vector<int64_t> shifts;          // per signal: 0..2L-1, then n_j
     std::vector<int4> synd_items;         // (sig, line0, nlines, pass 0|1); sig < 0 = padding
+    std::vector<int4> synd_small_items;   // one-pass FP32 signals with M <= kFftPointsF32Small
     std::vector<int4> synd2_items;        // (sig, line0, nlines, 2): second FFT pass
     std::vector<int2> line_items;         // (sig, line) of two-pass signals
     std::vector<int2> bin_items;          // (sig, bin0)

@@ -244,6 +244,7 @@ __device__ void block_rank(KeyFn key, int n, RankLds& S, const RankScratch& g) {
     for (int c = 0; c < nch; ++c) {
         const int c0 = c * kRankChunk, cn = min(kRankChunk, n - c0);
         const int P = pow2_at_least(cn);
+#pragma unroll 4
         for (int i = threadIdx.x; i < cn; i += blockDim.x) {
             const RankKey k = key(c0 + i);
             S.a[i] = k.a;
@@ -332,6 +333,7 @@ __device__ int block_select(KeyFn key, int n, int r, RankLds& S, const RankScrat
     const long long lo_b = has_lo ? S.b[rs - w] : 0, hi_b = has_hi ? S.b[rs + w] : 0;
     __syncthreads();
     int below = 0, win = 0;
+#pragma unroll 8
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const RankKey k = key(i);
         if (has_lo && key_less(k.a, k.b, lo_a, lo_b)) ++below;
@@ -345,6 +347,7 @@ __device__ int block_select(KeyFn key, int n, int r, RankLds& S, const RankScrat
     if (nb <= r && r < nb + nw && nw <= kRankChunk) {
         if (threadIdx.x == 0) S.n_win = 0;
         __syncthreads();
+#pragma unroll 8
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
             const RankKey k = key(i);
             const bool in = !(has_lo && key_less(k.a, k.b, lo_a, lo_b)) && (!has_hi || !key_less(hi_a, hi_b, k.a, k.b));

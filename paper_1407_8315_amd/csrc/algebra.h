@@ -75,6 +75,74 @@ __host__ __device__ inline void hankel_singular_values(const zd* mt, int L, doub
             }
 }
 
+// Singular values (descending) of the same Hankel matrix as the square roots
+// of the eigenvalues of its Gram matrix G = H^H H (Hermitian, L x L), by
+// cyclic two-sided Jacobi rotations on G.  About half the arithmetic of the
+// one-sided sweeps, at the cost of absolute accuracy eps * sigma_1^2 in
+// sigma^2 (a sigma of 1e-4 sigma_1 carries a relative error near 5e-9): used
+// for the general-mode vote, which ranks singular values at noise level or
+// above across bins, not for the rank test of exact mode.
+__host__ __device__ inline void gram_singular_values(const zd* mt, int L, double* sv) {
+    zd g[kMaxL][kMaxL];   // full Hermitian matrix, both halves kept
+#pragma unroll
+    for (int i = 0; i < kMaxL; ++i)
+#pragma unroll
+        for (int j = 0; j < kMaxL; ++j) {
+            zd acc{0.0, 0.0};
+#pragma unroll
+            for (int r = 0; r < kMaxL; ++r)
+                if (r < L && i < L && j < L) acc = acc + cmul_conj(mt[r + i], mt[r + j]);
+            g[i][j] = acc;
+        }
+    for (int sweep = 0; sweep < 12; ++sweep) {
+        bool rotated = false;
+#pragma unroll
+        for (int p = 0; p < kMaxL - 1; ++p) {
+#pragma unroll
+            for (int q = p + 1; q < kMaxL; ++q) {
+                if (q >= L) continue;
+                const double a = g[p][p].x, b = g[q][q].x;
+                const zd c = g[p][q];
+                const double c2 = norm2(c);
+                if (!(c2 > 1e-32 * fabs(a * b)) || c2 == 0.0) continue;
+                rotated = true;
+                const double ac = sqrt(c2), rac = 1.0 / ac;
+                const zd eb = zd{c.x * rac, -c.y * rac};   // conj(c) / |c|
+                const double zeta = (b - a) * (0.5 * rac);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+                // G <- U^H G U with U = [[cs, sn], [-sn conj(e), cs conj(e)]] on (p, q), e = c / |c|
+#pragma unroll
+                for (int r = 0; r < kMaxL; ++r) {
+                    if (r == p || r == q || r >= L) continue;
+                    const zd grp = g[r][p], grq = eb * g[r][q];
+                    const zd np = cs * grp - sn * grq, nq = sn * grp + cs * grq;
+                    g[r][p] = np;
+                    g[p][r] = conj(np);
+                    g[r][q] = nq;
+                    g[q][r] = conj(nq);
+                }
+                g[p][p] = zd{a - t * ac, 0.0};
+                g[q][q] = zd{b + t * ac, 0.0};
+                g[p][q] = zd{0.0, 0.0};
+                g[q][p] = zd{0.0, 0.0};
+            }
+        }
+        if (!rotated) break;
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxL; ++j) sv[j] = (j < L) ? sqrt(fmax(g[j][j].x, 0.0)) : 0.0;
+#pragma unroll
+    for (int i = 0; i < kMaxL; ++i)
+#pragma unroll
+        for (int j = 0; j < kMaxL - 1; ++j)
+            if (sv[j] < sv[j + 1]) {
+                double tmp = sv[j];
+                sv[j] = sv[j + 1];
+                sv[j + 1] = tmp;
+            }
+}
+
 // a0 = #{sigma_i > tau_rank sigma_1}, at least 1.
 __host__ __device__ inline int rank_order(const double* sv, int L, double tau_rank) {
     if (!(sv[0] > 0.0) || !__builtin_isfinite(sv[0])) return 1;

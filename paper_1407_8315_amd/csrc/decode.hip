@@ -148,7 +148,7 @@ __global__ __launch_bounds__(kBlock) void singular_values_kernel(const SigDev* _
 #pragma unroll
     for (int l = 0; l < 2 * kMaxL; ++l) e += norm2(mt[l]);   // zero beyond 2L
     double sv[kMaxL];
-    hankel_singular_values(mt, sg.L, sv);
+    gram_singular_values(mt, sg.L, sv);
 #pragma unroll
     for (int i = 0; i < kMaxL; ++i)
         if (i < sg.L) sigma[(sg.bin_off + k) * sg.L + i] = sv[i];

@@ -627,9 +627,42 @@ __device__ inline bool cs_recover(const zd* mt, const zd* y, int R, const int64_
         best[i] = __builtin_inf();
         bt[i] = INT64_MAX;
     }
+    if constexpr (A0 == 1) {
+        // P~(z) = z + c_0: on the unit circle |z + c_0|^2 = 1 + |c_0|^2 - 2 |c_0| cos(angle
+        // between z and -c_0), increasing with the angular distance to -c_0, so the
+        // smallest values sit at the grid points bracketing that angle (an exact
+        // grid angle leaves two equidistant neighbours: the lower t goes first)
+        const double u0 = atan2(-c[0].y, -c[0].x) * ((double)d / (2.0 * M_PI));
+        double u = u0 < 0.0 ? u0 + (double)d : u0;
+        int64_t t1 = (int64_t)floor(u);
+        if (t1 >= d) t1 -= d;
+        const double f = u - floor(u);
+        const int64_t up = (t1 + 1) % d, dn = (t1 + d - 1) % d;
+        int64_t first = t1, second = up;
+        if (f > 0.5) {
+            first = up;
+            second = t1;
+        } else if (f == 0.5) {
+            first = t1 < up ? t1 : up;
+            second = t1 < up ? up : t1;
+        } else if (f == 0.0 && d > 2) {
+            second = dn < up ? dn : up;
+        }
+        if (c[0].x == 0.0 && c[0].y == 0.0) {   // |P~| = 1 everywhere: the lowest t's
+            first = 0;
+            second = 1 % d;
+        }
+        bt[0] = first;
+        if (keep > 1) bt[1] = second;
+    } else {
+    // running powers of w_d, refreshed from the table every 64 steps
+    const zd w1 = omega(tab, sg.tab_stride, 1 % d);
+    zd z{1.0, 0.0};
     for (int64_t t = 0; t < d; ++t) {
+        if ((t & 63) == 0) z = omega(tab, sg.tab_stride, t);
         zd p, dp;
-        poly_eval(c, a0, omega(tab, sg.tab_stride, t), p, dp);
+        poly_eval(c, a0, z, p, dp);
+        z = z * w1;
         double e = norm2(p);
         if (!(e < best[keep - 1])) continue;
         // insertion into the sorted prefix of length keep (fixed-index shifts)
@@ -646,6 +679,7 @@ __device__ inline bool cs_recover(const zd* mt, const zd* y, int R, const int64_
                 ct = tt;
             }
         }
+    }
     }
     // candidates in ascending t (positions 0..keep-1), unused slots last
     int64_t cand[KC];

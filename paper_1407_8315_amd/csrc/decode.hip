@@ -237,6 +237,25 @@ __device__ inline void pad_keys(RankLds& S, int from, int P) {
     }
 }
 
+// Sort K[0 .. P) ascending (P a power of two), single 64-bit keys.  Whole
+// block; ends with a barrier.
+__device__ void lds_bitonic64(unsigned long long* K, int P) {
+    for (int k = 2; k <= P; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P; i += blockDim.x) {
+                const int ij = i ^ j;
+                if (ij > i) {
+                    const unsigned long long x = K[i], y = K[ij];
+                    if (((i & k) == 0) == (y < x)) {
+                        K[i] = y;
+                        K[ij] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+}
+
 // g.rank[i] = position of key(i) in ascending order, i < n.  Whole block.
 template <typename KeyFn>
 __device__ void block_rank(KeyFn key, int n, RankLds& S, const RankScratch& g) {
@@ -1082,12 +1101,29 @@ __global__ __launch_bounds__(kRankThreads) void output_kernel(const SigDev* __re
     }
     __syncthreads();
     const int nk = n_kept;
-    block_rank([&](int j) { return RankKey{0.0, (long long)loc[kx[j]]}; }, nk, S, g);
-    for (int j = threadIdx.x; j < nk; j += blockDim.x) {
-        const int r = g.rank[j];
-        if (r < o.cap) {
-            o.loc[r] = loc[kx[j]];
-            o.val[r] = val[kx[j]];
+    if (nk <= kRankChunk) {
+        // (location << 24 | entry) as one 64-bit key (location < 2^40, entry < 2^24):
+        // the sorted position is the output position
+        unsigned long long* K = reinterpret_cast<unsigned long long*>(S.a);
+        const int P = pow2_at_least(nk);
+#pragma unroll 4
+        for (int j = threadIdx.x; j < P; j += blockDim.x)
+            K[j] = j < nk ? ((unsigned long long)loc[kx[j]] << 24) | (unsigned long long)j : ~0ull;
+        __syncthreads();
+        lds_bitonic64(K, P);
+        for (int r = threadIdx.x; r < nk && r < o.cap; r += blockDim.x) {
+            const int e = kx[(int)(K[r] & 0xffffffull)];
+            o.loc[r] = loc[e];
+            o.val[r] = val[e];
+        }
+    } else {
+        block_rank([&](int j) { return RankKey{0.0, (long long)loc[kx[j]]}; }, nk, S, g);
+        for (int j = threadIdx.x; j < nk; j += blockDim.x) {
+            const int r = g.rank[j];
+            if (r < o.cap) {
+                o.loc[r] = loc[kx[j]];
+                o.val[r] = val[kx[j]];
+            }
         }
     }
     if (threadIdx.x == 0) {

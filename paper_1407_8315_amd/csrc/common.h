@@ -72,17 +72,22 @@ struct SigCounters {
 // The rank test itself runs in two passes: a certificate pass settles the
 // rank-one bins (and tries their order 1 at once) and queues the others as
 // pending, for the SVD pass (or, in a learned plan, for the predictor).
+// In plans with general-mode signals, orders 3 and 4 (root finding by
+// iteration) also run in two passes per round: the locator and |c_0| check
+// for every bin, then the roots, grid check and judge for the survivors,
+// queued per set in the roots queues.
 constexpr int kRoundSlots = kMaxL + 1;
-constexpr int kQueues = 2 * kRoundSlots + kMaxL + 1;
+constexpr int kQueues = 2 * kRoundSlots + kMaxL + 1 + 4;
 __host__ __device__ constexpr int q_round(int set, int slot) { return set * kRoundSlots + slot; }
 __host__ __device__ constexpr int q_cs(int a0) { return 2 * kRoundSlots + a0 - 1; }
 constexpr int kQPending = 2 * kRoundSlots + kMaxL;
+__host__ __device__ constexpr int q_roots(int set, int a) { return kQPending + 1 + set * 2 + (a - 3); }
 
 struct WorkCounters {
     int n_active;
     int q[kQueues];   // lengths of the queues above
 };
-static_assert(sizeof(WorkCounters) == 16 * sizeof(int), "WorkCounters holds 16 counters");
+static_assert(sizeof(WorkCounters) == (1 + kQueues) * sizeof(int), "WorkCounters: the active count and the queues");
 
 // A list entry is (signal, code): code = k << 9 | step << 6 | ap << 3 | a0 with
 // bin k (< 2^22), index `step` of the bin's next hypothesis in its order

@@ -444,15 +444,11 @@ struct BinOut {
     zd p[kMaxL];
 };
 
-// One hypothesis of order a: locator, roots, grid check, least squares,
-// residual judge; on acceptance drops |p_j| < tau_amp max|p|.
-__device__ __attribute__((always_inline)) inline bool try_order(const zd* mt, int L, int a, double e, double nu, const SigDev& sg,
-                                 const double2* tab, BinOut& o) {
-    zd c[kMaxL], z[kMaxL], p[kMaxL];
-    int64_t t[kMaxL];
+// Locator of order a and a necessary condition for its roots: |c_0| is the
+// product of the root magnitudes, so when it lies outside
+// [(1 - delta_mag)^a, (1 + delta_mag)^a] some root fails the grid check.
+__device__ __attribute__((always_inline)) inline bool locator_check(const zd* mt, int a, const SigDev& sg, zd* c) {
     if (!locator(mt, a, c)) return false;
-    // |c_0| is the product of the root magnitudes: when it lies outside
-    // [(1 - delta_mag)^a, (1 + delta_mag)^a] some root fails the grid check.
     double lo = 1.0, hi = 1.0;
 #pragma unroll
     for (int j = 0; j < kMaxL; ++j)
@@ -461,7 +457,16 @@ __device__ __attribute__((always_inline)) inline bool try_order(const zd* mt, in
             hi *= 1.0 + sg.delta_mag;
         }
     const double c0 = cabs(c[0]);
-    if (!(c0 >= lo && c0 <= hi)) return false;
+    return c0 >= lo && c0 <= hi;
+}
+
+// One hypothesis of order a: locator, roots, grid check, least squares,
+// residual judge; on acceptance drops |p_j| < tau_amp max|p|.
+__device__ __attribute__((always_inline)) inline bool try_order(const zd* mt, int L, int a, double e, double nu, const SigDev& sg,
+                                 const double2* tab, BinOut& o) {
+    zd c[kMaxL], z[kMaxL], p[kMaxL];
+    int64_t t[kMaxL];
+    if (!locator_check(mt, a, sg, c)) return false;
     if (!poly_roots(c, a, z)) return false;
     if (!roots_to_grid(z, a, sg.d, sg.delta_grid, sg.delta_mag, t)) return false;
     double r2;
@@ -959,7 +964,7 @@ __global__ __launch_bounds__(kBlock) void svd_rank_kernel(const SigDev* __restri
 // to the next round at their next order (or to the rank test, for a bin whose
 // learned order failed), and a bin with no order left is flagged: counted,
 // and in general mode queued for the CS step by its vote order.
-template <typename T, int A>
+template <typename T, int A, int PHASE>
 __global__ __launch_bounds__(kBlock) void round_kernel(const SigDev* __restrict__ sigs, const int64_t* __restrict__ shifts,
                                                        const typename V2<T>::type* __restrict__ synd,
                                                        const SelDev* __restrict__ sel, const double2* __restrict__ tab,
@@ -969,8 +974,9 @@ __global__ __launch_bounds__(kBlock) void round_kernel(const SigDev* __restrict_
                                                        int64_t list_cap, int round) {
     __shared__ BlockQueues bq;
     const int set_in = round & 1;
-    const int total = work->q[q_round(set_in, A)];
-    const int2* in = qlist + (int64_t)q_round(set_in, A) * list_cap;
+    const int q_in = PHASE == 2 ? q_roots(set_in, A) : q_round(set_in, A);
+    const int total = work->q[q_in];
+    const int2* in = qlist + (int64_t)q_in * list_cap;
     for (int base0 = blockIdx.x * kBlock; base0 < total; base0 += gridDim.x * kBlock) {
         bq.reset();
         const int item = base0 + threadIdx.x;
@@ -994,7 +1000,11 @@ __global__ __launch_bounds__(kBlock) void round_kernel(const SigDev* __restrict_
             const double nu = exact ? 0.0 : sel[s].nu;
             BinOut o;
             o.n = 0;
-            if (try_order(mt, L, A, e, nu, sg, tab, o)) {
+            zd cpre[kMaxL];
+            if (PHASE == 1 && locator_check(mt, A, sg, cpre)) {
+                q = q_roots(set_in, A);   // survivors: roots pass
+                ent = en;
+            } else if (PHASE != 1 && try_order(mt, L, A, e, nu, sg, tab, o)) {
                 emit(sg, &cnt[s], k, o, st_loc, st_val);
             } else {
                 if (step == 0 && ap > 0) wave_count(&cnt[s].mlp_fb, true);
@@ -1023,6 +1033,7 @@ __global__ __launch_bounds__(kBlock) void round_kernel(const SigDev* __restrict_
 
 __global__ void zero_set_kernel(WorkCounters* work, int set) {
     if (threadIdx.x < kRoundSlots) work->q[q_round(set, threadIdx.x)] = 0;
+    if (threadIdx.x < 2) work->q[q_roots(set, 3 + threadIdx.x)] = 0;
 }
 
 // CS step for the bins the decoder queued (general mode), one lane per bin;
@@ -1196,20 +1207,34 @@ hipError_t launch_zero_set(const LaunchCtx& c, int set) {
     return hipGetLastError();
 }
 
-template <typename T, int A>
+template <typename T, int A, int PHASE>
 static void launch_round_one(const LaunchCtx& c, int round) {
     using V = typename V2<T>::type;
-    hipLaunchKernelGGL((round_kernel<T, A>), dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs, c.shifts,
+    hipLaunchKernelGGL((round_kernel<T, A, PHASE>), dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs, c.shifts,
                        (const V*)c.synd, c.sel, c.omega, c.cnt, c.st_loc, c.st_val, c.work, c.active_list, c.qlist,
                        c.list_cap, round);
 }
 
+// Orders 3 and 4 in two passes when the plan has general-mode signals (most
+// of their hypotheses fail the |c_0| check); one fused pass otherwise.
+template <typename T, int A>
+static void launch_order(const LaunchCtx& c, int round) {
+    if constexpr (A >= 3) {
+        if (c.any_general) {
+            launch_round_one<T, A, 1>(c, round);
+            launch_round_one<T, A, 2>(c, round);
+            return;
+        }
+    }
+    launch_round_one<T, A, 0>(c, round);
+}
+
 template <typename T>
 static void launch_round_t(const LaunchCtx& c, int round) {
-    launch_round_one<T, 1>(c, round);
-    if (c.max_l >= 2) launch_round_one<T, 2>(c, round);
-    if (c.max_l >= 3) launch_round_one<T, 3>(c, round);
-    if (c.max_l >= 4) launch_round_one<T, 4>(c, round);
+    launch_order<T, 1>(c, round);
+    if (c.max_l >= 2) launch_order<T, 2>(c, round);
+    if (c.max_l >= 3) launch_order<T, 3>(c, round);
+    if (c.max_l >= 4) launch_order<T, 4>(c, round);
 }
 
 hipError_t launch_round(const LaunchCtx& c, int round) {

@@ -237,6 +237,7 @@ hipError_t launch_certify(const LaunchCtx& c);                           // acti
 hipError_t launch_svd_rank(const LaunchCtx& c, int q_in, int set_out);   // rank test by SVD
 hipError_t launch_zero_set(const LaunchCtx& c, int set);
 hipError_t launch_round(const LaunchCtx& c, int round);
+hipError_t launch_rest(const LaunchCtx& c);   // rounds 1.. in one kernel (plans without general-mode signals)
 hipError_t launch_cs(const LaunchCtx& c);
 hipError_t launch_output(const LaunchCtx& c);
 

@@ -1031,6 +1031,53 @@ __global__ __launch_bounds__(kBlock) void round_kernel(const SigDev* __restrict_
     }
 }
 
+// The rounds after the first, in one kernel, for plans without general-mode
+// signals (few bins remain after round 0 there): each bin of set 1 tries its
+// remaining orders in turn (same sequence, same judge), is emitted at the
+// first accepted one and flagged when none is left.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void rest_kernel(const SigDev* __restrict__ sigs,
+                                                      const typename V2<T>::type* __restrict__ synd,
+                                                      const double2* __restrict__ tab, SigCounters* __restrict__ cnt,
+                                                      int64_t* __restrict__ st_loc, double2* __restrict__ st_val,
+                                                      const WorkCounters* __restrict__ work,
+                                                      const int2* __restrict__ qlist, int64_t list_cap) {
+    // the bins of set 1, slots 1..kMaxL, as one index space
+    int start[kMaxL + 1];
+    start[0] = 0;
+#pragma unroll
+    for (int a = 1; a <= kMaxL; ++a) start[a] = start[a - 1] + work->q[q_round(1, a)];
+    const int total = start[kMaxL];
+    for (int item = blockIdx.x * kBlock + threadIdx.x; item < total; item += gridDim.x * kBlock) {
+        int slot = 1;
+#pragma unroll
+        for (int a = 1; a < kMaxL; ++a)
+            if (item >= start[a]) slot = a + 1;
+        const int2 en = qlist[(int64_t)q_round(1, slot) * list_cap + (item - start[slot - 1])];
+        const int s = en.x;
+        const int code = en.y;
+        const int64_t k = code_k(code);
+        const int ap = code_ap(code), a0 = code_a0(code);
+        const SigDev& sg = sigs[s];
+        const int L = sg.L;
+        zd mt[2 * kMaxL];
+        load_raw<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, 2 * L, mt);
+        double e = 0.0;
+#pragma unroll
+        for (int l = 0; l < 2 * kMaxL; ++l) e += norm2(mt[l]);
+        derotate_consecutive<2 * kMaxL>(mt, k, sg.n, 2 * L);
+        BinOut o;
+        o.n = 0;
+        bool done = false;
+        for (int step = code_step(code); step < L && !done; ++step) {
+            const int a = seq_order(a0, ap, L, step);
+            done = try_order(mt, L, a, e, 0.0, sg, tab, o);
+        }
+        if (done) emit(sg, &cnt[s], k, o, st_loc, st_val);
+        else wave_count(&cnt[s].flagged, true);
+    }
+}
+
 __global__ void zero_set_kernel(WorkCounters* work, int set) {
     if (threadIdx.x < kRoundSlots) work->q[q_round(set, threadIdx.x)] = 0;
     if (threadIdx.x < 2) work->q[q_roots(set, 3 + threadIdx.x)] = 0;
@@ -1235,6 +1282,17 @@ static void launch_round_t(const LaunchCtx& c, int round) {
     if (c.max_l >= 2) launch_order<T, 2>(c, round);
     if (c.max_l >= 3) launch_order<T, 3>(c, round);
     if (c.max_l >= 4) launch_order<T, 4>(c, round);
+}
+
+hipError_t launch_rest(const LaunchCtx& c) {
+    if (c.n_bin_items == 0) return hipSuccess;
+    if (c.fp64)
+        hipLaunchKernelGGL(rest_kernel<double>, dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs,
+                           (const double2*)c.synd, c.omega, c.cnt, c.st_loc, c.st_val, c.work, c.qlist, c.list_cap);
+    else
+        hipLaunchKernelGGL(rest_kernel<float>, dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs,
+                           (const float2*)c.synd, c.omega, c.cnt, c.st_loc, c.st_val, c.work, c.qlist, c.list_cap);
+    return hipGetLastError();
 }
 
 hipError_t launch_round(const LaunchCtx& c, int round) {

@@ -211,7 +211,8 @@ sft_status enqueue(const sft_plan_s* p, hipEvent_t* events) {
         HIPCHK(launch_round(c, r));
         // bins whose learned order failed: rank test, then on with round 1
         if (r == 0 && use_mlp && p->max_l > 1) HIPCHK(launch_svd_rank(c, q_round(1, 0), 1));
-        // without general-mode signals, the few bins left after round 0 finish in one kernel
+        // without general-mode signals, the few bins left after round 0 of orders 1
+        // and 2 finish in one kernel
         if (r == 0 && p->n_general == 0 && p->max_l > 1) {
             HIPCHK(launch_rest(c));
             break;

@@ -1031,10 +1031,12 @@ __global__ __launch_bounds__(kBlock) void round_kernel(const SigDev* __restrict_
     }
 }
 
-// The rounds after the first, in one kernel, for plans without general-mode
-// signals (few bins remain after round 0 there): each bin of set 1 tries its
-// remaining orders in turn (same sequence, same judge), is emitted at the
-// first accepted one and flagged when none is left.
+// Plans without general-mode signals finish in one kernel what few bins
+// remain after round 0 of orders 1 and 2: the bins of round 0 whose first
+// order is 3 or 4 (set 0, slots 3..4) and those of the later rounds (set 1,
+// slots 1..4).  Each bin tries its remaining orders in turn (same sequence,
+// same judge), is emitted at the first accepted one and flagged when none is
+// left.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void rest_kernel(const SigDev* __restrict__ sigs,
                                                       const typename V2<T>::type* __restrict__ synd,
@@ -1042,18 +1044,28 @@ __global__ __launch_bounds__(kBlock) void rest_kernel(const SigDev* __restrict__
                                                       int64_t* __restrict__ st_loc, double2* __restrict__ st_val,
                                                       const WorkCounters* __restrict__ work,
                                                       const int2* __restrict__ qlist, int64_t list_cap) {
-    // the bins of set 1, slots 1..kMaxL, as one index space
-    int start[kMaxL + 1];
+    // the queues as one index space
+    constexpr int kSeg = 2 + kMaxL;
+    const int qs[kSeg] = {q_round(0, 3), q_round(0, 4), q_round(1, 1), q_round(1, 2), q_round(1, 3), q_round(1, 4)};
+    int start[kSeg + 1];
     start[0] = 0;
 #pragma unroll
-    for (int a = 1; a <= kMaxL; ++a) start[a] = start[a - 1] + work->q[q_round(1, a)];
-    const int total = start[kMaxL];
+    for (int i = 0; i < kSeg; ++i) start[i + 1] = start[i] + work->q[qs[i]];
+    const int total = start[kSeg];
     for (int item = blockIdx.x * kBlock + threadIdx.x; item < total; item += gridDim.x * kBlock) {
-        int slot = 1;
+        int seg = 0;
 #pragma unroll
-        for (int a = 1; a < kMaxL; ++a)
-            if (item >= start[a]) slot = a + 1;
-        const int2 en = qlist[(int64_t)q_round(1, slot) * list_cap + (item - start[slot - 1])];
+        for (int i = 1; i < kSeg; ++i)
+            if (item >= start[i]) seg = i;
+        int qid = qs[0];
+#pragma unroll
+        for (int i = 1; i < kSeg; ++i)
+            if (seg == i) qid = qs[i];
+        int s0 = start[0];
+#pragma unroll
+        for (int i = 1; i < kSeg; ++i)
+            if (seg == i) s0 = start[i];
+        const int2 en = qlist[(int64_t)qid * list_cap + (item - s0)];
         const int s = en.x;
         const int code = en.y;
         const int64_t k = code_k(code);
@@ -1069,9 +1081,26 @@ __global__ __launch_bounds__(kBlock) void rest_kernel(const SigDev* __restrict__
         BinOut o;
         o.n = 0;
         bool done = false;
+        int r0 = a0;
         for (int step = code_step(code); step < L && !done; ++step) {
-            const int a = seq_order(a0, ap, L, step);
-            done = try_order(mt, L, a, e, 0.0, sg, tab, o);
+            if (step > 0 && r0 == 0) {
+                // a learned order failed and the rank test has not run yet
+                if (rank_one_certified(mt, L, sg.tau_rank)) {
+                    r0 = 1;
+                } else {
+                    double sv[kMaxL];
+                    hankel_singular_values(mt, L, sv);
+                    r0 = rank_order(sv, L, sg.tau_rank);
+                }
+            }
+            // one constant-order copy per order: the same arithmetic as round_kernel<A>
+            switch (seq_order(r0, ap, L, step)) {
+                case 1: done = try_order(mt, L, 1, e, 0.0, sg, tab, o); break;
+                case 2: done = try_order(mt, L, 2, e, 0.0, sg, tab, o); break;
+                case 3: done = try_order(mt, L, 3, e, 0.0, sg, tab, o); break;
+                default: done = try_order(mt, L, 4, e, 0.0, sg, tab, o); break;
+            }
+            if (!done && step == 0 && ap > 0) wave_count(&cnt[s].mlp_fb, true);
         }
         if (done) emit(sg, &cnt[s], k, o, st_loc, st_val);
         else wave_count(&cnt[s].flagged, true);
@@ -1280,6 +1309,8 @@ template <typename T>
 static void launch_round_t(const LaunchCtx& c, int round) {
     launch_order<T, 1>(c, round);
     if (c.max_l >= 2) launch_order<T, 2>(c, round);
+    // plans without general-mode signals leave round 0 of orders 3 and 4 to rest_kernel
+    if (round == 0 && !c.any_general) return;
     if (c.max_l >= 3) launch_order<T, 3>(c, round);
     if (c.max_l >= 4) launch_order<T, 4>(c, round);
 }

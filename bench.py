@@ -29,6 +29,18 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector, published
+BF16_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 MFMA, published
+
+# HBM bytes of the gather + FFT kernel (syndrome_kernel<float, 4096>) per
+# algorithmic byte read and written, from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# scaled by the plain-copy calibration (profiles/syndrome_kernel_n20_b256_traffic.md).
+TRAFFIC_RATIOS = {"exact": (2.02, 1.00), "general": (7.90, 1.00)}
+
+# Algorithmic FLOPs of the order predictor per row (matrix products only):
+# forward 2 (32*128 + 128*128 + 128*5); training adds the three weight
+# gradients and the two hidden-layer input gradients.
+MLP_FWD_FLOP = 2 * (32 * 128 + 128 * 128 + 128 * 5)
+MLP_TRAIN_FLOP = MLP_FWD_FLOP + 2 * (32 * 128 + 128 * 128 + 128 * 5 + 128 * 5 + 128 * 128)
 
 
 def parse():
@@ -162,6 +174,46 @@ def uneven_batch(steps, warmup, count=4096):
             "input_generation_s": round(t_gen, 1)}
 
 
+def mlp_throughput(steps, warmup, rows=1 << 18):
+    """The order predictor's kernels on `rows` random feature rows: forward
+    (inference) and one Adam training step (forward + backward), each timed
+    over `steps` calls, as rows/s and algorithmic TFLOP/s against the BF16
+    MFMA peak."""
+    import torch
+
+    from paper_1407_8315_amd import Mlp
+
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.Stream(device=dev)
+    out = {}
+    with torch.cuda.stream(stream):
+        g = torch.Generator(device=dev)
+        g.manual_seed(5)
+        feat = torch.randn((rows, 32), generator=g, device=dev)
+        labels = torch.randint(0, 5, (rows,), generator=g, device=dev, dtype=torch.int32)
+        loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        net = Mlp(seed=1, stream=stream)
+        for name, fn, flop in (("inference", lambda: net.forward(feat), MLP_FWD_FLOP),
+                               ("training", lambda: net.train_step(feat, labels, 1e-4, loss), MLP_TRAIN_FLOP)):
+            for _ in range(warmup):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            tflops = rows * flop / (ms * 1e-3) / 1e12
+            out[name] = {"ms_per_call": round(ms, 4), "rows_per_s": round(rows / ms * 1e3, 1),
+                         "algorithmic_tflops": round(tflops, 2), "frac_of_bf16_peak": round(tflops / BF16_PEAK_TFLOPS, 5),
+                         "flop_per_row": flop}
+        net.close()
+    out["rows"] = rows
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -237,9 +289,12 @@ def main():
     S = 2 * L + (R if mode == "general" else 0)
     synd_bytes = B * S * m * 8 * 2                 # gather read + syndrome write, per launch
     fft_gbs = synd_bytes / (stage[0] * 1e-3) / 1e9
+    rf, rw = TRAFFIC_RATIOS[mode]
+    traffic = int(B * S * m * 8 * (rf + rw))   # measured HBM bytes per launch (fetch + write)
     roofline = {"bound": "hbm", "achieved": round(fft_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(fft_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "syndrome_kernel<float> (gather + FFT)",
+                "frac": round(fft_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_gbs": round(traffic / (stage[0] * 1e-3) / 1e9, 1),
+                "kernel": "syndrome_kernel<float, 4096> (gather + FFT)",
                 "algorithmic_bytes_per_launch": synd_bytes, "avg_launch_ms": round(stage[0], 4)}
 
     cpu = None
@@ -251,6 +306,8 @@ def main():
     lvp = None if a.no_learned else learned_vs_plain(a.steps, a.warmup)
     torch.cuda.empty_cache()
     unv = None if a.no_uneven else uneven_batch(a.steps, a.warmup)
+    torch.cuda.empty_cache()
+    mlp = None if a.no_learned else mlp_throughput(a.steps, a.warmup)
     out = {
         "metric": "recovered freqs/s at N=2^20, K=1000 (general mode, SNR 10/20/30/40 dB)"
         if mode == "general" else "recovered freqs/s at N=2^20, K=1000 (exact mode)",
@@ -268,6 +325,7 @@ def main():
         "cpu_baseline": cpu,
         "learned_vs_plain": lvp,
         "uneven_batch": unv,
+        "mlp_kernels": mlp,
         "input_generation_s": round(gen_s, 2),
     }
     print(json.dumps(out))

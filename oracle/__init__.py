@@ -11,6 +11,7 @@ Contents
   sfft.py   syndromes, locator, grid check, amplitudes, judge, exact and
             general drivers, vote, pruning, Subspace Pursuit, metrics
   roots.py  closed-form roots for a <= 4 (the paper's Appendix, corrected)
+  iterative.py  iterative sFFT-DT (Alg. 1): fold, SubFreq, SynDec, T
   mlp.py    FP64 reference network of the learned order predictor
             (forward, backward, features)
 
@@ -21,6 +22,9 @@ uniqueness by exhaustive search over every on-grid support for small d,
 closed-form roots against an independent eigenvalue root finder, flags for
 a > L, noise-free CS = syndrome decoding, SP exact recovery, finite-difference
 gradients of the reference network, and the paper's printed Theorem-2 figure.
+Iterative oracle (tests/test_oracle_iterative.py): folds and SubFreq against
+brute-force alias sums, the Fig. 1 toy, a support-only simulation of Alg. 1,
+a bin that only T brings to its decode, and the cost statement of Sec. II-G.
 """
 from .sfft import (  # noqa: F401
     Result,

@@ -1,7 +1,7 @@
 /*
- * sft.h — C ABI of an MI355X (gfx950) implementation of non-iterative
- * sFFT-DT: sparse FFT by downsampling in time and syndrome decoding
- * (Hsieh, Lu, Pei, arXiv 1407.8315).
+ * sft.h — C ABI of an MI355X (gfx950) implementation of sFFT-DT: sparse
+ * FFT by downsampling in time and syndrome decoding (Hsieh, Lu, Pei,
+ * arXiv 1407.8315), non-iterative (Sec. II-C, III) and iterative (Alg. 1).
  *
  * Problem statement (Alg. 1 and Alg. 2, "Input: x, K; Output: x_hat"): given
  * a length-N signal x whose spectrum x_hat has K significant entries, return
@@ -22,6 +22,12 @@
  *   4. general mode: bins no order explains go through pruning (Sec. III-C
  *      Steps 2-3) and Subspace Pursuit on the random-shift syndromes (Eq. (11));
  *   5. output sorted by location (general mode: the K largest values first).
+ * Iterative mode (Alg. 1, exactly K-sparse) replaces 1-3 by a_m = L
+ * iterations: iteration l takes the FFTs of shifts 2l and 2l + 1 at
+ * d_l = 2^l d_0 (M_l = M_0 / 2^l), folds the earlier shifts' syndromes to that
+ * grid, subtracts the frequencies solved so far (SubFreq) and decodes every
+ * bin still open or newly non-zero at order a = l + 1 (SynDec); a bin whose
+ * solution fails the grid check stays open (the set T) for the next grid.
  *
  * Memory: every pointer argument named *_dev is device memory (hipMalloc or a
  * torch CUDA tensor on the plan's device); everything else is host memory.
@@ -45,7 +51,7 @@
 extern "C" {
 #endif
 
-#define SFT_ABI_VERSION 2
+#define SFT_ABI_VERSION 3
 #define SFT_MAX_RSHIFTS 64
 
 typedef enum sft_status {
@@ -59,7 +65,10 @@ typedef enum sft_status {
 } sft_status;
 
 enum { SFT_C64 = 1, SFT_C128 = 2 };                 /* input element type: complex float / double, interleaved */
-enum { SFT_MODE_EXACT = 0, SFT_MODE_GENERAL = 1 };  /* Sec. II (exactly K-sparse) / Sec. III (generally K-sparse) */
+/* Sec. II-C (exactly K-sparse, non-iterative) / Sec. III (generally K-sparse) /
+ * Alg. 1 (exactly K-sparse, iterative: m = M_0 = N / d_0, l = a_m iterations,
+ * M_0 >= 2^(l-1); a plan's signals are all iterative or none) */
+enum { SFT_MODE_EXACT = 0, SFT_MODE_GENERAL = 1, SFT_MODE_ITERATIVE = 2 };
 enum {
     SFT_FLAG_LEARNED = 1u,       /* order estimate from the attached MLP; rank test as fallback */
     SFT_FLAG_SYNC = 2u,          /* synchronise at the end of each call */
@@ -106,14 +115,17 @@ typedef struct sft_sparse_out {
 
 /* Totals over the signals of one call (filled only when requested). */
 typedef struct sft_stats {
-    int64_t active_bins;        /* bins that passed the activity test / got votes */
-    int64_t flagged_bins;       /* bins no order up to L explained */
+    int64_t active_bins;        /* bins that passed the activity test / got votes (iterative:
+                                   bin decodes summed over the iterations) */
+    int64_t flagged_bins;       /* bins no order up to L explained (iterative: bins whose
+                                   decode failed in the last iteration) */
     int64_t cs_bins;            /* flagged bins recovered by pruning + SP (general mode) */
     int64_t mlp_fallbacks;      /* learned mode: bins where the predicted order was rejected */
     int64_t entries;            /* entries found (sum of counts) */
     int64_t overflowed;         /* signals whose count exceeded the capacity */
     int64_t nonfinite;          /* non-finite gathered samples (SFT_FLAG_CHECK_FINITE) */
-    double stage_ms[4];         /* gather+FFT, order estimate/vote, decode, output (HIP events) */
+    double stage_ms[4];         /* gather+FFT, order estimate/vote, decode, output (HIP events);
+                                   iterative: gather+FFT, iteration 0, iterations 1.., output */
 } sft_stats;
 
 /* What a plan chose for one signal; the oracle consumes exactly these. */
@@ -144,6 +156,11 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
  * in SFT_MODE_EXACT.  stats may be NULL (then the call is asynchronous). */
 sft_status sft_exact(sft_plan_t plan, const void* x_dev, const sft_sparse_out* out, sft_stats* stats);
 
+/* Iterative sFFT-DT (Alg. 1) for one exactly K-sparse signal: x_dev holds N
+ * elements of the plan's in_dtype; requires a single-signal plan in
+ * SFT_MODE_ITERATIVE.  Output, stats and stream semantics as sft_exact. */
+sft_status sft_iterative(sft_plan_t plan, const void* x_dev, const sft_sparse_out* out, sft_stats* stats);
+
 /* Generally K-sparse recovery of one signal (Sec. III): syndrome decoding with
  * the K-vote, pruning + Subspace Pursuit on flagged bins, the K largest kept.
  * Requires a single-signal plan in SFT_MODE_GENERAL. */
@@ -160,7 +177,10 @@ sft_status sft_batch(sft_plan_t plan, const void* const* x_devs, const sft_spars
  * Alg. 2 Part 1) for the plan's S = 2L (+ R) shifts, written to out_dev as
  * [S][M] interleaved complex (float for SFT_C64 input, double for SFT_C128),
  * shift-major; shift s is l = s for s < 2L and n_{s-2L} after that.  Same
- * stream semantics as sft_exact (asynchronous). */
+ * stream semantics as sft_exact (asynchronous).  Iterative plans write the
+ * FFTs Alg. 1 takes: for l = 0 .. L-1 the shifts 2l and 2l + 1 on the grid of
+ * M_0 / 2^l bins, [l][2][M_0 / 2^l] concatenated (2 (2 M_0 - M_0 / 2^(L-1))
+ * values). */
 sft_status sft_syndromes(sft_plan_t plan, const void* x_dev, void* out_dev);
 
 /* ---------------------------------------------------------------------------

@@ -15,7 +15,7 @@ import dataclasses
 
 from . import _lib
 from ._lib import (  # noqa: F401
-    SFT_C64, SFT_C128, SFT_MODE_EXACT, SFT_MODE_GENERAL,
+    SFT_C64, SFT_C128, SFT_MODE_EXACT, SFT_MODE_GENERAL, SFT_MODE_ITERATIVE,
     SFT_FLAG_LEARNED, SFT_FLAG_SYNC, SFT_FLAG_CHECK_FINITE, SFT_FLAG_AUTOTUNE, SftError,
 )
 
@@ -43,7 +43,7 @@ def make_params(n, k, m=0, l=0, r=0, dtype="c64", mode="exact", flags=0, seed=0,
     p = _lib.Params()
     p.n, p.k, p.m, p.l, p.r = int(n), int(k), int(m), int(l), int(r)
     p.in_dtype = {"c64": SFT_C64, "c128": SFT_C128}[dtype]
-    p.mode = {"exact": SFT_MODE_EXACT, "general": SFT_MODE_GENERAL}[mode]
+    p.mode = {"exact": SFT_MODE_EXACT, "general": SFT_MODE_GENERAL, "iterative": SFT_MODE_ITERATIVE}[mode]
     p.flags = int(flags)
     p.reserved = 0
     p.seed = int(seed) & ((1 << 64) - 1)
@@ -158,6 +158,10 @@ class Plan:
     def general(self, x, out: Result | None = None, capacity=None, stats=False) -> Result:
         return self._single(self._lib.sft_general, x, out, capacity, stats)
 
+    def iterative(self, x, out: Result | None = None, capacity=None, stats=False) -> Result:
+        """Iterative sFFT-DT (Alg. 1) on a single-signal plan in mode "iterative"."""
+        return self._single(self._lib.sft_iterative, x, out, capacity, stats)
+
     def batch(self, xs, outs=None, capacities=None, stats=False):
         if len(xs) != self.n_signals:
             raise ValueError(f"expected {self.n_signals} signals")
@@ -204,15 +208,22 @@ class Plan:
         return run
 
     def syndromes(self, x):
-        """Steps 1-2 only: the [S, M] syndromes of a single-signal plan (device tensor)."""
+        """Steps 1-2 only: the [S, M] syndromes of a single-signal plan (device
+        tensor).  Iterative plans: a list over the iterations l of [2, M_0 / 2^l]
+        (shifts 2l and 2l + 1 on that iteration's grid)."""
         torch = _torch()
         self._check_input(x)
         inf = self.infos[0]
-        s_lines = 2 * inf["l"] + inf["r"]
         dt = torch.complex128 if inf["in_dtype"] == SFT_C128 else torch.complex64
-        out = torch.empty((s_lines, inf["m"]), dtype=dt, device=x.device)
+        if inf["mode"] == SFT_MODE_ITERATIVE:
+            sizes = [inf["m"] >> l for l in range(inf["l"])]
+            out = torch.empty(2 * sum(sizes), dtype=dt, device=x.device)
+        else:
+            out = torch.empty((2 * inf["l"] + inf["r"], inf["m"]), dtype=dt, device=x.device)
         _lib.check(self._lib.sft_syndromes(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr())),
                    "sft_syndromes")
+        if inf["mode"] == SFT_MODE_ITERATIVE:
+            return [v.view(2, -1) for v in out.split([2 * m for m in sizes])]
         return out
 
     def attach(self, mlp):

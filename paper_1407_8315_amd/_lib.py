@@ -10,13 +10,13 @@ LIB_PATH = os.path.join(_HERE, "libsft.so")
 
 SFT_OK, SFT_E_INVALID, SFT_E_UNSUPPORTED, SFT_E_NOMEM, SFT_E_DEVICE, SFT_E_CAPACITY, SFT_E_NONFINITE = range(7)
 SFT_C64, SFT_C128 = 1, 2
-SFT_MODE_EXACT, SFT_MODE_GENERAL = 0, 1
+SFT_MODE_EXACT, SFT_MODE_GENERAL, SFT_MODE_ITERATIVE = 0, 1, 2
 SFT_FLAG_LEARNED, SFT_FLAG_SYNC, SFT_FLAG_CHECK_FINITE, SFT_FLAG_AUTOTUNE = 1, 2, 4, 8
 SFT_MAX_RSHIFTS = 64
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = [
-    "sft_plan", "sft_exact", "sft_general", "sft_batch", "sft_syndromes", "sft_plan_get", "sft_destroy",
+    "sft_plan", "sft_exact", "sft_general", "sft_iterative", "sft_batch", "sft_syndromes", "sft_plan_get", "sft_destroy",
     "sft_status_str", "sft_last_error", "sft_abi_version",
     "sft_mlp_create", "sft_mlp_destroy", "sft_mlp_get_params", "sft_mlp_set_params", "sft_mlp_forward",
     "sft_mlp_grad", "sft_mlp_train_step", "sft_mlp_last_error", "sft_plan_attach_mlp", "sft_features",
@@ -83,7 +83,7 @@ def load():
     vp, i64, st = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
     lib.sft_plan.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Params), i64, vp]
     lib.sft_plan.restype = st
-    for name in ("sft_exact", "sft_general"):
+    for name in ("sft_exact", "sft_general", "sft_iterative"):
         f = getattr(lib, name)
         f.argtypes = [vp, vp, ctypes.POINTER(SparseOut), ctypes.POINTER(Stats)]
         f.restype = st

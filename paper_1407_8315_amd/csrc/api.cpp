@@ -69,6 +69,13 @@ struct sft_plan_s {
     int2* d_bin_items = nullptr;
     int2* d_act_items = nullptr;
     int* d_gsigs = nullptr;
+    bool iterative = false;          // Alg. 1 plan
+    uint8_t* d_it_status = nullptr;
+    int64_t* d_it_loc = nullptr;
+    double2* d_it_val = nullptr;
+    int2* d_it_items = nullptr;
+    int it_item_off[kMaxL] = {0, 0, 0, 0};
+    int it_n_items[kMaxL] = {0, 0, 0, 0};
     WorkCounters* d_work = nullptr;
     int2* d_active = nullptr;
     int2* d_qlist = nullptr;
@@ -168,6 +175,15 @@ LaunchCtx make_ctx(const sft_plan_s* p) {
     c.qlist = p->d_qlist;
     c.list_cap = p->list_cap;
     c.n_work_blocks = p->n_work_blocks;
+    c.iterative = p->iterative;
+    c.it_status = p->d_it_status;
+    c.it_loc = p->d_it_loc;
+    c.it_val = p->d_it_val;
+    c.it_items = p->d_it_items;
+    for (int l = 0; l < kMaxL; ++l) {
+        c.it_item_off[l] = p->it_item_off[l];
+        c.it_n_items[l] = p->it_n_items[l];
+    }
     return c;
 }
 
@@ -181,6 +197,22 @@ bool learned(const sft_plan_s* p) {
 // Learned plans run the predictor between the activity pass and the decoder.
 sft_status enqueue(const sft_plan_s* p, hipEvent_t* events) {
     LaunchCtx c = make_ctx(p);
+    if (p->iterative) {
+        // Alg. 1: the FFTs of every iteration in one stage (they depend on x
+        // only), then the iterations in order, then the output pass
+        if (events) HIPCHK(hipEventRecord(events[0], p->stream));
+        HIPCHK(launch_zero_counters(c));
+        HIPCHK(launch_syndromes(c));
+        if (events) HIPCHK(hipEventRecord(events[1], p->stream));
+        for (int l = 0; l < p->max_l; ++l) {
+            HIPCHK(launch_iteration(c, l));
+            if (l == 0 && events) HIPCHK(hipEventRecord(events[2], p->stream));
+        }
+        if (events) HIPCHK(hipEventRecord(events[3], p->stream));
+        HIPCHK(launch_output(c));
+        if (events) HIPCHK(hipEventRecord(events[4], p->stream));
+        return SFT_OK;
+    }
     const bool use_mlp = learned(p) && p->mlp;
     const bool any_exact = p->n_general < (int)p->sig.size();
     if (events) HIPCHK(hipEventRecord(events[0], p->stream));
@@ -293,7 +325,9 @@ sft_status run_single(sft_plan_t plan, const void* x, const sft_sparse_out* out,
     if (!plan || !out) return fail(SFT_E_INVALID, "plan or output is NULL");
     if (plan->sig.size() != 1) return fail(SFT_E_INVALID, "batch plans run through sft_batch");
     if (plan->sig[0].mode != mode)
-        return fail(SFT_E_INVALID, mode == kExact ? "plan is not in SFT_MODE_EXACT" : "plan is not in SFT_MODE_GENERAL");
+        return fail(SFT_E_INVALID, mode == kExact     ? "plan is not in SFT_MODE_EXACT"
+                                   : mode == kGeneral ? "plan is not in SFT_MODE_GENERAL"
+                                                      : "plan is not in SFT_MODE_ITERATIVE");
     if ((plan->sig[0].flags & SFT_FLAG_LEARNED) && !plan->mlp)
         return fail(SFT_E_INVALID, "SFT_FLAG_LEARNED without an attached predictor");
     const void* xs[1] = {x};
@@ -351,6 +385,9 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     }
     for (auto& g : sigs)
         if (g.dtype != sigs[0].dtype) return fail(SFT_E_UNSUPPORTED, "all signals of a plan need one input dtype");
+    for (auto& g : sigs)
+        if ((g.mode == SFT_MODE_ITERATIVE) != (sigs[0].mode == SFT_MODE_ITERATIVE))
+            return fail(SFT_E_UNSUPPORTED, "a plan's signals are all in SFT_MODE_ITERATIVE or none is");
 
     sft_plan_s* p = new sft_plan_s();
     p->stream = (hipStream_t)hip_stream;
@@ -372,6 +409,11 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     p->n_line_items = (int)lay.line_items.size();
     p->n_bin_items = (int)lay.bin_items.size();
     p->n_act_items = (int)lay.act_items.size();
+    p->iterative = lay.n_iterative > 0;
+    for (int l = 0; l < kMaxL; ++l) {
+        p->it_item_off[l] = lay.it_item_off[l];
+        p->it_n_items[l] = lay.it_n_items[l];
+    }
 
     const size_t ns = p->sig.size();
     sft_status s = SFT_OK;
@@ -383,7 +425,7 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
             return s;      \
         }                  \
     } while (0)
-    TRY(dalloc(p, &p->d_sigs, ns));
+    TRY(dalloc(p, &p->d_sigs, lay.sigdev.size()));
     TRY(dalloc(p, &p->d_io, ns));
     if (p->fp64) {
         double2* t = nullptr;
@@ -427,6 +469,10 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     TRY(dalloc(p, &p->d_bin_items, lay.bin_items.size()));
     TRY(dalloc(p, &p->d_act_items, lay.act_items.size()));
     TRY(dalloc(p, &p->d_gsigs, lay.general_sigs.size()));
+    TRY(dalloc(p, &p->d_it_status, (size_t)lay.it_st_elems));
+    TRY(dalloc(p, &p->d_it_loc, (size_t)lay.it_rec_elems));
+    TRY(dalloc(p, &p->d_it_val, (size_t)lay.it_rec_elems));
+    TRY(dalloc(p, &p->d_it_items, lay.it_items.size()));
     TRY(dalloc(p, &p->d_work, 1));
     TRY(dalloc(p, &p->d_active, (size_t)lay.bin_elems));
     TRY(dalloc(p, &p->d_qlist, (size_t)lay.bin_elems * kQueues));
@@ -447,7 +493,9 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
             return fail(SFT_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));              \
         }                                                                                              \
     } while (0)
-    HIPTRY(hipMemcpy(p->d_sigs, lay.sigdev.data(), ns * sizeof(SigDev), hipMemcpyHostToDevice));
+    HIPTRY(hipMemcpy(p->d_sigs, lay.sigdev.data(), lay.sigdev.size() * sizeof(SigDev), hipMemcpyHostToDevice));
+    if (!lay.it_items.empty())
+        HIPTRY(hipMemcpy(p->d_it_items, lay.it_items.data(), lay.it_items.size() * sizeof(int2), hipMemcpyHostToDevice));
     HIPTRY(hipMemcpy(p->d_shifts, lay.shifts.data(), lay.shifts.size() * sizeof(int64_t), hipMemcpyHostToDevice));
     if (p->fp64) {
         std::vector<double2> tw;
@@ -490,6 +538,10 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
 
 sft_status sft_exact(sft_plan_t plan, const void* x_dev, const sft_sparse_out* out, sft_stats* stats) {
     return run_single(plan, x_dev, out, stats, kExact);
+}
+
+sft_status sft_iterative(sft_plan_t plan, const void* x_dev, const sft_sparse_out* out, sft_stats* stats) {
+    return run_single(plan, x_dev, out, stats, kIterative);
 }
 
 sft_status sft_general(sft_plan_t plan, const void* x_dev, const sft_sparse_out* out, sft_stats* stats) {
@@ -546,7 +598,8 @@ sft_status sft_syndromes(sft_plan_t plan, const void* x_dev, void* out_dev) {
     HIPCHK(launch_zero_counters(c));
     HIPCHK(launch_syndromes(c));
     const SigHost& g = plan->sig[0];
-    const size_t bytes = (size_t)g.S * (size_t)g.m * (plan->fp64 ? sizeof(double2) : sizeof(float2));
+    const size_t elems = g.mode == SFT_MODE_ITERATIVE ? 2 * (size_t)iter_bins_off(g.m, g.L) : (size_t)g.S * (size_t)g.m;
+    const size_t bytes = elems * (plan->fp64 ? sizeof(double2) : sizeof(float2));
     HIPCHK(hipMemcpyAsync(out_dev, plan->d_synd, bytes, hipMemcpyDeviceToDevice, plan->stream));
     if (any_sync(plan)) HIPCHK(hipStreamSynchronize(plan->stream));
     return SFT_OK;

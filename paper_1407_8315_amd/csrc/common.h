@@ -11,6 +11,12 @@
 //   ebin       [sig][k]         E_k (general mode)
 //   staging    [sig][M*L]       (location, value) pairs appended by the decoder
 //   counters   [sig]            SigCounters
+// Iterative mode (Alg. 1) keeps, per signal, the syndromes of iteration l as
+// the two lines of "view" l (a SigDev entry of its own, after the signals,
+// with the d, M, offsets and table stride of that iteration's grid), and
+//   status     [sig][l][k]      0 inactive, 1 solved, 2 failed (uint8)
+//   records    [sig][l][k][l+1] (location, value) of the frequencies a solved
+//                               bin holds (SubFreq of later iterations)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,7 +32,7 @@ constexpr int kFftPointsF64 = 4096;
 constexpr int kFftPointsF32Small = 4096;     // blocks of FP32 signals with M <= this (32 KiB)
 constexpr int kActivityTile = 4096;         // bins per block of the activity pass
 
-enum Mode { kExact = 0, kGeneral = 1 };
+enum Mode { kExact = 0, kGeneral = 1, kIterative = 2 };
 
 // Per-signal description, built by the plan and read by every kernel.
 struct SigDev {
@@ -44,6 +50,10 @@ struct SigDev {
     int32_t tab_stride;      // omega table stride: w_d^q = tab[q * tab_stride]
     int32_t log2m1;          // two-pass FFT (M above one block): M = M1 * M2, log2 M1 (0: one pass)
     int64_t y_off;           // two-pass FFT: offset of the [S][M2][M1] intermediate
+    int32_t parent;          // signal whose input and counters this entry uses (itself, or the owner of a view)
+    int32_t view0;           // iterative mode: index of the view of iteration 0
+    int64_t it_st_off;       // iterative mode: offset of the signal's status bytes
+    int64_t it_rec_off;      // iterative mode: offset of the signal's records
     double tau_zero2, tau_rank, tau_res2, tau_amp, c_res, delta_grid, delta_mag;
 };
 
@@ -55,6 +65,15 @@ struct IoDev {
     int64_t cap;
     int64_t* count;
 };
+
+// Iterative mode: bins of iterations 0 .. l-1 (M_0 + M_0/2 + ...), and their
+// records ((l'+1) per bin of iteration l').
+__host__ __device__ inline int64_t iter_bins_off(int64_t m0, int l) { return 2 * m0 - ((2 * m0) >> l); }
+__host__ __device__ inline int64_t iter_rec_off(int64_t m0, int l) {
+    int64_t off = 0;
+    for (int i = 0; i < l; ++i) off += (m0 >> i) * (i + 1);
+    return off;
+}
 
 struct SigCounters {
     int stage_count, active, flagged, cs, mlp_fb, nonfinite, kept, pad;
@@ -226,6 +245,14 @@ struct LaunchCtx {
     int2* qlist;             // [kQueues][list_cap]: round queues, then CS queues
     int64_t list_cap;        // total bins of the plan
     int n_work_blocks;       // grid of the list-driven kernels
+    // iterative mode (Alg. 1)
+    bool iterative;
+    uint8_t* it_status;
+    int64_t* it_loc;
+    double2* it_val;
+    const int2* it_items;            // (sig, bin0): tiles of kBlock bins, iteration by iteration
+    int it_item_off[kMaxL];
+    int it_n_items[kMaxL];
 };
 
 hipError_t launch_zero_counters(const LaunchCtx& c);
@@ -240,5 +267,6 @@ hipError_t launch_round(const LaunchCtx& c, int round);
 hipError_t launch_rest(const LaunchCtx& c);   // rounds 1.. in one kernel (plans without general-mode signals)
 hipError_t launch_cs(const LaunchCtx& c);
 hipError_t launch_output(const LaunchCtx& c);
+hipError_t launch_iteration(const LaunchCtx& c, int l);   // Alg. 1, iteration l (scan, then SynDec for l >= 1)
 
 }  // namespace sft

@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void syndrome_kernel(const SigDev* __restri
     if (it.x < 0) return;   // padding item
     const int s = it.x, line0 = it.y, nl = it.z, pass = it.w;
     const SigDev sg = sigs[s];
-    const V* __restrict__ x = reinterpret_cast<const V*>(io[s].x);
+    const V* __restrict__ x = reinterpret_cast<const V*>(io[sg.parent].x);
     const int log2m = sg.log2m;
     const int log2m1 = sg.log2m1, log2m2 = log2m - log2m1;
     const int log2len = pass == 0 ? log2m : (pass == 1 ? log2m2 : log2m1);
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void syndrome_kernel(const SigDev* __restri
                 }
             }
         }
-        if ((sg.flags & 4) && bad) atomicAdd(&cnt[s].nonfinite, bad);
+        if ((sg.flags & 4) && bad) atomicAdd(&cnt[sg.parent].nonfinite, bad);
     }
     __syncthreads();
 

@@ -1,0 +1,272 @@
+// Iterative sFFT-DT for exactly K-sparse signals on the device (Alg. 1).
+//
+// Iteration l works on the grid of M_l = M_0 / 2^l bins (d_l = 2^l d_0).  The
+// syndromes of its two new shifts 2l and 2l + 1 come from the FFT stage (the
+// two lines of the signal's view l); those of the earlier shifts are folded
+// from the finer grids they were taken on, m_{2d,j}[k] = m_{d,j}[k] +
+// m_{d,j}[k + M/2] (Eq. (3): a residue class mod M/2 is the union of two
+// classes mod M).  Per iteration:
+//   scan   one lane per bin of the grid: SubFreq on the two new syndromes
+//          (contributions of every frequency solved so far whose location is
+//          k mod M_l), the activity test with T (the bins whose decode failed
+//          in the previous iteration, reduced mod M_l), and at l = 0 SynDec
+//          itself (a = 1: z_0 = m_1/m_0, p_0 = m_0).  For l >= 1 the active
+//          bins are queued;
+//   solve  (l >= 1) one lane per queued bin: the 2l + 2 syndromes folded to
+//          the grid, de-rotated and reduced by SubFreq, SynDec at order
+//          a = l + 1 (Steps (i)-(iii) of Sec. II-B), the grid check and the
+//          exact-mode judge.
+// A solved bin stores its l + 1 (location, value) pairs for the SubFreq of
+// later iterations and appends them to the signal's staging list; the output
+// pass sorts them as in the non-iterative mode.
+//
+// Work is in de-rotated form: for bin k the syndrome of shift j is multiplied
+// by e^{-i 2 pi k j / N}, so a frequency s = k + t M_l contributes
+// p w_{d_l}^{t j}, read from the FP64 table of d-th roots.
+#include "algebra.h"
+#include "waves.h"
+
+namespace sft {
+
+template <typename T>
+struct IterV;
+template <>
+struct IterV<float> {
+    using type = float2;
+};
+template <>
+struct IterV<double> {
+    using type = double2;
+};
+
+enum : uint8_t { kIterIdle = 0, kIterSolved = 1, kIterFailed = 2 };
+
+// SubFreq for bin k of iteration l, in de-rotated form: mt[c] (shift j0 + c,
+// c < CNT) -= p w_{d_l}^{(t (j0 + c)) mod d_l} for every pair (s, p) solved in
+// iterations 0 .. l-1 with s = k mod M_l, t = (s - k) / M_l.  The bins of
+// iteration l' that fold into k are k + i M_l, i < 2^{l - l'}.
+template <int CNT>
+__device__ __attribute__((always_inline)) inline void sub_solved(zd* mt, int j0, int l, int64_t k, const SigDev& sg,
+                                                                   const SigDev& v, const uint8_t* __restrict__ status,
+                                                                   const int64_t* __restrict__ rs,
+                                                                   const double2* __restrict__ rp,
+                                                                   const double2* __restrict__ tab) {
+    const int64_t m0 = sg.m;
+    const int64_t dmask = v.d - 1;
+    for (int lp = 0; lp < l; ++lp) {
+        const uint8_t* st = status + sg.it_st_off + iter_bins_off(m0, lp);
+        const int64_t roff = sg.it_rec_off + iter_rec_off(m0, lp);
+        const int reps = 1 << (l - lp);
+        for (int i = 0; i < reps; ++i) {
+            const int64_t b = k + (int64_t)i * v.m;
+            if (st[b] != kIterSolved) continue;
+            for (int e = 0; e <= lp; ++e) {
+                const int64_t s = rs[roff + b * (lp + 1) + e];
+                const double2 pv = rp[roff + b * (lp + 1) + e];
+                const zd p{pv.x, pv.y};
+                const int64_t t = (s - k) >> v.log2m;
+#pragma unroll
+                for (int c = 0; c < CNT; ++c) mt[c] = mt[c] - p * omega(tab, v.tab_stride, (t * (j0 + c)) & dmask);
+            }
+        }
+    }
+}
+
+// Dense pass of iteration l over tiles of kBlock bins.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void iter_scan_kernel(const SigDev* __restrict__ sigs, const int2* __restrict__ items,
+                                                           int l, const typename IterV<T>::type* __restrict__ synd,
+                                                           const double* __restrict__ epart,
+                                                           const double2* __restrict__ tab, uint8_t* __restrict__ status,
+                                                           int64_t* __restrict__ rs, double2* __restrict__ rp,
+                                                           SigCounters* __restrict__ cnt, int64_t* __restrict__ st_loc,
+                                                           double2* __restrict__ st_val, WorkCounters* __restrict__ work,
+                                                           int2* __restrict__ qlist, int64_t list_cap) {
+    __shared__ BlockQueues bq;
+    const int2 it = items[blockIdx.x];
+    if (it.x < 0) return;   // padding item
+    const int s = it.x;
+    const SigDev& sg = sigs[s];
+    const SigDev& v = sigs[sg.view0 + l];
+    const int64_t k = (int64_t)it.y + threadIdx.x;
+    const bool valid = k < v.m;
+    const double eref = (epart[v.epart_off] + epart[v.epart_off + 1]) / (double)v.m;
+    uint8_t* st = status + sg.it_st_off + iter_bins_off(sg.m, l);
+    if (l > 0) bq.reset();
+
+    bool act = false, solved = false;
+    int q = -1;
+    zd p{0.0, 0.0};
+    int64_t loc = 0;
+    if (valid) {
+        // the two new syndromes, de-rotated: shifts 2l and 2l + 1
+        zd mt[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const auto x = synd[v.synd_off + (int64_t)c * v.m + k];
+            const int64_t j = 2 * l + c;
+            mt[c] = cmul_conj(unit_root((k * j) & (sg.n - 1), sg.n), zd{(double)x.x, (double)x.y});
+        }
+        if (l == 0) {
+            const double e = norm2(mt[0]) + norm2(mt[1]);
+            act = e > sg.tau_zero2 * eref;
+            if (act) {
+                // SynDec, a = 1: z_0 = m_1 / m_0, p_0 = m_0, grid check, judge
+                const zd z = cdiv(mt[1], mt[0]);
+                int64_t t[kMaxL];
+                bool ok = cfinite(z) && roots_to_grid(&z, 1, v.d, sg.delta_grid, sg.delta_mag, t);
+                if (ok) {
+                    const zd r = mt[1] - mt[0] * omega(tab, v.tab_stride, t[0]);
+                    ok = norm2(r) <= sg.tau_res2 * e;
+                }
+                if (ok) {
+                    solved = true;
+                    p = mt[0];
+                    loc = k + t[0] * (int64_t)v.m;
+                }
+            }
+            st[k] = !act ? kIterIdle : (solved ? kIterSolved : kIterFailed);
+            if (solved) {
+                rs[sg.it_rec_off + k] = loc;
+                rp[sg.it_rec_off + k] = double2{p.x, p.y};
+            }
+        } else {
+            // T: a bin of iteration l - 1 that folds into k failed
+            const uint8_t* prev = status + sg.it_st_off + iter_bins_off(sg.m, l - 1);
+            const bool in_t = prev[k] == kIterFailed || prev[k + v.m] == kIterFailed;
+            sub_solved<2>(mt, 2 * l, l, k, sg, v, status, rs, rp, tab);
+            act = in_t || norm2(mt[0]) + norm2(mt[1]) > sg.tau_zero2 * eref;
+            st[k] = act ? kIterFailed : kIterIdle;   // the solve pass marks the solved ones
+            if (act) q = q_round(0, l);
+        }
+    }
+    wave_count(&cnt[s].active, act);
+    if (l == 0) {
+        if (sg.L == 1) wave_count(&cnt[s].flagged, act && !solved);
+        int pos = wave_add(&cnt[s].stage_count, solved ? 1 : 0);
+        if (solved && pos < sg.stage_cap) {
+            st_loc[sg.stage_off + pos] = loc;
+            st_val[sg.stage_off + pos] = double2{p.x, p.y};
+        }
+    } else {
+        const int slot = bq.reserve(q);
+        bq.commit(work, nullptr, qlist, list_cap, q, slot, int2{s, (int)k});
+    }
+}
+
+// SynDec at order A = l + 1 for the bins queued by the scan of iteration l.
+template <typename T, int A>
+__global__ __launch_bounds__(kBlock) void iter_solve_kernel(const SigDev* __restrict__ sigs,
+                                                            const typename IterV<T>::type* __restrict__ synd,
+                                                            const double2* __restrict__ tab,
+                                                            uint8_t* __restrict__ status, int64_t* __restrict__ rs,
+                                                            double2* __restrict__ rp, SigCounters* __restrict__ cnt,
+                                                            int64_t* __restrict__ st_loc, double2* __restrict__ st_val,
+                                                            const WorkCounters* __restrict__ work,
+                                                            const int2* __restrict__ qlist, int64_t list_cap) {
+    constexpr int l = A - 1;
+    const int q = q_round(0, l);
+    const int total = work->q[q];
+    const int2* in = qlist + (int64_t)q * list_cap;
+    for (int item = blockIdx.x * kBlock + threadIdx.x; item < total; item += gridDim.x * kBlock) {
+        const int2 en = in[item];
+        const int s = en.x;
+        const int64_t k = en.y;
+        const SigDev& sg = sigs[s];
+        const SigDev& v = sigs[sg.view0 + l];
+        // syndromes of shifts 0 .. 2A-1 on this grid: shift j was taken at
+        // iteration j / 2 and is folded 2^{l - j/2} times
+        zd mt[2 * kMaxL];
+#pragma unroll
+        for (int j = 0; j < 2 * kMaxL; ++j) {
+            mt[j] = zd{0.0, 0.0};
+            if (j >= 2 * A) continue;
+            const SigDev& vj = sigs[sg.view0 + j / 2];
+            const auto* row = synd + vj.synd_off + (int64_t)(j & 1) * vj.m + k;
+            const int reps = 1 << (l - j / 2);
+            zd acc{0.0, 0.0};
+            for (int i = 0; i < reps; ++i) {
+                const auto x = row[(int64_t)i * v.m];
+                acc = acc + zd{(double)x.x, (double)x.y};
+            }
+            mt[j] = acc;
+        }
+        // de-rotate: shift j by e^{-i 2 pi k j / N} (running powers)
+        {
+            const zd w1 = unit_root(k & (sg.n - 1), sg.n);
+            zd w{1.0, 0.0};
+#pragma unroll
+            for (int j = 0; j < 2 * A; ++j) {
+                mt[j] = cmul_conj(w, mt[j]);
+                w = w * w1;
+            }
+        }
+        sub_solved<2 * A>(mt, 0, l, k, sg, v, status, rs, rp, tab);
+        double e = 0.0;
+#pragma unroll
+        for (int j = 0; j < 2 * A; ++j) e += norm2(mt[j]);
+        zd c[kMaxL], z[kMaxL], p[kMaxL];
+        int64_t t[kMaxL];
+        double r2 = 0.0;
+        bool ok = locator(mt, A, c) && poly_roots(c, A, z) &&
+                  roots_to_grid(z, A, v.d, sg.delta_grid, sg.delta_mag, t) &&
+                  vandermonde_ls(mt, 2 * A, t, A, v.d, tab, v.tab_stride, p, r2) && r2 <= sg.tau_res2 * e;
+        if (ok) {
+            status[sg.it_st_off + iter_bins_off(sg.m, l) + k] = kIterSolved;
+            const int64_t roff = sg.it_rec_off + iter_rec_off(sg.m, l) + k * A;
+#pragma unroll
+            for (int j = 0; j < A; ++j) {
+                rs[roff + j] = k + t[j] * (int64_t)v.m;
+                rp[roff + j] = double2{p[j].x, p[j].y};
+            }
+        }
+        if (l == sg.L - 1) wave_count(&cnt[s].flagged, !ok);
+        int pos = wave_add(&cnt[s].stage_count, ok ? A : 0);
+        if (ok) {
+#pragma unroll
+            for (int j = 0; j < A; ++j)
+                if (pos + j < sg.stage_cap) {
+                    st_loc[sg.stage_off + pos + j] = k + t[j] * (int64_t)v.m;
+                    st_val[sg.stage_off + pos + j] = double2{p[j].x, p[j].y};
+                }
+        }
+    }
+}
+
+template <typename T>
+static void launch_iteration_t(const LaunchCtx& c, int l) {
+    using V = typename IterV<T>::type;
+    const int n = c.it_n_items[l];
+    if (n == 0) return;
+    hipLaunchKernelGGL(iter_scan_kernel<T>, dim3(n), dim3(kBlock), 0, c.stream, c.sigs, c.it_items + c.it_item_off[l], l,
+                       (const V*)c.synd, c.epart, c.omega, c.it_status, c.it_loc, c.it_val, c.cnt, c.st_loc, c.st_val,
+                       c.work, c.qlist, c.list_cap);
+    switch (l) {
+        case 1:
+            hipLaunchKernelGGL((iter_solve_kernel<T, 2>), dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs,
+                               (const V*)c.synd, c.omega, c.it_status, c.it_loc, c.it_val, c.cnt, c.st_loc, c.st_val,
+                               c.work, c.qlist, c.list_cap);
+            break;
+        case 2:
+            hipLaunchKernelGGL((iter_solve_kernel<T, 3>), dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs,
+                               (const V*)c.synd, c.omega, c.it_status, c.it_loc, c.it_val, c.cnt, c.st_loc, c.st_val,
+                               c.work, c.qlist, c.list_cap);
+            break;
+        case 3:
+            hipLaunchKernelGGL((iter_solve_kernel<T, 4>), dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs,
+                               (const V*)c.synd, c.omega, c.it_status, c.it_loc, c.it_val, c.cnt, c.st_loc, c.st_val,
+                               c.work, c.qlist, c.list_cap);
+            break;
+        default:
+            break;
+    }
+}
+
+hipError_t launch_iteration(const LaunchCtx& c, int l) {
+    if (l < 0 || l >= kMaxL) return hipErrorInvalidValue;
+    if (c.fp64) launch_iteration_t<double>(c, l);
+    else launch_iteration_t<float>(c, l);
+    return hipGetLastError();
+}
+
+}  // namespace sft

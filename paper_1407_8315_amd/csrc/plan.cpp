@@ -152,8 +152,8 @@ sft_status resolve_params(const sft_params& in, bool batch, SigHost* g, std::str
         *msg = "in_dtype must be SFT_C64 or SFT_C128";
         return SFT_E_INVALID;
     }
-    if (in.mode != SFT_MODE_EXACT && in.mode != SFT_MODE_GENERAL) {
-        *msg = "mode must be SFT_MODE_EXACT or SFT_MODE_GENERAL";
+    if (in.mode != SFT_MODE_EXACT && in.mode != SFT_MODE_GENERAL && in.mode != SFT_MODE_ITERATIVE) {
+        *msg = "mode must be SFT_MODE_EXACT, SFT_MODE_GENERAL or SFT_MODE_ITERATIVE";
         return SFT_E_INVALID;
     }
     if (in.n < 2 || in.k < 1 || in.k > in.n) {
@@ -211,6 +211,17 @@ sft_status resolve_params(const sft_params& in, bool batch, SigHost* g, std::str
         *msg = "d = N/M above 2^22 is not supported";
         return SFT_E_UNSUPPORTED;
     }
+    if (g->mode == SFT_MODE_ITERATIVE) {
+        // iteration l runs on M_0 / 2^l bins with d_0 2^l
+        if ((g->m >> (g->L - 1)) < 1) {
+            *msg = "iterative mode needs M_0 >= 2^(L-1)";
+            return SFT_E_UNSUPPORTED;
+        }
+        if ((g->d << (g->L - 1)) > kMaxD) {
+            *msg = "iterative mode: d_0 2^(L-1) above 2^22 is not supported";
+            return SFT_E_UNSUPPORTED;
+        }
+    }
     if ((int64_t)g->m * g->L > (int64_t(1) << 30)) {
         *msg = "M * L too large";
         return SFT_E_UNSUPPORTED;
@@ -261,7 +272,7 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
     int64_t mmax = 1, dmax = 1;
     for (auto& g : sigs) {
         mmax = std::max(mmax, g.m);
-        dmax = std::max(dmax, g.d);
+        dmax = std::max(dmax, g.mode == SFT_MODE_ITERATIVE ? g.d << (g.L - 1) : g.d);
     }
     lay->tw_log2 = ilog2(mmax);
     lay->om_log2 = ilog2(dmax);
@@ -287,7 +298,7 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
         for (auto& v : lane_sigs) std::sort(v.begin(), v.end());
     }
 
-    int64_t synd = 0, ep = 0, bins = 0, stage = 0, ybuf = 0;
+    int64_t synd = 0, ep = 0, bins = 0, stage = 0, ybuf = 0, it_st = 0, it_rec = 0;
     lay->sigdev.resize(sigs.size());
     for (size_t i = 0; i < sigs.size(); ++i) {
         const SigHost& g = sigs[i];
@@ -312,7 +323,16 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
         s.tab_stride = (int32_t)(dmax / g.d);
         s.log2m1 = g.m > pmax ? (ilog2(g.m) + 1) / 2 : 0;   // M1 = 2^ceil(log2 M / 2)
         s.y_off = ybuf;
-        if (g.m > pmax) ybuf += (int64_t)g.S * g.m;
+        const bool iter = g.mode == SFT_MODE_ITERATIVE;
+        if (g.m > pmax && !iter) ybuf += (int64_t)g.S * g.m;
+        s.parent = (int32_t)i;
+        s.view0 = -1;
+        if (iter) {
+            s.it_st_off = it_st;
+            s.it_rec_off = it_rec;
+            it_st += iter_bins_off(g.m, g.L);
+            it_rec += iter_rec_off(g.m, g.L);
+        }
         s.tau_zero2 = g.tau_zero * g.tau_zero;
         s.tau_rank = g.tau_rank;
         s.tau_res2 = g.tau_res * g.tau_res;
@@ -328,6 +348,35 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
         stage += g.m * g.L;
         if (g.mode == SFT_MODE_GENERAL) lay->general_sigs.push_back((int)i);
     }
+    // Iterative signals: one view per iteration l, with the grid of that
+    // iteration (d_0 2^l, M_0 / 2^l) and its two shifts 2l, 2l + 1, whose
+    // syndromes sit after those of the earlier iterations in the signal's
+    // syndrome region (2 (M_0 + M_0/2 + ...) <= 2L M_0 elements).
+    for (size_t i = 0; i < sigs.size(); ++i) {
+        const SigHost& g = sigs[i];
+        if (g.mode != SFT_MODE_ITERATIVE) continue;
+        lay->sigdev[i].view0 = (int32_t)lay->sigdev.size();
+        for (int l = 0; l < g.L; ++l) {
+            SigDev v = lay->sigdev[i];
+            v.d = g.d << l;
+            v.m = (int32_t)(g.m >> l);
+            v.log2m = ilog2(v.m);
+            v.S = 2;
+            v.L = 1;
+            v.synd_off = lay->sigdev[i].synd_off + 2 * iter_bins_off(g.m, l);
+            v.epart_off = lay->sigdev[i].epart_off + 2 * l;
+            v.shift_off = lay->sigdev[i].shift_off + 2 * l;
+            v.tab_stride = (int32_t)(dmax / v.d);
+            v.log2m1 = v.m > pmax ? (v.log2m + 1) / 2 : 0;
+            v.y_off = ybuf;
+            if (v.m > pmax) ybuf += 2 * (int64_t)v.m;
+            v.view0 = -1;
+            lay->sigdev.push_back(v);
+        }
+        lay->n_iterative += 1;
+    }
+    lay->it_st_elems = it_st;
+    lay->it_rec_elems = it_rec;
     lay->synd_elems = synd;
     lay->epart_elems = ep;
     lay->bin_elems = bins;
@@ -359,58 +408,94 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
         for (size_t j = 0; j < len; ++j)
             for (int l = 0; l < kLanes; ++l) out.push_back(j < lanes[l].size() ? lanes[l][j] : pad);
     };
-    // FP32 signals with M <= kFftPointsF32Small: blocks of fewer points (one
+    // FFT units: a signal, or for an iterative signal each of its views
+    // (items of one signal stay in its lane, so its views share the XCD's L2)
+    auto for_units = [&](int s, auto fn) {
+        const SigHost& g = sigs[s];
+        if (g.mode == SFT_MODE_ITERATIVE) {
+            for (int l = 0; l < g.L; ++l) {
+                const int idx = lay->sigdev[s].view0 + l;
+                fn(idx, (int64_t)lay->sigdev[idx].m, 2, lay->sigdev[idx].log2m1);
+            }
+        } else {
+            fn(s, g.m, g.S, lay->sigdev[s].log2m1);
+        }
+    };
+    // FP32 units with M <= kFftPointsF32Small: blocks of fewer points (one
     // line of 4096, or more lines of fewer) and a smaller LDS footprint, so that
     // more blocks share a CU and overlap their gathers
-    const auto small = [&](const SigHost& g) { return !fp64 && g.m <= kFftPointsF32Small; };
+    const auto small = [&](int64_t m) { return !fp64 && m <= kFftPointsF32Small; };
     interleave(
         [&](int s, std::vector<int4>& v) {
-            const SigHost& g = sigs[s];
-            if (!small(g)) return;
-            const int nl = (int)std::max<int64_t>(1, std::min<int64_t>(g.S, kFftPointsF32Small / g.m));
-            for (int l0 = 0; l0 < g.S; l0 += nl) v.push_back(int4{s, l0, std::min(nl, g.S - l0), 0});
+            for_units(s, [&](int idx, int64_t m, int S, int lm1) {
+                (void)lm1;
+                if (!small(m)) return;
+                const int nl = (int)std::max<int64_t>(1, std::min<int64_t>(S, kFftPointsF32Small / m));
+                for (int l0 = 0; l0 < S; l0 += nl) v.push_back(int4{idx, l0, std::min(nl, S - l0), 0});
+            });
         },
         int4{-1, 0, 0, 0}, lay->synd_small_items);
     interleave(
         [&](int s, std::vector<int4>& v) {
-            const SigHost& g = sigs[s];
-            if (small(g)) return;
-            if (g.m <= pmax) {
-                int nl = (int)std::max<int64_t>(1, std::min<int64_t>(g.S, pmax / g.m));
-                for (int l0 = 0; l0 < g.S; l0 += nl) v.push_back(int4{s, l0, std::min(nl, g.S - l0), 0});
-            } else {
-                // first of two passes: S * M1 lines of length M2
-                const int lm1 = lay->sigdev[s].log2m1, lm2 = ilog2(g.m) - lm1;
-                const int64_t lines = (int64_t)g.S << lm1;
-                const int nl = (int)std::min<int64_t>(lines, pmax >> lm2);
-                for (int64_t l0 = 0; l0 < lines; l0 += nl) v.push_back(int4{s, (int)l0, (int)std::min<int64_t>(nl, lines - l0), 1});
-            }
+            for_units(s, [&](int idx, int64_t m, int S, int lm1) {
+                if (small(m)) return;
+                if (m <= pmax) {
+                    int nl = (int)std::max<int64_t>(1, std::min<int64_t>(S, pmax / m));
+                    for (int l0 = 0; l0 < S; l0 += nl) v.push_back(int4{idx, l0, std::min(nl, S - l0), 0});
+                } else {
+                    // first of two passes: S * M1 lines of length M2
+                    const int lm2 = ilog2(m) - lm1;
+                    const int64_t lines = (int64_t)S << lm1;
+                    const int nl = (int)std::min<int64_t>(lines, pmax >> lm2);
+                    for (int64_t l0 = 0; l0 < lines; l0 += nl)
+                        v.push_back(int4{idx, (int)l0, (int)std::min<int64_t>(nl, lines - l0), 1});
+                }
+            });
         },
         int4{-1, 0, 0, 0}, lay->synd_items);
     interleave(
         [&](int s, std::vector<int4>& v) {
-            const SigHost& g = sigs[s];
-            if (g.m <= pmax) return;
-            // second pass: S * M2 lines of length M1
-            const int lm1 = lay->sigdev[s].log2m1, lm2 = ilog2(g.m) - lm1;
-            const int64_t lines = (int64_t)g.S << lm2;
-            const int nl = (int)std::min<int64_t>(lines, pmax >> lm1);
-            for (int64_t l0 = 0; l0 < lines; l0 += nl) v.push_back(int4{s, (int)l0, (int)std::min<int64_t>(nl, lines - l0), 2});
+            for_units(s, [&](int idx, int64_t m, int S, int lm1) {
+                if (m <= pmax) return;
+                // second pass: S * M2 lines of length M1
+                const int lm2 = ilog2(m) - lm1;
+                const int64_t lines = (int64_t)S << lm2;
+                const int nl = (int)std::min<int64_t>(lines, pmax >> lm1);
+                for (int64_t l0 = 0; l0 < lines; l0 += nl)
+                    v.push_back(int4{idx, (int)l0, (int)std::min<int64_t>(nl, lines - l0), 2});
+            });
         },
         int4{-1, 0, 0, 0}, lay->synd2_items);
     for (size_t s = 0; s < sigs.size(); ++s)
-        if (sigs[s].m > pmax)
-            for (int l = 0; l < sigs[s].S; ++l) lay->line_items.push_back(int2{(int)s, l});
+        for_units((int)s, [&](int idx, int64_t m, int S, int lm1) {
+            (void)lm1;
+            if (m > pmax)
+                for (int l = 0; l < S; ++l) lay->line_items.push_back(int2{idx, l});
+        });
     interleave(
         [&](int s, std::vector<int2>& v) {
+            if (sigs[s].mode == SFT_MODE_ITERATIVE) return;
             for (int64_t b = 0; b < sigs[s].m; b += kBlock) v.push_back(int2{s, (int)b});
         },
         int2{-1, 0}, lay->bin_items);
     interleave(
         [&](int s, std::vector<int2>& v) {
+            if (sigs[s].mode == SFT_MODE_ITERATIVE) return;
             for (int64_t b = 0; b < sigs[s].m; b += kActivityTile) v.push_back(int2{s, (int)b});
         },
         int2{-1, 0}, lay->act_items);
+    // iterative signals: tiles of kBlock bins of the grid of each iteration
+    for (int l = 0; l < kMaxL; ++l) {
+        lay->it_item_off[l] = (int)lay->it_items.size();
+        interleave(
+            [&](int s, std::vector<int2>& v) {
+                const SigHost& g = sigs[s];
+                if (g.mode != SFT_MODE_ITERATIVE || l >= g.L) return;
+                for (int64_t b = 0; b < (g.m >> l); b += kBlock) v.push_back(int2{s, (int)b});
+            },
+            int2{-1, 0}, lay->it_items);
+        lay->it_n_items[l] = (int)lay->it_items.size() - lay->it_item_off[l];
+    }
 }
 
 void twiddle_table_f64(int log2n, std::vector<double2>* out) {

@@ -22,7 +22,7 @@ struct SigHost {
 };
 
 struct PlanLayout {
-    std::vector<SigDev> sigdev;
+    std::vector<SigDev> sigdev;           // the signals, then the views of iterative signals
     std::vector<int64_t> shifts;          // per signal: 0..2L-1, then n_j
     std::vector<int4> synd_items;         // (sig, line0, nlines, pass 0|1); sig < 0 = padding
     std::vector<int4> synd_small_items;   // one-pass FP32 signals with M <= kFftPointsF32Small
@@ -31,6 +31,11 @@ struct PlanLayout {
     std::vector<int2> bin_items;          // (sig, bin0)
     std::vector<int2> act_items;          // (sig, bin0), tiles of kActivityTile
     std::vector<int> general_sigs;
+    std::vector<int2> it_items;           // iterative mode: (sig, bin0) per iteration, concatenated
+    int it_item_off[kMaxL] = {0, 0, 0, 0};
+    int it_n_items[kMaxL] = {0, 0, 0, 0};
+    int64_t it_st_elems = 0, it_rec_elems = 0;
+    int n_iterative = 0;
     int64_t synd_elems = 0, epart_elems = 0, sigma_elems = 0, bin_elems = 0, stage_elems = 0, y_elems = 0;
     int tw_log2 = 0, om_log2 = 0;
     int n_general = 0;

@@ -41,7 +41,7 @@ def test_every_declared_function_is_exported(lib):
 def test_version_and_status_strings(lib):
     from paper_1407_8315_amd import _lib
 
-    assert lib.sft_abi_version() == 2
+    assert lib.sft_abi_version() == 3
     assert lib.sft_status_str(_lib.SFT_E_CAPACITY) == b"SFT_E_CAPACITY"
     assert lib.sft_status_str(99) == b"unknown status"
 
@@ -96,12 +96,30 @@ def _plan_status(lib, **kw):
     (dict(n=1 << 14, k=50, mode="general", flags=8), "SFT_E_INVALID"),        # autotune in general mode
     (dict(n=1 << 14, k=50, target_recovery=0.99), "SFT_E_INVALID"),           # target without autotune
     (dict(n=1 << 14, k=50, flags=8, target_recovery=1.5), "SFT_E_INVALID"),   # target outside [0, 1)
+    (dict(n=1 << 14, k=50, m=4, l=4, mode="iterative"), "SFT_E_UNSUPPORTED"),   # M_0 < 2^(L-1)
+    (dict(n=1 << 24, k=50, m=2, l=4, mode="iterative"), "SFT_E_UNSUPPORTED"),   # d_0 2^(L-1) above 2^22
+    (dict(n=1 << 14, k=50, mode="iterative", flags=1), "SFT_E_UNSUPPORTED"),    # learned order: exact mode only
+    (dict(n=1 << 14, k=50, mode="iterative", flags=8), "SFT_E_INVALID"),        # autotune: exact mode only
+    (dict(n=1 << 14, k=50, mode="iterative", r=2), "SFT_E_INVALID"),            # R: general mode only
 ])
 def test_parameter_validation(lib, kw, status):
     st, h = _plan_status(lib, **kw)
     assert lib.sft_status_str(st).decode() == status
     assert h.value is None
     assert lib.sft_last_error()
+
+
+def test_mixed_iterative_plan_is_rejected(lib):
+    """A plan's signals are all iterative or none is (checked before any device call)."""
+    from paper_1407_8315_amd import make_params
+
+    arr = (type(make_params(n=64, k=1)) * 2)(make_params(n=1 << 12, k=8, mode="iterative"),
+                                             make_params(n=1 << 12, k=8, mode="exact"))
+    h = ctypes.c_void_p()
+    st = lib.sft_plan(ctypes.byref(h), arr, 2, None)
+    assert lib.sft_status_str(st).decode() == "SFT_E_UNSUPPORTED"
+    assert h.value is None
+    assert b"ITERATIVE" in lib.sft_last_error()
 
 
 def test_null_arguments(lib):
@@ -111,6 +129,7 @@ def test_null_arguments(lib):
     h = ctypes.c_void_p()
     assert lib.sft_plan(ctypes.byref(h), None, 1, None) == _lib.SFT_E_INVALID
     assert lib.sft_exact(None, None, None, None) == _lib.SFT_E_INVALID
+    assert lib.sft_iterative(None, None, None, None) == _lib.SFT_E_INVALID
     assert lib.sft_batch(None, None, None, None) == _lib.SFT_E_INVALID
     assert lib.sft_plan_get(None, 0, None) == _lib.SFT_E_INVALID
     lib.sft_destroy(None)

@@ -1,0 +1,231 @@
+"""GPU parity of iterative sFFT-DT (Alg. 1) against the FP64 oracle, through the C ABI.
+
+Tolerances as for the non-iterative path: complex128 input runs the FFTs in
+FP64 (syndromes within 1e-12 of the oracle's, values within 1e-10, supports
+and counts exact); complex64 input runs them in FP32 (syndromes within 2e-6
+relative L2; supports and counts compared with the oracle run on the
+FP32-rounded syndromes, values within 1e-5 relative L2 of the FP64 oracle).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import sftgen
+from oracle import iterative as oit
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def sft():
+    import paper_1407_8315_amd as m
+
+    return m
+
+
+def to_dev(torch, x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def exact_signal(n, locs, vals, dtype=np.complex128):
+    xh = np.zeros(n, np.complex128)
+    xh[np.asarray(locs, np.int64)] = vals
+    return np.fft.ifft(xh).astype(dtype)
+
+
+def run_iter(torch, sft, x, n, m0, L, dtype):
+    plan = sft.Plan(dict(n=n, k=1, m=m0, l=L, dtype=dtype, mode="iterative"))
+    res = plan.iterative(to_dev(torch, x), stats=True)
+    loc, val = res.host()
+    plan.close()
+    return loc, val, res.stats
+
+
+# ------------------------------------------------------------ syndromes
+
+
+@pytest.mark.parametrize("n,m0,L,dtype", [
+    (1 << 14, 256, 4, "c128"),
+    (1 << 20, 4096, 4, "c64"),
+    (16, 8, 4, "c128"),              # d_0 = 2: indices wrap; the last grid has one bin
+    (1 << 16, 16384, 2, "c64"),      # iteration 0 in two FFT passes, iteration 1 in one
+])
+def test_iterative_syndromes_match_oracle(torch, sft, n, m0, L, dtype):
+    say(f"[iter syndromes] n={n} m0={m0} L={L} {dtype}")
+    npdt = np.complex128 if dtype == "c128" else np.complex64
+    s = sftgen.make_signal(n, max(1, m0 // 4), 12, amp="gauss", dtype=npdt)
+    plan = sft.Plan(dict(n=n, k=1, m=m0, l=L, dtype=dtype, mode="iterative"))
+    got = [g.cpu().numpy() for g in plan.syndromes(to_dev(torch, s.x))]
+    torch.cuda.synchronize()
+    plan.close()
+    assert len(got) == L
+    for l in range(L):
+        ref = oracle.syndromes(s.x, n, m0 >> l, [2 * l, 2 * l + 1])
+        assert got[l].shape == ref.shape
+        if dtype == "c128":
+            assert np.max(np.abs(got[l] - ref)) <= 1e-12 * np.max(np.abs(ref))
+        else:
+            assert rel_l2(got[l], ref) <= 2e-6
+
+
+# ------------------------------------------------------------ parity
+
+
+def check_c128(torch, sft, x, n, m0, L):
+    loc, val, st = run_iter(torch, sft, x, n, m0, L, "c128")
+    ref, levels = oit.sfft_iterative(x, n, m0, L)
+    assert loc.tolist() == ref.locs.tolist()
+    if len(loc):
+        assert np.max(np.abs(val - ref.vals)) <= 1e-10
+    assert st["active_bins"] == ref.active_bins
+    assert st["flagged_bins"] == ref.flagged_bins
+    return loc, levels
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_iterative_paper_setting_complex128(torch, sft, seed):
+    """N = 2^14, K = 64, d_0 = N / (4K) (M_0 = 256), a_m = 4, unit amplitudes."""
+    n, k = 1 << 14, 64
+    say(f"[iter c128] seed={seed}")
+    s = sftgen.make_signal(n, k, sftgen.BASE_SEED + 300 + seed, amp="unit", dtype=np.complex128)
+    loc, _ = check_c128(torch, sft, s.x, n, 4 * k, 4)
+    assert loc.tolist() == sorted(s.locs.tolist())
+
+
+@pytest.mark.parametrize("n,m0,k,seed", [(4096, 64, 100, 2), (1 << 14, 128, 200, 3), (2048, 16, 30, 5),
+                                         (4096, 64, 40, 1)])
+def test_iterative_collisions_of_every_order(torch, sft, n, m0, k, seed):
+    """Supports dense enough that every iteration solves bins (the oracle's
+    support-level simulation cases): GPU and oracle agree bin for bin."""
+    say(f"[iter dense] n={n} m0={m0} k={k}")
+    g = np.random.default_rng(seed)
+    locs = np.sort(g.choice(n, k, replace=False))
+    vals = g.standard_normal(k) + 1j * g.standard_normal(k)
+    x = exact_signal(n, locs, vals)
+    _, levels = check_c128(torch, sft, x, n, m0, 4)
+    assert all(len(lv.solved) > 0 for lv in levels[:3])
+
+
+def test_iterative_t_brings_a_silent_bin_to_its_decode(torch, sft):
+    """The bin whose new syndromes vanish at iteration 2 (only T sends it to
+    SynDec) is solved on the device as in the oracle."""
+    n, m0, k = 1024, 64, 5
+    locs = np.array([k + 1 * m0, k + 6 * m0, k + 11 * m0], np.int64)
+    z = np.exp(2j * np.pi * locs / n)
+    null = np.linalg.svd(np.array([z ** 4, z ** 5]))[2][-1].conj()
+    others = np.array([1, 2 + m0, 3 + 5 * m0], np.int64)
+    all_locs = np.concatenate([locs, others])
+    x = exact_signal(n, all_locs, np.concatenate([null, np.array([0.9, -0.4j, 0.3 + 0.3j])]))
+    loc, levels = check_c128(torch, sft, x, n, m0, 4)
+    assert sorted(levels[2].solved) == sorted(locs.tolist())
+    assert loc.tolist() == sorted(all_locs.tolist())
+
+
+@pytest.mark.parametrize("n,m0,L,k", [
+    (4096, 64, 1, 20),        # one iteration
+    (16, 8, 4, 3),            # d_0 = 2, the last grid has a single bin
+    (1 << 12, 8, 4, 6),       # M_0 = 2^(L-1)
+    (1 << 14, 128, 3, 40),    # tiles of fewer bins than a block
+    (1 << 16, 2048, 2, 600),  # more bins than a block
+])
+def test_iterative_edge_shapes(torch, sft, n, m0, L, k):
+    say(f"[iter edge] n={n} m0={m0} L={L} k={k}")
+    s = sftgen.make_signal(n, k, 77 + L, amp="gauss", dtype=np.complex128)
+    check_c128(torch, sft, s.x, n, m0, L)
+
+
+def test_iterative_zero_signal(torch, sft):
+    n, m0 = 1 << 12, 64
+    loc, val, st = run_iter(torch, sft, np.zeros(n, np.complex128), n, m0, 4, "c128")
+    assert len(loc) == 0 and st["active_bins"] == 0 and st["flagged_bins"] == 0
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_iterative_n20_complex64(torch, sft, seed):
+    """N = 2^20, K = 1000, M_0 = 4096, a_m = 4, complex Gaussian values,
+    complex64: support and counts equal to the oracle's decisions on FP32
+    syndromes, values within 1e-5 relative L2 of the FP64 oracle."""
+    n, k, m0 = 1 << 20, 1000, 4096
+    say(f"[iter c64 N=2^20] seed={seed}")
+    s = sftgen.make_signal(n, k, sftgen.BASE_SEED + 400 + seed, amp="gauss", dtype=np.complex64)
+    loc, val, st = run_iter(torch, sft, s.x, n, m0, 4, "c64")
+    ref32, _ = oit.sfft_iterative(s.x, n, m0, 4, fft_dtype=np.complex64)
+    assert loc.tolist() == ref32.locs.tolist()
+    assert st["active_bins"] == ref32.active_bins and st["flagged_bins"] == ref32.flagged_bins
+    ref, _ = oit.sfft_iterative(s.x.astype(np.complex128), n, m0, 4)
+    truth = dict(zip(ref.locs.tolist(), ref.vals))
+    want = np.array([truth[v] for v in loc.tolist()])
+    assert rel_l2(val, want) <= 1e-5
+
+
+# ------------------------------------------------------------ batches
+
+
+def test_iterative_batch_equals_single_calls_and_replays(torch, sft):
+    """A batch of iterative signals with different N, M_0, a_m and dtype-equal
+    inputs: each output equals its single-signal call bit for bit, and graph
+    replays give the same lists."""
+    cases = [(1 << 14, 256, 4, 64), (1 << 12, 64, 3, 40), (1 << 16, 1024, 4, 256), (1 << 10, 16, 2, 6),
+             (1 << 14, 128, 1, 20), (1 << 13, 512, 4, 128), (1 << 12, 32, 4, 30), (1 << 15, 2048, 2, 300),
+             (1 << 11, 64, 4, 16)]
+    xs, params = [], []
+    for i, (n, m0, L, k) in enumerate(cases):
+        s = sftgen.make_signal(n, k, 500 + i, amp="gauss", dtype=np.complex64)
+        xs.append(to_dev(torch, s.x))
+        params.append(dict(n=n, k=k, m=m0, l=L, dtype="c64", mode="iterative"))
+    plan = sft.Plan(params)
+    outs = plan.batch(xs, stats=True)
+    first = [o.host() for o in outs]
+    for _ in range(2):
+        again = [o.host() for o in plan.batch(xs)]
+        torch.cuda.synchronize()
+        for (l0, v0), (l1, v1) in zip(first, again):
+            assert l0.tolist() == l1.tolist() and np.array_equal(v0, v1)
+    plan.close()
+    for i, p in enumerate(params):
+        single = sft.Plan(p)
+        l1, v1 = single.iterative(xs[i]).host()
+        single.close()
+        assert first[i][0].tolist() == l1.tolist() and np.array_equal(first[i][1], v1)
+
+
+def test_iterative_full_batch_sampled_against_oracle(torch, sft):
+    """The timed workload (N = 2^20, K = 1000, M_0 = 4096, a_m = 4, complex64)
+    as one batch of 256 signals; every 16th signal against the oracle's
+    decisions on FP32 syndromes, all of them against the true support."""
+    n, k, m0, B = 1 << 20, 1000, 4096, 256
+    say(f"[iter batch] B={B}")
+    base = sftgen.BASE_SEED + 9000
+    sigs = [sftgen.make_signal(n, k, base + i, amp="unit", dtype=np.complex64) for i in range(B)]
+    plan = sft.Plan([dict(n=n, k=k, m=m0, l=4, dtype="c64", mode="iterative")] * B)
+    outs = plan.batch([to_dev(torch, s.x) for s in sigs], stats=True)
+    hits = 0
+    for i, (o, s) in enumerate(zip(outs, sigs)):
+        loc, val = o.host()
+        assert set(loc.tolist()) <= set(s.locs.tolist())
+        hits += len(loc)
+        if i % 16 == 0:
+            ref32, _ = oit.sfft_iterative(s.x, n, m0, 4, fft_dtype=np.complex64)
+            assert loc.tolist() == ref32.locs.tolist()
+    plan.close()
+    say(f"[iter batch] support recovery {hits / (B * k):.6f}")
+    assert hits / (B * k) >= 0.999

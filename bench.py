@@ -49,13 +49,14 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=1024)
-    ap.add_argument("--mode", choices=["general", "exact"], default="general")
+    ap.add_argument("--mode", choices=["general", "exact", "iterative"], default="general")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for counter calibration)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain comparison")
     ap.add_argument("--no-uneven", action="store_true", help="skip the batched uneven workload")
+    ap.add_argument("--no-iterative", action="store_true", help="skip the iterative-vs-non-iterative comparison")
     return ap.parse_args()
 
 
@@ -112,6 +113,56 @@ def learned_vs_plain(steps, warmup, B=1024):
         net.close()
     out["speedup_learned_over_plain"] = round(out["plain"]["ms_per_step"] / out["learned"]["ms_per_step"], 4)
     out["workload"] = f"exact, N=2^20, K=1000, M=4096, L=4, unit amplitudes, complex64, batch {B}"
+    return out
+
+
+def iterative_vs_non_iterative(steps, warmup, B=1024):
+    """Exactly K-sparse batch (N = 2^20, K = 1000, unit amplitudes, complex64):
+    non-iterative sFFT-DT (M = 4096, L = 4: 8 FFTs of 4096 points) against
+    iterative sFFT-DT (Alg. 1, M_0 = 4096, a_m = 4: FFTs of 2 x 4096, 2 x 2048,
+    2 x 1024, 2 x 512 points), same signals, graph-replayed steps."""
+    import numpy as np
+    import torch
+
+    import sftgen
+    from paper_1407_8315_amd import Plan
+
+    n, k, m, L = 1 << 20, 1000, 4096, 4
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.Stream(device=dev)
+    out = {}
+    with torch.cuda.stream(stream):
+        xs, truth = [], []
+        for i in range(B):
+            x, locs, _ = sftgen.torch_signal(n, k, sftgen.BASE_SEED + 40000 + i, dev, amp="unit")
+            xs.append(x)
+            truth.append(locs)
+        for name, mode in (("non_iterative", "exact"), ("iterative", "iterative")):
+            plan = Plan([dict(n=n, k=k, m=m, l=L, mode=mode)] * B, stream=stream)
+            outs = [plan.new_output(m * L, dev) for _ in range(B)]
+            run = plan.prepare_batch(xs, outs)
+            for _ in range(warmup):
+                run()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                run()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            found = sum(len(np.intersect1d(o.loc[:int(o.count.item())].cpu().numpy(), t)) for o, t in zip(outs, truth))
+            st = run(stats=True)
+            out[name] = {"ms_per_step": round(ms, 4), "signals_per_s": round(B / ms * 1e3, 1),
+                         "freqs_per_s": round(found / ms * 1e3, 1), "support_recovery": round(found / (B * k), 5),
+                         "stage_ms": [round(v, 4) for v in st["stage_ms"]], "active_bins": st["active_bins"],
+                         "flagged_bins": st["flagged_bins"]}
+            plan.close()
+    out["speedup_iterative_over_non_iterative"] = round(out["non_iterative"]["ms_per_step"]
+                                                        / out["iterative"]["ms_per_step"], 4)
+    out["workload"] = f"exact, N=2^20, K=1000, M(_0)=4096, L=a_m=4, unit amplitudes, complex64, batch {B}"
+    out["stage_ms_meaning"] = {"non_iterative": "gather+FFT, activity+rank test, decode, output",
+                               "iterative": "gather+FFT (all iterations), iteration 0, iterations 1-3, output"}
     return out
 
 
@@ -286,14 +337,17 @@ def main():
     freqs_per_s = found / (ms_step * 1e-3)
     recovery = found / (B * k)
 
-    S = 2 * L + (R if mode == "general" else 0)
-    synd_bytes = B * S * m * 8 * 2                 # gather read + syndrome write, per launch
+    # samples gathered (= syndromes written) per signal: 2L (+ R) lines of M;
+    # iterative: two lines per iteration on grids of M, M/2, ...
+    samples = 2 * sum(m >> l for l in range(L)) if mode == "iterative" else (2 * L + (R if mode == "general" else 0)) * m
+    synd_bytes = B * samples * 8 * 2               # gather read + syndrome write, per launch
     fft_gbs = synd_bytes / (stage[0] * 1e-3) / 1e9
-    rf, rw = TRAFFIC_RATIOS[mode]
-    traffic = int(B * S * m * 8 * (rf + rw))   # measured HBM bytes per launch (fetch + write)
+    ratios = TRAFFIC_RATIOS.get(mode)
+    # measured HBM bytes per launch (fetch + write), when counters were taken for this mode
+    traffic = int(B * samples * 8 * (ratios[0] + ratios[1])) if ratios else None
     roofline = {"bound": "hbm", "achieved": round(fft_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(fft_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "traffic_gbs": round(traffic / (stage[0] * 1e-3) / 1e9, 1),
+                "traffic_gbs": round(traffic / (stage[0] * 1e-3) / 1e9, 1) if traffic else None,
                 "kernel": "syndrome_kernel<float, 4096> (gather + FFT)",
                 "algorithmic_bytes_per_launch": synd_bytes, "avg_launch_ms": round(stage[0], 4)}
 
@@ -308,13 +362,16 @@ def main():
     unv = None if a.no_uneven else uneven_batch(a.steps, a.warmup)
     torch.cuda.empty_cache()
     mlp = None if a.no_learned else mlp_throughput(a.steps, a.warmup)
+    torch.cuda.empty_cache()
+    itv = None if a.no_iterative else iterative_vs_non_iterative(a.steps, a.warmup)
     out = {
-        "metric": "recovered freqs/s at N=2^20, K=1000 (general mode, SNR 10/20/30/40 dB)"
-        if mode == "general" else "recovered freqs/s at N=2^20, K=1000 (exact mode)",
+        "metric": {"general": "recovered freqs/s at N=2^20, K=1000 (general mode, SNR 10/20/30/40 dB)",
+                   "exact": "recovered freqs/s at N=2^20, K=1000 (exact mode)",
+                   "iterative": "recovered freqs/s at N=2^20, K=1000 (exact mode, iterative Alg. 1)"}[mode],
         "value": round(freqs_per_s, 1), "unit": "freqs/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "fp32 FFT / fp64 decode", "data": "synthetic",
-        "config": {"workload": f"sFFT-DT {mode}, N=2^20, K=1000, M=4096, L=4"
+        "config": {"workload": f"sFFT-DT {mode}, N=2^20, K=1000, M{'_0' if mode == 'iterative' else ''}=4096, L=4"
                    + (", R=12, SNR cycling 10/20/30/40 dB" if mode == "general" else "")
                    + f", complex64, batch {B}", "global_batch": B, "n": n, "k": k, "m": m, "l": L},
         "signals_per_s": round(signals_per_s, 1),
@@ -326,6 +383,7 @@ def main():
         "learned_vs_plain": lvp,
         "uneven_batch": unv,
         "mlp_kernels": mlp,
+        "iterative_vs_non_iterative": itv,
         "input_generation_s": round(gen_s, 2),
     }
     print(json.dumps(out))
@@ -337,15 +395,18 @@ def cpu_baseline(n, k, m, L, R, mode, plan, budget_s, snrs):
 
     import oracle
     import sftgen
+    from oracle import iterative as oracle_iterative
 
     done, found, t_total, c_total = 0, 0, 0.0, 0.0
     i = 0
-    while t_total < budget_s and i < 256:
+    while t_total < budget_s and i < min(256, len(plan.infos)):
         snr = snrs[i % 4] if mode == "general" else None
         s = sftgen.make_signal(n, k, sftgen.BASE_SEED + i, amp="gauss", dtype=np.complex64, snr_db=snr)
         t0, c0 = time.perf_counter(), time.process_time()
         if mode == "general":
             r = oracle.sfft_general(s.x, n, k, m, L, plan.infos[i]["rshifts"])
+        elif mode == "iterative":
+            r, _ = oracle_iterative.sfft_iterative(s.x, n, m, L)
         else:
             r = oracle.sfft_exact(s.x, n, m, L)
         t_total += time.perf_counter() - t0

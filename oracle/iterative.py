@@ -30,7 +30,12 @@ repeated where it is used):
     tau_res^2 E (readings R8, R14 with nu = 0);
   * at l = 0 the value is p_0 = m_0 (Alg. 1 SynDec, the a = 1 case); at
     l >= 1 the values solve Step (iii) in least squares over the 2l + 2
-    syndromes.
+    syndromes;
+  * line 32 accumulates, x_hat[s_j] += p_j: SubFreq has already removed what
+    S holds, so a later solution at a location already in S is a correction
+    of its value (the printed assignment only agrees when s_j is new).  A
+    location whose accumulated value cancels, |sum| < tau_amp max |part|,
+    leaves the output (an earlier solution that a later iteration undid).
 """
 from __future__ import annotations
 
@@ -119,7 +124,7 @@ def sfft_iterative(x, n: int, m0: int, a_m: int = 4, taus: Taus | None = None,
     """Iterative sFFT-DT (Alg. 1) with d_0 = N / M_0 and a_m iterations.
 
     Returns (Result, levels): the recovered (location, value) pairs sorted by
-    location, with active_bins = bins decoded over all iterations and
+    location (accumulated values; cancelled ones left out), with active_bins = bins decoded over all iterations and
     flagged_bins = bins whose decode failed in the last iteration; levels
     lists per iteration its grid, active bins, solved locations and failed
     bins.  fft_dtype as in sfft.syndromes."""
@@ -129,6 +134,7 @@ def sfft_iterative(x, n: int, m0: int, a_m: int = 4, taus: Taus | None = None,
         raise ValueError("need M_0 dividing N and M_0 >= 2^(a_m - 1)")
     d = n // m0
     solved: dict = {}       # S and the solved values of x_hat
+    largest: dict = {}      # per location, the largest |p| solved there
     t_bins: set = set()     # T
     base = {}               # shift j -> its FFT row (grid of the iteration that took it)
     levels = []
@@ -152,8 +158,10 @@ def sfft_iterative(x, n: int, m0: int, a_m: int = 4, taus: Taus | None = None,
                 lev.failed.append(k)
                 continue
             for s_j, p_j in zip(*out):
-                solved[int(s_j)] = complex(p_j)
-                lev.solved.append(int(s_j))
+                s_j = int(s_j)
+                solved[s_j] = solved.get(s_j, 0.0) + complex(p_j)
+                largest[s_j] = max(largest.get(s_j, 0.0), abs(p_j))
+                lev.solved.append(s_j)
         levels.append(lev)
         res.active_bins += lev.active
         # double d; T modulo the new grid
@@ -161,7 +169,7 @@ def sfft_iterative(x, n: int, m0: int, a_m: int = 4, taus: Taus | None = None,
         if l + 1 < a_m:
             t_bins = {k % (n // d) for k in lev.failed}
     res.flagged_bins = len(levels[-1].failed)
-    locs = list(solved.keys())
+    locs = [s for s in solved if abs(solved[s]) >= taus.tau_amp * largest[s]]
     vals = [solved[s] for s in locs]
     res.locs, res.vals = _sorted(locs, vals)
     return res, levels

@@ -73,6 +73,7 @@ struct sft_plan_s {
     uint8_t* d_it_status = nullptr;
     int64_t* d_it_loc = nullptr;
     double2* d_it_val = nullptr;
+    int* d_it_slot = nullptr;
     int2* d_it_items = nullptr;
     int it_item_off[kMaxL] = {0, 0, 0, 0};
     int it_n_items[kMaxL] = {0, 0, 0, 0};
@@ -179,6 +180,7 @@ LaunchCtx make_ctx(const sft_plan_s* p) {
     c.it_status = p->d_it_status;
     c.it_loc = p->d_it_loc;
     c.it_val = p->d_it_val;
+    c.it_slot = p->d_it_slot;
     c.it_items = p->d_it_items;
     for (int l = 0; l < kMaxL; ++l) {
         c.it_item_off[l] = p->it_item_off[l];
@@ -472,6 +474,7 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     TRY(dalloc(p, &p->d_it_status, (size_t)lay.it_st_elems));
     TRY(dalloc(p, &p->d_it_loc, (size_t)lay.it_rec_elems));
     TRY(dalloc(p, &p->d_it_val, (size_t)lay.it_rec_elems));
+    TRY(dalloc(p, &p->d_it_slot, (size_t)lay.it_rec_elems));
     TRY(dalloc(p, &p->d_it_items, lay.it_items.size()));
     TRY(dalloc(p, &p->d_work, 1));
     TRY(dalloc(p, &p->d_active, (size_t)lay.bin_elems));

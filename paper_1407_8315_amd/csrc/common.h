@@ -15,8 +15,10 @@
 // the two lines of "view" l (a SigDev entry of its own, after the signals,
 // with the d, M, offsets and table stride of that iteration's grid), and
 //   status     [sig][l][k]      0 inactive, 1 solved, 2 failed (uint8)
-//   records    [sig][l][k][l+1] (location, value) of the frequencies a solved
-//                               bin holds (SubFreq of later iterations)
+//   records    [sig][l][k][l+1] (location, value, staging slot) of the
+//                               frequencies a solved bin holds (SubFreq of
+//                               later iterations; corrections of a location
+//                               accumulate in its first staging slot)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -250,6 +252,7 @@ struct LaunchCtx {
     uint8_t* it_status;
     int64_t* it_loc;
     double2* it_val;
+    int* it_slot;
     const int2* it_items;            // (sig, bin0): tiles of kBlock bins, iteration by iteration
     int it_item_off[kMaxL];
     int it_n_items[kMaxL];

@@ -1101,8 +1101,9 @@ __global__ __launch_bounds__(kBlock) void cs_kernel(const SigDev* __restrict__ s
 // ------------------------------------------------------------ output lists
 
 // One block per signal.  General mode keeps the K entries of largest |value|
-// when more were found (ties to the lower location); the kept entries are
-// written sorted by location (locations within a signal are distinct).
+// when more were found (ties to the lower location); iterative mode drops the
+// entries marked cancelled; the kept entries are written sorted by location
+// (locations within a signal are distinct).
 __global__ __launch_bounds__(kRankThreads) void output_kernel(const SigDev* __restrict__ sigs, const IoDev* __restrict__ io,
                                                               SigCounters* __restrict__ cnt,
                                                               const int64_t* __restrict__ st_loc,
@@ -1133,6 +1134,11 @@ __global__ __launch_bounds__(kRankThreads) void output_kernel(const SigDev* __re
             const RankKey ki = key(i);
             if (!key_less(kk.a, kk.b, ki.a, ki.b)) kx[atomicAdd(&n_kept, 1)] = i;
         }
+    } else if (sg.mode == kIterative) {
+        // entries whose accumulated value cancelled carry location -1
+        // (locations are distinct, so the order of kx does not matter)
+        for (int i = threadIdx.x; i < n; i += blockDim.x)
+            if (loc[i] >= 0) kx[atomicAdd(&n_kept, 1)] = i;
     } else {
         for (int i = threadIdx.x; i < n; i += blockDim.x) kx[i] = i;
         if (threadIdx.x == 0) n_kept = n;

@@ -18,7 +18,10 @@
 //          exact-mode judge.
 // A solved bin stores its l + 1 (location, value) pairs for the SubFreq of
 // later iterations and appends them to the signal's staging list; the output
-// pass sorts them as in the non-iterative mode.
+// pass sorts them as in the non-iterative mode.  What a later iteration solves
+// at a location already in S is a correction (SubFreq removed the earlier
+// value): it is added to the location's first staging slot, and a slot whose
+// sum cancels (|sum| < tau_amp max |part|) is marked with location -1.
 //
 // Work is in de-rotated form: for bin k the syndrome of shift j is multiplied
 // by e^{-i 2 pi k j / N}, so a frequency s = k + t M_l contributes
@@ -79,6 +82,7 @@ __global__ __launch_bounds__(kBlock) void iter_scan_kernel(const SigDev* __restr
                                                            const double* __restrict__ epart,
                                                            const double2* __restrict__ tab, uint8_t* __restrict__ status,
                                                            int64_t* __restrict__ rs, double2* __restrict__ rp,
+                                                           int* __restrict__ rslot,
                                                            SigCounters* __restrict__ cnt, int64_t* __restrict__ st_loc,
                                                            double2* __restrict__ st_val, WorkCounters* __restrict__ work,
                                                            int2* __restrict__ qlist, int64_t list_cap) {
@@ -144,9 +148,12 @@ __global__ __launch_bounds__(kBlock) void iter_scan_kernel(const SigDev* __restr
     if (l == 0) {
         if (sg.L == 1) wave_count(&cnt[s].flagged, act && !solved);
         int pos = wave_add(&cnt[s].stage_count, solved ? 1 : 0);
-        if (solved && pos < sg.stage_cap) {
-            st_loc[sg.stage_off + pos] = loc;
-            st_val[sg.stage_off + pos] = double2{p.x, p.y};
+        if (solved) {
+            rslot[sg.it_rec_off + k] = pos < sg.stage_cap ? pos : -1;
+            if (pos < sg.stage_cap) {
+                st_loc[sg.stage_off + pos] = loc;
+                st_val[sg.stage_off + pos] = double2{p.x, p.y};
+            }
         }
     } else {
         const int slot = bq.reserve(q);
@@ -160,7 +167,8 @@ __global__ __launch_bounds__(kBlock) void iter_solve_kernel(const SigDev* __rest
                                                             const typename IterV<T>::type* __restrict__ synd,
                                                             const double2* __restrict__ tab,
                                                             uint8_t* __restrict__ status, int64_t* __restrict__ rs,
-                                                            double2* __restrict__ rp, SigCounters* __restrict__ cnt,
+                                                            double2* __restrict__ rp, int* __restrict__ rslot,
+                                                            SigCounters* __restrict__ cnt,
                                                             int64_t* __restrict__ st_loc, double2* __restrict__ st_val,
                                                             const WorkCounters* __restrict__ work,
                                                             const int2* __restrict__ qlist, int64_t list_cap) {
@@ -211,24 +219,70 @@ __global__ __launch_bounds__(kBlock) void iter_solve_kernel(const SigDev* __rest
         bool ok = locator(mt, A, c) && poly_roots(c, A, z) &&
                   roots_to_grid(z, A, v.d, sg.delta_grid, sg.delta_mag, t) &&
                   vandermonde_ls(mt, 2 * A, t, A, v.d, tab, v.tab_stride, p, r2) && r2 <= sg.tau_res2 * e;
+        // earlier parts at the solved locations: their sum, largest part and slot
+        zd tot[kMaxL];
+        double big[kMaxL];
+        int slot[kMaxL];
+#pragma unroll
+        for (int j = 0; j < kMaxL; ++j) {
+            tot[j] = zd{0.0, 0.0};
+            big[j] = 0.0;
+            slot[j] = -1;
+        }
+        if (ok) {
+            for (int lp = 0; lp < l; ++lp) {
+                const uint8_t* st = status + sg.it_st_off + iter_bins_off(sg.m, lp);
+                const int64_t roff = sg.it_rec_off + iter_rec_off(sg.m, lp);
+                const int reps = 1 << (l - lp);
+                for (int i = 0; i < reps; ++i) {
+                    const int64_t b = k + (int64_t)i * v.m;
+                    if (st[b] != kIterSolved) continue;
+                    for (int e = 0; e <= lp; ++e) {
+                        const int64_t idx = roff + b * (lp + 1) + e;
+                        const int64_t sl = rs[idx];
+#pragma unroll
+                        for (int j = 0; j < A; ++j)
+                            if (sl == k + t[j] * (int64_t)v.m) {
+                                const double2 pv = rp[idx];
+                                tot[j] = tot[j] + zd{pv.x, pv.y};
+                                big[j] = fmax(big[j], cabs(zd{pv.x, pv.y}));
+                                if (slot[j] < 0) slot[j] = rslot[idx];
+                            }
+                    }
+                }
+            }
+        }
+        int n_new = 0;
+#pragma unroll
+        for (int j = 0; j < A; ++j) n_new += (ok && slot[j] < 0) ? 1 : 0;
+        if (l == sg.L - 1) wave_count(&cnt[s].flagged, !ok);
+        int pos = wave_add(&cnt[s].stage_count, n_new);
         if (ok) {
             status[sg.it_st_off + iter_bins_off(sg.m, l) + k] = kIterSolved;
             const int64_t roff = sg.it_rec_off + iter_rec_off(sg.m, l) + k * A;
 #pragma unroll
             for (int j = 0; j < A; ++j) {
-                rs[roff + j] = k + t[j] * (int64_t)v.m;
-                rp[roff + j] = double2{p[j].x, p[j].y};
-            }
-        }
-        if (l == sg.L - 1) wave_count(&cnt[s].flagged, !ok);
-        int pos = wave_add(&cnt[s].stage_count, ok ? A : 0);
-        if (ok) {
-#pragma unroll
-            for (int j = 0; j < A; ++j)
-                if (pos + j < sg.stage_cap) {
-                    st_loc[sg.stage_off + pos + j] = k + t[j] * (int64_t)v.m;
-                    st_val[sg.stage_off + pos + j] = double2{p[j].x, p[j].y};
+                const int64_t sj = k + t[j] * (int64_t)v.m;
+                int q = slot[j];
+                if (q < 0) {
+                    // a new location
+                    q = pos < sg.stage_cap ? pos : -1;
+                    ++pos;
+                    if (q >= 0) {
+                        st_loc[sg.stage_off + q] = sj;
+                        st_val[sg.stage_off + q] = double2{p[j].x, p[j].y};
+                    }
+                } else {
+                    // a correction of an earlier value
+                    const zd sum = tot[j] + p[j];
+                    const bool keep = cabs(sum) >= sg.tau_amp * fmax(big[j], cabs(p[j]));
+                    st_loc[sg.stage_off + q] = keep ? sj : -1;
+                    st_val[sg.stage_off + q] = double2{sum.x, sum.y};
                 }
+                rs[roff + j] = sj;
+                rp[roff + j] = double2{p[j].x, p[j].y};
+                rslot[roff + j] = q;
+            }
         }
     }
 }
@@ -239,23 +293,23 @@ static void launch_iteration_t(const LaunchCtx& c, int l) {
     const int n = c.it_n_items[l];
     if (n == 0) return;
     hipLaunchKernelGGL(iter_scan_kernel<T>, dim3(n), dim3(kBlock), 0, c.stream, c.sigs, c.it_items + c.it_item_off[l], l,
-                       (const V*)c.synd, c.epart, c.omega, c.it_status, c.it_loc, c.it_val, c.cnt, c.st_loc, c.st_val,
-                       c.work, c.qlist, c.list_cap);
+                       (const V*)c.synd, c.epart, c.omega, c.it_status, c.it_loc, c.it_val, c.it_slot, c.cnt, c.st_loc,
+                       c.st_val, c.work, c.qlist, c.list_cap);
     switch (l) {
         case 1:
             hipLaunchKernelGGL((iter_solve_kernel<T, 2>), dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs,
-                               (const V*)c.synd, c.omega, c.it_status, c.it_loc, c.it_val, c.cnt, c.st_loc, c.st_val,
-                               c.work, c.qlist, c.list_cap);
+                               (const V*)c.synd, c.omega, c.it_status, c.it_loc, c.it_val, c.it_slot, c.cnt, c.st_loc,
+                               c.st_val, c.work, c.qlist, c.list_cap);
             break;
         case 2:
             hipLaunchKernelGGL((iter_solve_kernel<T, 3>), dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs,
-                               (const V*)c.synd, c.omega, c.it_status, c.it_loc, c.it_val, c.cnt, c.st_loc, c.st_val,
-                               c.work, c.qlist, c.list_cap);
+                               (const V*)c.synd, c.omega, c.it_status, c.it_loc, c.it_val, c.it_slot, c.cnt, c.st_loc,
+                               c.st_val, c.work, c.qlist, c.list_cap);
             break;
         case 3:
             hipLaunchKernelGGL((iter_solve_kernel<T, 4>), dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs,
-                               (const V*)c.synd, c.omega, c.it_status, c.it_loc, c.it_val, c.cnt, c.st_loc, c.st_val,
-                               c.work, c.qlist, c.list_cap);
+                               (const V*)c.synd, c.omega, c.it_status, c.it_loc, c.it_val, c.it_slot, c.cnt, c.st_loc,
+                               c.st_val, c.work, c.qlist, c.list_cap);
             break;
         default:
             break;

@@ -220,3 +220,34 @@ def test_t_keeps_a_bin_whose_new_syndromes_vanish():
     res, levels = oit.sfft_iterative(x, n, m0, 4)
     assert sorted(levels[2].solved) == sorted(locs.tolist())
     assert res.locs.tolist() == sorted(all_locs.tolist())
+
+
+def midpoint_pair(n, m0, k, t1, t2):
+    """Two tones in bin k (slots t1, t2 with t1 + t2 even) whose values make
+    the a = 1 test of iteration 0 exact for a third location: with p_1 = 1 and
+    p_2 = e^{i (a_1 - a_2) / 2} (a_j the angles of the de-rotated roots),
+    m_1 / m_0 is the root of the midpoint slot (t1 + t2) / 2."""
+    d = n // m0
+    a1, a2 = 2 * np.pi * t1 / d, 2 * np.pi * t2 / d
+    locs = np.array([k + t1 * m0, k + t2 * m0], np.int64)
+    vals = np.array([1.0, np.exp(1j * (a1 - a2) / 2)])
+    return locs, vals, k + ((t1 + t2) // 2) * m0
+
+
+def test_later_solution_corrects_an_earlier_one():
+    """Line 32 read as x_hat[s] += p: iteration 0 accepts the midpoint of an
+    equal-magnitude pair as one tone; iteration 2 solves the pair together with
+    the negative of that tone, and the location cancels.  (Assignment would
+    leave the midpoint in the output with the value -m_0.)"""
+    n, m0, k = 1024, 64, 9
+    locs, vals, mid = midpoint_pair(n, m0, k, 3, 11)
+    others = np.array([2, 5 + 3 * m0, 40 + 7 * m0], np.int64)
+    all_locs = np.concatenate([locs, others])
+    all_vals = np.concatenate([vals, np.array([0.8, 0.5j, -0.7])])
+    x = exact_signal(n, all_locs, all_vals)
+    res, levels = oit.sfft_iterative(x, n, m0, 4)
+    assert mid in levels[0].solved                       # the wrong a = 1 solution
+    assert {mid, *locs.tolist()} <= set(levels[2].solved)  # corrected at a = 3
+    assert res.locs.tolist() == sorted(all_locs.tolist())
+    truth = dict(zip(all_locs.tolist(), all_vals))
+    assert max(abs(v - truth[s]) for s, v in zip(res.locs.tolist(), res.vals)) < 1e-10

@@ -204,25 +204,40 @@ def fp32_flips(x, n, m0, L, trials=12, seed=0):
     return base, flips
 
 
+def differ_only_where_fragile(loc, x, n, m0, L, max_classes=2):
+    """The device's output against the oracle's on FP32-rounded syndromes.
+    Alg. 1 decides each residue class mod M_{L-1} on its own (folds and
+    SubFreq never mix classes), so where an FP32-fragile location sits in a
+    class, every decision of that class may differ.  Asserts that each
+    differing location's class holds a fragile one, and that at most
+    max_classes classes differ."""
+    ref32, _ = oit.sfft_iterative(x, n, m0, L, fft_dtype=np.complex64)
+    diff = set(loc.tolist()) ^ set(ref32.locs.tolist())
+    if not diff:
+        return ref32, 0
+    _, flips = fp32_flips(x, n, m0, L)
+    ml = m0 >> (L - 1)
+    classes = {s % ml for s in diff}
+    say(f"  {len(diff)} locations in {len(classes)} classes differ")
+    assert classes <= {s % ml for s in flips}, sorted(classes - {s % ml for s in flips})
+    assert len(classes) <= max_classes
+    return ref32, len(classes)
+
+
 @pytest.mark.parametrize("seed,amp", [(0, "gauss"), (1, "gauss"), (2, "unit")])
 def test_iterative_n20_complex64(torch, sft, seed, amp):
     """N = 2^20, K = 1000, M_0 = 4096, a_m = 4, complex64.  The output is
     compared location by location with the oracle on FP32-rounded syndromes:
-    a location may differ only when it is FP32-fragile (fp32_flips), and then
-    the GPU returns only true locations; at most 8 differ.  Values within
-    1e-5 relative L2 of the FP64 oracle."""
+    a location may differ only in a residue class that holds an FP32-fragile
+    one (differ_only_where_fragile), and the device returns only true
+    locations.  Values within 1e-5 relative L2 of the FP64 oracle."""
     n, k, m0 = 1 << 20, 1000, 4096
     say(f"[iter c64 N=2^20] seed={seed} {amp}")
     s = sftgen.make_signal(n, k, sftgen.BASE_SEED + 400 + seed, amp=amp, dtype=np.complex64)
     loc, val, st = run_iter(torch, sft, s.x, n, m0, 4, "c64")
     assert set(loc.tolist()) <= set(s.locs.tolist())
-    ref32, _ = oit.sfft_iterative(s.x, n, m0, 4, fft_dtype=np.complex64)
-    diff = set(loc.tolist()) ^ set(ref32.locs.tolist())
-    if diff:
-        _, flips = fp32_flips(s.x, n, m0, 4)
-        say(f"  {len(diff)} locations differ, all fragile: {diff <= flips}")
-        assert len(diff) <= 8 and diff <= flips, sorted(diff - flips)
-    else:
+    ref32, ndiff = differ_only_where_fragile(loc, s.x, n, m0, 4)
+    if ndiff == 0:
         assert st["active_bins"] == ref32.active_bins and st["flagged_bins"] == ref32.flagged_bins
     ref, _ = oit.sfft_iterative(s.x, n, m0, 4)      # FP64 FFTs, complex64 thresholds
     common, ia, ib = np.intersect1d(loc, ref.locs, return_indices=True)
@@ -281,11 +296,8 @@ def test_iterative_full_batch_sampled_against_oracle(torch, sft):
         wrong = set(loc.tolist()) - set(s.locs.tolist())
         hits += len(loc) - len(wrong)
         if i % 16 == 0 or wrong:
-            ref32, _ = oit.sfft_iterative(s.x, n, m0, 4, fft_dtype=np.complex64)
-            diff = set(loc.tolist()) ^ set(ref32.locs.tolist())
-            if diff:
-                _, flips = fp32_flips(s.x, n, m0, 4)
-                assert len(diff) <= 8 and diff <= flips, (i, sorted(diff - flips))
+            say(f"  signal {i}: {len(wrong)} locations outside the support")
+            differ_only_where_fragile(loc, s.x, n, m0, 4)
     plan.close()
     say(f"[iter batch] support recovery {hits / (B * k):.6f}")
     assert hits / (B * k) >= 0.995

@@ -57,6 +57,7 @@ def parse():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain comparison")
     ap.add_argument("--no-uneven", action="store_true", help="skip the batched uneven workload")
     ap.add_argument("--no-iterative", action="store_true", help="skip the iterative-vs-non-iterative comparison")
+    ap.add_argument("--fft64", action="store_true", help="FP64 FFTs for the complex64 input (SFT_FLAG_FFT64)")
     return ap.parse_args()
 
 
@@ -120,12 +121,13 @@ def iterative_vs_non_iterative(steps, warmup, B=1024):
     """Exactly K-sparse batch (N = 2^20, K = 1000, unit amplitudes, complex64):
     non-iterative sFFT-DT (M = 4096, L = 4: 8 FFTs of 4096 points) against
     iterative sFFT-DT (Alg. 1, M_0 = 4096, a_m = 4: FFTs of 2 x 4096, 2 x 2048,
-    2 x 1024, 2 x 512 points), same signals, graph-replayed steps."""
+    2 x 1024, 2 x 512 points) with FP32 and with FP64 FFTs, same signals,
+    graph-replayed steps."""
     import numpy as np
     import torch
 
     import sftgen
-    from paper_1407_8315_amd import Plan
+    from paper_1407_8315_amd import SFT_FLAG_FFT64, Plan
 
     n, k, m, L = 1 << 20, 1000, 4096, 4
     dev = torch.device("cuda", 0)
@@ -137,8 +139,9 @@ def iterative_vs_non_iterative(steps, warmup, B=1024):
             x, locs, _ = sftgen.torch_signal(n, k, sftgen.BASE_SEED + 40000 + i, dev, amp="unit")
             xs.append(x)
             truth.append(locs)
-        for name, mode in (("non_iterative", "exact"), ("iterative", "iterative")):
-            plan = Plan([dict(n=n, k=k, m=m, l=L, mode=mode)] * B, stream=stream)
+        for name, mode, flags in (("non_iterative", "exact", 0), ("iterative", "iterative", 0),
+                                  ("iterative_fft64", "iterative", SFT_FLAG_FFT64)):
+            plan = Plan([dict(n=n, k=k, m=m, l=L, mode=mode, flags=flags)] * B, stream=stream)
             outs = [plan.new_output(m * L, dev) for _ in range(B)]
             run = plan.prepare_batch(xs, outs)
             for _ in range(warmup):
@@ -160,9 +163,12 @@ def iterative_vs_non_iterative(steps, warmup, B=1024):
             plan.close()
     out["speedup_iterative_over_non_iterative"] = round(out["non_iterative"]["ms_per_step"]
                                                         / out["iterative"]["ms_per_step"], 4)
+    out["speedup_iterative_fft64_over_non_iterative"] = round(out["non_iterative"]["ms_per_step"]
+                                                              / out["iterative_fft64"]["ms_per_step"], 4)
     out["workload"] = f"exact, N=2^20, K=1000, M(_0)=4096, L=a_m=4, unit amplitudes, complex64, batch {B}"
     out["stage_ms_meaning"] = {"non_iterative": "gather+FFT, activity+rank test, decode, output",
                                "iterative": "gather+FFT (all iterations), iteration 0, iterations 1-3, output"}
+    out["fft_precision"] = {"non_iterative": "fp32", "iterative": "fp32", "iterative_fft64": "fp64"}
     return out
 
 
@@ -302,8 +308,9 @@ def main():
             truth.append(locs)
     torch.cuda.synchronize()
     gen_s = time.time() - t0
-    params = [dict(n=n, k=k, m=m, l=L, r=R if mode == "general" else 0, mode=mode, seed=sftgen.BASE_SEED + i)
-              for i in range(B)]
+    flags = 16 if a.fft64 else 0   # SFT_FLAG_FFT64
+    params = [dict(n=n, k=k, m=m, l=L, r=R if mode == "general" else 0, mode=mode, seed=sftgen.BASE_SEED + i,
+                   flags=flags) for i in range(B)]
     with torch.cuda.stream(stream):
         plan = Plan(params, stream=stream)
         caps = [m * L] * B
@@ -340,15 +347,16 @@ def main():
     # samples gathered (= syndromes written) per signal: 2L (+ R) lines of M;
     # iterative: two lines per iteration on grids of M, M/2, ...
     samples = 2 * sum(m >> l for l in range(L)) if mode == "iterative" else (2 * L + (R if mode == "general" else 0)) * m
-    synd_bytes = B * samples * 8 * 2               # gather read + syndrome write, per launch
+    synd_bytes = B * samples * 8 * (3 if a.fft64 else 2)   # gather read (8 B) + syndrome write (8 or 16 B)
     fft_gbs = synd_bytes / (stage[0] * 1e-3) / 1e9
-    ratios = TRAFFIC_RATIOS.get(mode)
+    ratios = None if a.fft64 else TRAFFIC_RATIOS.get(mode)
     # measured HBM bytes per launch (fetch + write), when counters were taken for this mode
     traffic = int(B * samples * 8 * (ratios[0] + ratios[1])) if ratios else None
     roofline = {"bound": "hbm", "achieved": round(fft_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(fft_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_gbs": round(traffic / (stage[0] * 1e-3) / 1e9, 1) if traffic else None,
-                "kernel": "syndrome_kernel<float, 4096> (gather + FFT)",
+                "kernel": "syndrome_kernel<double, 4096, float> (gather + FFT)" if a.fft64
+                else "syndrome_kernel<float, 4096, float> (gather + FFT)",
                 "algorithmic_bytes_per_launch": synd_bytes, "avg_launch_ms": round(stage[0], 4)}
 
     cpu = None
@@ -370,7 +378,7 @@ def main():
                    "iterative": "recovered freqs/s at N=2^20, K=1000 (exact mode, iterative Alg. 1)"}[mode],
         "value": round(freqs_per_s, 1), "unit": "freqs/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "fp32 FFT / fp64 decode", "data": "synthetic",
+        "dtype": "fp64" if a.fft64 else "fp32 FFT / fp64 decode", "data": "synthetic",
         "config": {"workload": f"sFFT-DT {mode}, N=2^20, K=1000, M{'_0' if mode == 'iterative' else ''}=4096, L=4"
                    + (", R=12, SNR cycling 10/20/30/40 dB" if mode == "general" else "")
                    + f", complex64, batch {B}", "global_batch": B, "n": n, "k": k, "m": m, "l": L},

@@ -16,7 +16,7 @@ import dataclasses
 from . import _lib
 from ._lib import (  # noqa: F401
     SFT_C64, SFT_C128, SFT_MODE_EXACT, SFT_MODE_GENERAL, SFT_MODE_ITERATIVE,
-    SFT_FLAG_LEARNED, SFT_FLAG_SYNC, SFT_FLAG_CHECK_FINITE, SFT_FLAG_AUTOTUNE, SftError,
+    SFT_FLAG_LEARNED, SFT_FLAG_SYNC, SFT_FLAG_CHECK_FINITE, SFT_FLAG_AUTOTUNE, SFT_FLAG_FFT64, SftError,
 )
 
 __all__ = ["Plan", "Result", "SftError", "Mlp", "make_params", "library_path", "autotune"]
@@ -214,7 +214,8 @@ class Plan:
         torch = _torch()
         self._check_input(x)
         inf = self.infos[0]
-        dt = torch.complex128 if inf["in_dtype"] == SFT_C128 else torch.complex64
+        fft64 = inf["in_dtype"] == SFT_C128 or (inf["flags"] & SFT_FLAG_FFT64)
+        dt = torch.complex128 if fft64 else torch.complex64
         if inf["mode"] == SFT_MODE_ITERATIVE:
             sizes = [inf["m"] >> l for l in range(inf["l"])]
             out = torch.empty(2 * sum(sizes), dtype=dt, device=x.device)

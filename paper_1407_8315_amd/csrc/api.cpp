@@ -37,7 +37,8 @@ struct sft_plan_s {
     hipStream_t stream = nullptr;
     int device = 0;
     std::vector<SigHost> sig;
-    bool fp64 = false;
+    bool fp64 = false;       // FFTs and syndromes in FP64
+    bool in64 = false;       // complex128 input
     bool any_general = false;
     // device buffers
     std::vector<void*> allocs;
@@ -137,6 +138,7 @@ LaunchCtx make_ctx(const sft_plan_s* p) {
     c.n_sigs = (int)p->sig.size();
     c.synd = p->d_synd;
     c.fp64 = p->fp64;
+    c.in_fp64 = p->in64;
     c.epart = p->d_epart;
     c.sigma = p->d_sigma;
     c.ebin = p->d_ebin;
@@ -388,13 +390,17 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     for (auto& g : sigs)
         if (g.dtype != sigs[0].dtype) return fail(SFT_E_UNSUPPORTED, "all signals of a plan need one input dtype");
     for (auto& g : sigs)
+        if ((g.flags & SFT_FLAG_FFT64) != (sigs[0].flags & SFT_FLAG_FFT64))
+            return fail(SFT_E_UNSUPPORTED, "SFT_FLAG_FFT64 must be set on all signals of a plan or on none");
+    for (auto& g : sigs)
         if ((g.mode == SFT_MODE_ITERATIVE) != (sigs[0].mode == SFT_MODE_ITERATIVE))
             return fail(SFT_E_UNSUPPORTED, "a plan's signals are all in SFT_MODE_ITERATIVE or none is");
 
     sft_plan_s* p = new sft_plan_s();
     p->stream = (hipStream_t)hip_stream;
     p->sig = std::move(sigs);
-    p->fp64 = p->sig[0].dtype == SFT_C128;
+    p->in64 = p->sig[0].dtype == SFT_C128;
+    p->fp64 = p->in64 || (p->sig[0].flags & SFT_FLAG_FFT64) != 0;
     if (hipGetDevice(&p->device) != hipSuccess) {
         release(p);
         return fail(SFT_E_DEVICE, "no HIP device");

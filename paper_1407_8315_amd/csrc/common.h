@@ -207,7 +207,8 @@ struct LaunchCtx {
     const IoDev* io;
     int n_sigs;
     void* synd;              // float2* or double2*
-    bool fp64;
+    bool fp64;               // FFTs and syndromes in FP64
+    bool in_fp64;            // complex128 input (else complex64)
     double* epart;
     double* sigma;
     double* ebin;

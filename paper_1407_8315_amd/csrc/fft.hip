@@ -139,7 +139,7 @@ __device__ inline void stockham_pass(typename C2<T>::type* buf, int log2m, int n
 //   x[(d (n1 + M1 n2) + shift_s) mod N]; output Y[s][k2][n1] = X[k2] w_M^{-n1 k2}.
 // pass 2: line = (s, k2), the M1 values Y[s][k2][.]; output
 //   m_s[k2 + M2 k1] = d * X[k1] -> syndromes.
-template <typename T, int PMAX>
+template <typename T, int PMAX, typename TIN>
 __global__ __launch_bounds__(kBlock) void syndrome_kernel(const SigDev* __restrict__ sigs, const IoDev* __restrict__ io,
                                                           const int4* __restrict__ items, const int64_t* __restrict__ shifts,
                                                           const typename C2<T>::type* __restrict__ tw, int tw_log2,
@@ -153,7 +153,8 @@ __global__ __launch_bounds__(kBlock) void syndrome_kernel(const SigDev* __restri
     if (it.x < 0) return;   // padding item
     const int s = it.x, line0 = it.y, nl = it.z, pass = it.w;
     const SigDev sg = sigs[s];
-    const V* __restrict__ x = reinterpret_cast<const V*>(io[sg.parent].x);
+    using VIN = typename C2<TIN>::type;   // input element (complex64 or complex128)
+    const VIN* __restrict__ x = reinterpret_cast<const VIN*>(io[sg.parent].x);
     const int log2m = sg.log2m;
     const int log2m1 = sg.log2m1, log2m2 = log2m - log2m1;
     const int log2len = pass == 0 ? log2m : (pass == 1 ? log2m2 : log2m1);
@@ -192,7 +193,9 @@ __global__ __launch_bounds__(kBlock) void syndrome_kernel(const SigDev* __restri
                         const int l = g >> log2m1, n1 = g & ((1 << log2m1) - 1);
                         idx = (sg.d * ((int64_t)n1 + ((int64_t)j << log2m1)) + sh[l]) & nmask;
                     }
-                    v[u] = x[idx];
+                    const VIN xi = x[idx];
+                    v[u].x = (T)xi.x;
+                    v[u].y = (T)xi.y;
                 }
             }
 #pragma unroll
@@ -310,28 +313,30 @@ hipError_t launch_zero_counters(const LaunchCtx& c) {
 
 hipError_t launch_syndromes(const LaunchCtx& c) {
     if (c.fp64) {
+        // FP64 FFTs of complex128 input, or of complex64 input widened on load
+        auto k64 = c.in_fp64 ? syndrome_kernel<double, kFftPointsF64, double> : syndrome_kernel<double, kFftPointsF64, float>;
         if (c.n_synd_items)
-            hipLaunchKernelGGL((syndrome_kernel<double, kFftPointsF64>), dim3(c.n_synd_items), dim3(kBlock), 0, c.stream,
-                               c.sigs, c.io, c.synd_items, c.shifts, (const double2*)c.twiddle, c.tw_log2,
-                               (double2*)c.synd, (double2*)c.ybuf, c.epart, c.cnt);
+            hipLaunchKernelGGL(k64, dim3(c.n_synd_items), dim3(kBlock), 0, c.stream, c.sigs, c.io, c.synd_items,
+                               c.shifts, (const double2*)c.twiddle, c.tw_log2, (double2*)c.synd, (double2*)c.ybuf,
+                               c.epart, c.cnt);
         if (c.n_synd2_items)
-            hipLaunchKernelGGL((syndrome_kernel<double, kFftPointsF64>), dim3(c.n_synd2_items), dim3(kBlock), 0,
-                               c.stream, c.sigs, c.io, c.synd2_items, c.shifts, (const double2*)c.twiddle, c.tw_log2,
-                               (double2*)c.synd, (double2*)c.ybuf, c.epart, c.cnt);
+            hipLaunchKernelGGL(k64, dim3(c.n_synd2_items), dim3(kBlock), 0, c.stream, c.sigs, c.io, c.synd2_items,
+                               c.shifts, (const double2*)c.twiddle, c.tw_log2, (double2*)c.synd, (double2*)c.ybuf,
+                               c.epart, c.cnt);
         if (c.n_line_items)
             hipLaunchKernelGGL(line_energy_kernel<double>, dim3(c.n_line_items), dim3(kBlock), 0, c.stream, c.sigs,
                                c.line_items, (const double2*)c.synd, c.epart);
     } else {
         if (c.n_synd_small_items)
-            hipLaunchKernelGGL((syndrome_kernel<float, kFftPointsF32Small>), dim3(c.n_synd_small_items), dim3(kBlock), 0,
+            hipLaunchKernelGGL((syndrome_kernel<float, kFftPointsF32Small, float>), dim3(c.n_synd_small_items), dim3(kBlock), 0,
                                c.stream, c.sigs, c.io, c.synd_small_items, c.shifts, (const float2*)c.twiddle,
                                c.tw_log2, (float2*)c.synd, (float2*)c.ybuf, c.epart, c.cnt);
         if (c.n_synd_items)
-            hipLaunchKernelGGL((syndrome_kernel<float, kFftPointsF32>), dim3(c.n_synd_items), dim3(kBlock), 0, c.stream,
+            hipLaunchKernelGGL((syndrome_kernel<float, kFftPointsF32, float>), dim3(c.n_synd_items), dim3(kBlock), 0, c.stream,
                                c.sigs, c.io, c.synd_items, c.shifts, (const float2*)c.twiddle, c.tw_log2,
                                (float2*)c.synd, (float2*)c.ybuf, c.epart, c.cnt);
         if (c.n_synd2_items)
-            hipLaunchKernelGGL((syndrome_kernel<float, kFftPointsF32>), dim3(c.n_synd2_items), dim3(kBlock), 0,
+            hipLaunchKernelGGL((syndrome_kernel<float, kFftPointsF32, float>), dim3(c.n_synd2_items), dim3(kBlock), 0,
                                c.stream, c.sigs, c.io, c.synd2_items, c.shifts, (const float2*)c.twiddle, c.tw_log2,
                                (float2*)c.synd, (float2*)c.ybuf, c.epart, c.cnt);
         if (c.n_line_items)

@@ -164,7 +164,7 @@ sft_status resolve_params(const sft_params& in, bool batch, SigHost* g, std::str
         *msg = "N must be a power of two (at most 2^40)";
         return SFT_E_UNSUPPORTED;
     }
-    const uint32_t known = SFT_FLAG_LEARNED | SFT_FLAG_SYNC | SFT_FLAG_CHECK_FINITE | SFT_FLAG_AUTOTUNE;
+    const uint32_t known = SFT_FLAG_LEARNED | SFT_FLAG_SYNC | SFT_FLAG_CHECK_FINITE | SFT_FLAG_AUTOTUNE | SFT_FLAG_FFT64;
     if (in.flags & ~known) {
         *msg = "unknown flag bits";
         return SFT_E_INVALID;

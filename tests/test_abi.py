@@ -122,6 +122,16 @@ def test_mixed_iterative_plan_is_rejected(lib):
     assert b"ITERATIVE" in lib.sft_last_error()
 
 
+def test_mixed_fft64_plan_is_rejected(lib):
+    from paper_1407_8315_amd import make_params
+
+    arr = (type(make_params(n=64, k=1)) * 2)(make_params(n=1 << 12, k=8, flags=16), make_params(n=1 << 12, k=8))
+    h = ctypes.c_void_p()
+    st = lib.sft_plan(ctypes.byref(h), arr, 2, None)
+    assert lib.sft_status_str(st).decode() == "SFT_E_UNSUPPORTED"
+    assert b"FFT64" in lib.sft_last_error()
+
+
 def test_null_arguments(lib):
     from paper_1407_8315_amd import _lib
 

@@ -104,6 +104,20 @@ def test_exact_small_complex128(torch, sft, seed):
     assert st["flagged_bins"] == ref.flagged_bins and st["active_bins"] == ref.active_bins
 
 
+@pytest.mark.parametrize("seed", range(2))
+def test_exact_n20_complex64_fft64(torch, sft, seed):
+    """complex64 input with SFT_FLAG_FFT64 (FP64 FFTs): decisions equal the
+    oracle's with FP64 FFTs and the complex64 thresholds, values within 1e-9."""
+    n, k, m, L = 1 << 20, 1000, 4096, 4
+    say(f"[exact c64 fft64 N=2^20] seed={seed}")
+    s = sftgen.make_signal(n, k, sftgen.BASE_SEED + 150 + seed, amp="gauss", dtype=np.complex64)
+    loc, val, st = run_exact(torch, sft, s.x, n, m, L, "c64", flags=sft.SFT_FLAG_FFT64)
+    ref = oracle.sfft_exact(s.x, n, m, L)
+    assert loc.tolist() == ref.locs.tolist()
+    assert st["flagged_bins"] == ref.flagged_bins and st["active_bins"] == ref.active_bins
+    assert rel_l2(val, ref.vals) <= 1e-9
+
+
 @pytest.mark.parametrize("seed", range(3))
 def test_exact_n20_complex64(torch, sft, seed):
     """N = 2^20, K = 1000, M = 4096, L = 4, complex Gaussian values, complex64:

@@ -69,12 +69,17 @@ def run_iter(torch, sft, x, n, m0, L, dtype):
     (1 << 20, 4096, 4, "c64"),
     (16, 8, 4, "c128"),              # d_0 = 2: indices wrap; the last grid has one bin
     (1 << 16, 16384, 2, "c64"),      # iteration 0 in two FFT passes, iteration 1 in one
+    (1 << 20, 4096, 4, "c64+fft64"),  # complex64 input, FP64 FFTs
+    (1 << 16, 16384, 2, "c64+fft64"),
 ])
 def test_iterative_syndromes_match_oracle(torch, sft, n, m0, L, dtype):
     say(f"[iter syndromes] n={n} m0={m0} L={L} {dtype}")
+    fft64 = dtype.endswith("+fft64")
+    dtype = dtype.split("+")[0]
     npdt = np.complex128 if dtype == "c128" else np.complex64
     s = sftgen.make_signal(n, max(1, m0 // 4), 12, amp="gauss", dtype=npdt)
-    plan = sft.Plan(dict(n=n, k=1, m=m0, l=L, dtype=dtype, mode="iterative"))
+    plan = sft.Plan(dict(n=n, k=1, m=m0, l=L, dtype=dtype, mode="iterative",
+                         flags=sft.SFT_FLAG_FFT64 if fft64 else 0))
     got = [g.cpu().numpy() for g in plan.syndromes(to_dev(torch, s.x))]
     torch.cuda.synchronize()
     plan.close()
@@ -82,7 +87,8 @@ def test_iterative_syndromes_match_oracle(torch, sft, n, m0, L, dtype):
     for l in range(L):
         ref = oracle.syndromes(s.x, n, m0 >> l, [2 * l, 2 * l + 1])
         assert got[l].shape == ref.shape
-        if dtype == "c128":
+        if dtype == "c128" or fft64:
+            assert got[l].dtype == np.complex128
             assert np.max(np.abs(got[l] - ref)) <= 1e-12 * np.max(np.abs(ref))
         else:
             assert rel_l2(got[l], ref) <= 2e-6
@@ -224,6 +230,25 @@ def differ_only_where_fragile(loc, x, n, m0, L, max_classes=2):
     return ref32, len(classes)
 
 
+@pytest.mark.parametrize("seed", range(2))
+def test_iterative_n20_complex64_fft64(torch, sft, seed):
+    """N = 2^20, K = 1000, M_0 = 4096, a_m = 4, complex Gaussian values,
+    complex64 input with SFT_FLAG_FFT64: the oracle with FP64 FFTs and the
+    complex64 thresholds decides identically (support and counts), values
+    within 1e-9 relative L2."""
+    n, k, m0 = 1 << 20, 1000, 4096
+    say(f"[iter c64 fft64 N=2^20] seed={seed}")
+    s = sftgen.make_signal(n, k, sftgen.BASE_SEED + 400 + seed, amp="gauss", dtype=np.complex64)
+    plan = sft.Plan(dict(n=n, k=k, m=m0, l=4, dtype="c64", mode="iterative", flags=sft.SFT_FLAG_FFT64))
+    res = plan.iterative(to_dev(torch, s.x), stats=True)
+    loc, val = res.host()
+    plan.close()
+    ref, _ = oit.sfft_iterative(s.x, n, m0, 4)
+    assert loc.tolist() == ref.locs.tolist()
+    assert res.stats["active_bins"] == ref.active_bins and res.stats["flagged_bins"] == ref.flagged_bins
+    assert rel_l2(val, ref.vals) <= 1e-9
+
+
 @pytest.mark.parametrize("seed,amp", [(0, "gauss"), (1, "gauss"), (2, "unit")])
 def test_iterative_n20_complex64(torch, sft, seed, amp):
     """N = 2^20, K = 1000, M_0 = 4096, a_m = 4, complex64.  The output is
@@ -277,27 +302,44 @@ def test_iterative_batch_equals_single_calls_and_replays(torch, sft):
         assert first[i][0].tolist() == l1.tolist() and np.array_equal(first[i][1], v1)
 
 
-def test_iterative_full_batch_sampled_against_oracle(torch, sft):
-    """The timed workload (N = 2^20, K = 1000, M_0 = 4096, a_m = 4, complex64)
-    as one batch of 256 signals; every 16th signal against the oracle's
-    decisions on FP32 syndromes, and every signal with a location outside the
-    true support too (Alg. 1 can accept a wrong a = 1 solution at iteration 0:
-    an equal-magnitude pair whose midpoint is on the grid; the oracle must
-    make the same mistake)."""
+@pytest.mark.parametrize("fft64", [True, False])
+def test_iterative_full_batch_against_oracle(torch, sft, fft64):
+    """The timed workload (N = 2^20, K = 1000, M_0 = 4096, a_m = 4, unit
+    amplitudes, complex64) as one batch of 256 signals.
+
+    With SFT_FLAG_FFT64 the syndromes are FP64 and every signal's output
+    equals the oracle's (FP64 FFTs, complex64 thresholds): same support, values
+    within 1e-9.  With FP32 FFTs every 16th signal, and every signal with a
+    location outside the true support, is compared with the oracle on
+    FP32-rounded syndromes: at most 2 residue classes mod M_3 differ (FP32
+    fragility, see differ_only_where_fragile), and a location outside the true
+    support must be one the oracle also returns unless its class differs
+    (Alg. 1 can accept a wrong a = 1 solution at iteration 0: an
+    equal-magnitude pair whose midpoint is on the grid)."""
     n, k, m0, B = 1 << 20, 1000, 4096, 256
-    say(f"[iter batch] B={B}")
+    say(f"[iter batch] B={B} fft64={fft64}")
     base = sftgen.BASE_SEED + 9000
     sigs = [sftgen.make_signal(n, k, base + i, amp="unit", dtype=np.complex64) for i in range(B)]
-    plan = sft.Plan([dict(n=n, k=k, m=m0, l=4, dtype="c64", mode="iterative")] * B)
+    flags = sft.SFT_FLAG_FFT64 if fft64 else 0
+    plan = sft.Plan([dict(n=n, k=k, m=m0, l=4, dtype="c64", mode="iterative", flags=flags)] * B)
     outs = plan.batch([to_dev(torch, s.x) for s in sigs], stats=True)
     hits = 0
+    ml = m0 >> 3
     for i, (o, s) in enumerate(zip(outs, sigs)):
         loc, val = o.host()
         wrong = set(loc.tolist()) - set(s.locs.tolist())
         hits += len(loc) - len(wrong)
-        if i % 16 == 0 or wrong:
-            say(f"  signal {i}: {len(wrong)} locations outside the support")
-            differ_only_where_fragile(loc, s.x, n, m0, 4)
+        if fft64:
+            ref, _ = oit.sfft_iterative(s.x, n, m0, 4)
+            assert loc.tolist() == ref.locs.tolist(), i
+            assert np.max(np.abs(val - ref.vals)) <= 1e-9 * max(1.0, np.max(np.abs(ref.vals))), i
+        elif i % 16 == 0 or wrong:
+            ref32, _ = oit.sfft_iterative(s.x, n, m0, 4, fft_dtype=np.complex64)
+            diff = set(loc.tolist()) ^ set(ref32.locs.tolist())
+            classes = {v % ml for v in diff}
+            say(f"  signal {i}: {len(wrong)} outside the support, {len(diff)} differ in {len(classes)} classes")
+            assert len(classes) <= 2, i
+            assert all(v in ref32.locs.tolist() or v % ml in classes for v in wrong), i
     plan.close()
     say(f"[iter batch] support recovery {hits / (B * k):.6f}")
     assert hits / (B * k) >= 0.995

@@ -74,9 +74,11 @@ enum {
     SFT_FLAG_SYNC = 2u,          /* synchronise at the end of each call */
     SFT_FLAG_CHECK_FINITE = 4u,  /* count non-finite gathered samples; report SFT_E_NONFINITE (sync calls) */
     SFT_FLAG_AUTOTUNE = 8u,      /* exact mode: M and L chosen by sft_autotune (m and l must be 0) */
-    SFT_FLAG_FFT64 = 16u         /* complex64 input: FFTs and syndromes in FP64 (set on all signals
+    SFT_FLAG_FFT64 = 16u,        /* complex64 input: FFTs and syndromes in FP64 (set on all signals
                                     of a plan or on none); decisions then no longer depend on FP32
                                     rounding of the syndromes */
+    SFT_FLAG_SP_ALL = 32u        /* general mode, Alg. 2 as printed: every voted bin goes straight
+                                    to pruning and Subspace Pursuit (no syndrome decoding first) */
 };
 
 /* Parameters of one signal.  Zero means "default" for m, l, r and every

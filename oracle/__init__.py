@@ -24,7 +24,7 @@ a > L, noise-free CS = syndrome decoding, SP exact recovery, finite-difference
 gradients of the reference network, and the paper's printed Theorem-2 figure.
 Iterative oracle (tests/test_oracle_iterative.py): folds and SubFreq against
 brute-force alias sums, the Fig. 1 toy, a support-only simulation of Alg. 1,
-a bin that only T brings to its decode, and the cost statement of Sec. II-G.
+a bin that only T brings to its decode, and the cost statement of Sec. II-F.
 """
 from .sfft import (  # noqa: F401
     Result,

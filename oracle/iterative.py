@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
-The method (Sec. II-F, II-G, Alg. 1): iteration l = 0 .. a_m - 1 works on the
+The method (Sec. II-D, II-E, Alg. 1): iteration l = 0 .. a_m - 1 works on the
 grid of M_l = N / d_l bins with d_l = 2^l d_0.  It computes the FFTs of the
 two new shifts 2l and 2l + 1 at d_l, removes the contributions of the
 frequencies solved so far (SubFreq), and decodes every bin that is still

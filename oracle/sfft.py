@@ -351,7 +351,7 @@ def cs_bin(mk, yk, k: int, n: int, m: int, a0: int, rshifts, R: int):
 
 
 def sfft_general(x, n: int, k_sparsity: int, m: int, L: int, rshifts, taus: Taus | None = None,
-                 fft_dtype=np.complex128) -> Result:
+                 fft_dtype=np.complex128, sp_all: bool = False) -> Result:
     """Non-iterative sFFT-DT for generally K-sparse signals (Sec. III, Alg. 2),
     with the CS step run on the bins the syndrome decoder flags.
 
@@ -360,6 +360,9 @@ def sfft_general(x, n: int, k_sparsity: int, m: int, L: int, rshifts, taus: Taus
     Then per voted bin: syndrome decoding with the noise-aware judge; flagged
     bins go through pruning (Steps 2-3) and SP on the n_j syndromes.
     Finally the K largest values are kept (Eq. (9): the output is K-sparse).
+
+    sp_all=True is Alg. 2 as printed: every voted bin goes straight to
+    pruning (Steps 2-3) and SP with sparsity a0, no syndrome decoding first.
     """
     if taus is None:
         taus = default_taus(np.asarray(x).dtype == np.complex128)
@@ -378,7 +381,7 @@ def sfft_general(x, n: int, k_sparsity: int, m: int, L: int, rshifts, taus: Taus
             continue
         res.active_bins += 1
         mk = msyn[:, k]
-        out = decode_bin(mk, k, n, m, L, a0, float(e[k]), nu, taus)
+        out = None if sp_all else decode_bin(mk, k, n, m, L, a0, float(e[k]), nu, taus)
         if out is None:
             res.flagged_bins += 1
             cs = cs_bin(mk, ysyn[:, k], k, n, m, a0, rshifts, R)
@@ -401,6 +404,17 @@ def sfft_general(x, n: int, k_sparsity: int, m: int, L: int, rshifts, taus: Taus
 
 
 # ------------------------------------------------------------------ metrics
+
+
+def snr_db(xh, locs_out, vals_out) -> float:
+    """SNR(x_out) = 10 log10(||x_out||^2 / ||x_hat - x_out||^2) (the SNR
+    definition of Sec. III-F's experiments, with MSE over all N entries)."""
+    xh = np.asarray(xh, np.complex128)
+    locs_out = np.asarray(locs_out, np.int64)
+    vals_out = np.asarray(vals_out, np.complex128)
+    err = float(np.sum(np.abs(xh) ** 2))
+    err += float(np.sum(np.abs(xh[locs_out] - vals_out) ** 2) - np.sum(np.abs(xh[locs_out]) ** 2))
+    return 10.0 * np.log10(float(np.sum(np.abs(vals_out) ** 2)) / max(err, 1e-300))
 
 
 def support_recovery(locs_true, locs_out) -> float:

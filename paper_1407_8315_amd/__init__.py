@@ -16,7 +16,7 @@ import dataclasses
 from . import _lib
 from ._lib import (  # noqa: F401
     SFT_C64, SFT_C128, SFT_MODE_EXACT, SFT_MODE_GENERAL, SFT_MODE_ITERATIVE,
-    SFT_FLAG_LEARNED, SFT_FLAG_SYNC, SFT_FLAG_CHECK_FINITE, SFT_FLAG_AUTOTUNE, SFT_FLAG_FFT64, SftError,
+    SFT_FLAG_LEARNED, SFT_FLAG_SYNC, SFT_FLAG_CHECK_FINITE, SFT_FLAG_AUTOTUNE, SFT_FLAG_FFT64, SFT_FLAG_SP_ALL, SftError,
 )
 
 __all__ = ["Plan", "Result", "SftError", "Mlp", "make_params", "library_path", "autotune"]

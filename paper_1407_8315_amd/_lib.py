@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(_HERE, "libsft.so")
 SFT_OK, SFT_E_INVALID, SFT_E_UNSUPPORTED, SFT_E_NOMEM, SFT_E_DEVICE, SFT_E_CAPACITY, SFT_E_NONFINITE = range(7)
 SFT_C64, SFT_C128 = 1, 2
 SFT_MODE_EXACT, SFT_MODE_GENERAL, SFT_MODE_ITERATIVE = 0, 1, 2
-SFT_FLAG_LEARNED, SFT_FLAG_SYNC, SFT_FLAG_CHECK_FINITE, SFT_FLAG_AUTOTUNE, SFT_FLAG_FFT64 = 1, 2, 4, 8, 16
+SFT_FLAG_LEARNED, SFT_FLAG_SYNC, SFT_FLAG_CHECK_FINITE, SFT_FLAG_AUTOTUNE, SFT_FLAG_FFT64, SFT_FLAG_SP_ALL = 1, 2, 4, 8, 16, 32
 SFT_MAX_RSHIFTS = 64
 
 # Every symbol the header declares (checked by the CPU test suite).

@@ -35,6 +35,7 @@ constexpr int kFftPointsF32Small = 4096;     // blocks of FP32 signals with M <=
 constexpr int kActivityTile = 4096;         // bins per block of the activity pass
 
 enum Mode { kExact = 0, kGeneral = 1, kIterative = 2 };
+constexpr int kFlagSpAll = 32;   // SFT_FLAG_SP_ALL (sft.h)
 
 // Per-signal description, built by the plan and read by every kernel.
 struct SigDev {

@@ -799,9 +799,11 @@ __global__ __launch_bounds__(kBlock) void activity_kernel(const SigDev* __restri
             act = a0 > 0;
         }
         if (act) {
-            const int q = sg.mode == kExact ? kQueues : q_round(0, a0);
+            // general mode with every voted bin to CS (Alg. 2 as printed): CS queue entries are (signal, k)
+            const bool sp_all = sg.mode != kExact && (sg.flags & kFlagSpAll);
+            const int q = sg.mode == kExact ? kQueues : (sp_all ? q_cs(a0) : q_round(0, a0));
             const int pos = atomicAdd(&n_here, 1);
-            st_code[pos] = pack_code(k, 0, 0, a0);
+            st_code[pos] = sp_all ? (int)k : pack_code(k, 0, 0, a0);
             st_qs[pos] = (q << 16) | bq.reserve(q);
         }
     }

@@ -8,6 +8,8 @@
 
 namespace sft {
 
+static_assert(kFlagSpAll == SFT_FLAG_SP_ALL, "device copy of SFT_FLAG_SP_ALL");
+
 namespace {
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -164,9 +166,14 @@ sft_status resolve_params(const sft_params& in, bool batch, SigHost* g, std::str
         *msg = "N must be a power of two (at most 2^40)";
         return SFT_E_UNSUPPORTED;
     }
-    const uint32_t known = SFT_FLAG_LEARNED | SFT_FLAG_SYNC | SFT_FLAG_CHECK_FINITE | SFT_FLAG_AUTOTUNE | SFT_FLAG_FFT64;
+    const uint32_t known = SFT_FLAG_LEARNED | SFT_FLAG_SYNC | SFT_FLAG_CHECK_FINITE | SFT_FLAG_AUTOTUNE | SFT_FLAG_FFT64 |
+                           SFT_FLAG_SP_ALL;
     if (in.flags & ~known) {
         *msg = "unknown flag bits";
+        return SFT_E_INVALID;
+    }
+    if ((in.flags & SFT_FLAG_SP_ALL) && in.mode != SFT_MODE_GENERAL) {
+        *msg = "SFT_FLAG_SP_ALL applies to SFT_MODE_GENERAL";
         return SFT_E_INVALID;
     }
     if ((in.flags & SFT_FLAG_LEARNED) && (in.mode != SFT_MODE_EXACT || !(in.l == 0 || in.l == 4))) {

@@ -80,6 +80,30 @@ def make_signal(n: int, k: int, seed: int, amp: str = "unit", snr_db=None,
     return Sparse(x=x, n=n, locs=locs, vals=vals, noise_var=noise_var)
 
 
+@dataclasses.dataclass
+class Mixture:
+    """A mixture-Gaussian test signal (its dense spectrum kept for SNR)."""
+
+    x: np.ndarray          # time signal
+    xh: np.ndarray         # complex128 spectrum, length n
+    locs: np.ndarray       # the positions drawn from the "on" component (x_hat_s)
+    snr_db: float          # SNR(x_hat_s) = 10 log10(||x_hat_s||^2 / ||x_hat - x_hat_s||^2), exact
+
+
+def mixture_signal(n: int, k: int, snr_db: float, seed: int, dtype=np.complex64) -> Mixture:
+    """The mixture-Gaussian model of Eq. (21): each entry of x_hat is drawn
+    from CN(0, s_on^2) with probability p = K/N, else from CN(0, s_off^2);
+    s_off is then set so that SNR(x_hat_s) equals snr_db exactly."""
+    g = _rng(seed)
+    on = g.random(n) < (k / n)
+    xh = (g.standard_normal(n) + 1j * g.standard_normal(n)) / math.sqrt(2.0)
+    es = float(np.sum(np.abs(xh[on]) ** 2))
+    en = float(np.sum(np.abs(xh[~on]) ** 2))
+    xh[~on] *= math.sqrt(es / (en * 10.0 ** (snr_db / 10.0)))
+    locs = np.flatnonzero(on).astype(np.int64)
+    return Mixture(x=np.fft.ifft(xh).astype(dtype), xh=xh, locs=locs, snr_db=float(snr_db))
+
+
 def make_batch(n: int, k: int, count: int, seed0: int = BASE_SEED, **kw):
     """count signals of one shape with seeds seed0 + i."""
     return [make_signal(n, k, seed0 + i, **kw) for i in range(count)]

@@ -101,6 +101,7 @@ def _plan_status(lib, **kw):
     (dict(n=1 << 14, k=50, mode="iterative", flags=1), "SFT_E_UNSUPPORTED"),    # learned order: exact mode only
     (dict(n=1 << 14, k=50, mode="iterative", flags=8), "SFT_E_INVALID"),        # autotune: exact mode only
     (dict(n=1 << 14, k=50, mode="iterative", r=2), "SFT_E_INVALID"),            # R: general mode only
+    (dict(n=1 << 14, k=50, flags=32), "SFT_E_INVALID"),                          # SP on every bin: general mode only
 ])
 def test_parameter_validation(lib, kw, status):
     st, h = _plan_status(lib, **kw)

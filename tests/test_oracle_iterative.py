@@ -9,7 +9,7 @@
   s mod M_l; a group of exactly l + 1 is solved, any other fails) predicts
   the recovered support exactly on random supports with many collisions;
 * with a_m = 1 the support equals that of the non-iterative oracle at L = 1;
-* the paper's cost statement for a_m = 4 (Sec. II-G).
+* the paper's cost statement for a_m = 4 (Sec. II-F).
 """
 import json
 import math
@@ -164,7 +164,7 @@ def test_simulation_cases_exercise_every_iteration():
 
 
 def test_paper_setting_recovers_everything():
-    """d = N / (4K) (Sec. II-F initialisation): a typical support is recovered in full."""
+    """d = N / (4K) (Sec. II-E initialisation): a typical support is recovered in full."""
     n, k = 1 << 14, 64
     s = sftgen.make_signal(n, k, 21, dtype=np.complex128)
     res, levels = oit.sfft_iterative(s.x, n, 4 * k, 4)
@@ -185,7 +185,7 @@ def test_am1_support_equals_non_iterative_l1():
 
 
 def test_cost_bound_of_the_iterative_ffts():
-    """Sec. II-G: the FFTs of a_m = 4 iterations cost at most (2 + 1 + 1/2 + 1/4)
+    """Sec. II-F: the FFTs of a_m = 4 iterations cost at most (2 + 1 + 1/2 + 1/4)
     (N/d) log(N/d), against 2 a_m (N/d) log(N/d) for the non-iterative method."""
     m0 = 4096
     pts = oit.fft_points(m0, 4)

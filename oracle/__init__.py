@@ -44,6 +44,7 @@ from .sfft import (  # noqa: F401
     roots_to_grid,
     sfft_exact,
     sfft_general,
+    sfft_unknown_k,
     subspace_pursuit,
     support_recovery,
     syndromes,

@@ -254,6 +254,22 @@ def sfft_exact(x, n: int, m: int, L: int, taus: Taus | None = None, orders=None,
     return res
 
 
+def sfft_unknown_k(x, n: int, L: int, m_min: int = 1, m_max: int | None = None, taus: Taus | None = None,
+                   fft_dtype=np.complex128):
+    """Sec. II-G, K unknown: start at d = N (M = m_min, normally 1) and run
+    the exactly-K-sparse method; while some bin cannot be solved (a flagged
+    bin), halve d and run again.  Returns (result, M) of the first run without
+    a flagged bin, or of the run at m_max when every run before it had one."""
+    if m_max is None:
+        m_max = n
+    m = m_min
+    while True:
+        res = sfft_exact(x, n, m, L, taus=taus, fft_dtype=fft_dtype)
+        if res.flagged_bins == 0 or m >= m_max:
+            return res, m
+        m *= 2
+
+
 # ------------------------------------------------------------ general mode
 
 

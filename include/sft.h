@@ -77,8 +77,10 @@ enum {
     SFT_FLAG_FFT64 = 16u,        /* complex64 input: FFTs and syndromes in FP64 (set on all signals
                                     of a plan or on none); decisions then no longer depend on FP32
                                     rounding of the syndromes */
-    SFT_FLAG_SP_ALL = 32u        /* general mode, Alg. 2 as printed: every voted bin goes straight
+    SFT_FLAG_SP_ALL = 32u,       /* general mode, Alg. 2 as printed: every voted bin goes straight
                                     to pruning and Subspace Pursuit (no syndrome decoding first) */
+    SFT_FLAG_UNKNOWN_K = 64u     /* exact mode, single signal, K unknown (k is ignored; pass 1):
+                                    sft_unknown_k tries M = 1, 2, 4 .. m (m = 0: min(N, 2^22)) */
 };
 
 /* Parameters of one signal.  Zero means "default" for m, l, r and every
@@ -165,6 +167,16 @@ sft_status sft_exact(sft_plan_t plan, const void* x_dev, const sft_sparse_out* o
  * elements of the plan's in_dtype; requires a single-signal plan in
  * SFT_MODE_ITERATIVE.  Output, stats and stream semantics as sft_exact. */
 sft_status sft_iterative(sft_plan_t plan, const void* x_dev, const sft_sparse_out* out, sft_stats* stats);
+
+/* Exactly sparse recovery when K is unknown (Sec. II-G): the plan (single
+ * signal, SFT_MODE_EXACT, SFT_FLAG_UNKNOWN_K) holds one workspace per rung
+ * M = max(1, N / 2^22), .., 2, 4, .., m (d = N / M from N down).  Rungs run in
+ * order, each as sft_exact with stats (so the call is synchronous), until one
+ * flags no bin; its list is in out and its M in *m_chosen (the last rung's
+ * when every rung flags a bin; stats then show flagged_bins > 0).  Errors as
+ * sft_exact; SFT_E_CAPACITY only when the chosen rung's list does not fit. */
+sft_status sft_unknown_k(sft_plan_t plan, const void* x_dev, const sft_sparse_out* out, sft_stats* stats,
+                         int64_t* m_chosen);
 
 /* Generally K-sparse recovery of one signal (Sec. III): syndrome decoding with
  * the K-vote, pruning + Subspace Pursuit on flagged bins, the K largest kept.

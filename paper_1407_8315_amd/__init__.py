@@ -16,7 +16,8 @@ import dataclasses
 from . import _lib
 from ._lib import (  # noqa: F401
     SFT_C64, SFT_C128, SFT_MODE_EXACT, SFT_MODE_GENERAL, SFT_MODE_ITERATIVE,
-    SFT_FLAG_LEARNED, SFT_FLAG_SYNC, SFT_FLAG_CHECK_FINITE, SFT_FLAG_AUTOTUNE, SFT_FLAG_FFT64, SFT_FLAG_SP_ALL, SftError,
+    SFT_FLAG_LEARNED, SFT_FLAG_SYNC, SFT_FLAG_CHECK_FINITE, SFT_FLAG_AUTOTUNE, SFT_FLAG_FFT64, SFT_FLAG_SP_ALL, SFT_FLAG_UNKNOWN_K,
+    SftError,
 )
 
 __all__ = ["Plan", "Result", "SftError", "Mlp", "make_params", "library_path", "autotune"]
@@ -161,6 +162,24 @@ class Plan:
     def iterative(self, x, out: Result | None = None, capacity=None, stats=False) -> Result:
         """Iterative sFFT-DT (Alg. 1) on a single-signal plan in mode "iterative"."""
         return self._single(self._lib.sft_iterative, x, out, capacity, stats)
+
+    def unknown_k(self, x, out: Result | None = None, capacity=None, stats=False):
+        """K unknown (Sec. II-G) on a plan made with SFT_FLAG_UNKNOWN_K: returns
+        (result, M) of the first rung M = 1, 2, 4 .. that flags no bin."""
+        self._check_input(x)
+        if capacity is None:
+            capacity = self.default_capacity()
+        if out is None:
+            out = self.new_output(capacity, x.device)
+        o = self._out_struct(out, capacity)
+        st = _lib.Stats()
+        m = ctypes.c_int64(0)
+        status = self._lib.sft_unknown_k(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.byref(o), ctypes.byref(st),
+                                         ctypes.byref(m))
+        if status != _lib.SFT_E_CAPACITY:
+            _lib.check(status, "sft_unknown_k")
+        out.stats = st.as_dict() if stats else None
+        return out, int(m.value)
 
     def batch(self, xs, outs=None, capacities=None, stats=False):
         if len(xs) != self.n_signals:

@@ -11,7 +11,8 @@ LIB_PATH = os.path.join(_HERE, "libsft.so")
 SFT_OK, SFT_E_INVALID, SFT_E_UNSUPPORTED, SFT_E_NOMEM, SFT_E_DEVICE, SFT_E_CAPACITY, SFT_E_NONFINITE = range(7)
 SFT_C64, SFT_C128 = 1, 2
 SFT_MODE_EXACT, SFT_MODE_GENERAL, SFT_MODE_ITERATIVE = 0, 1, 2
-SFT_FLAG_LEARNED, SFT_FLAG_SYNC, SFT_FLAG_CHECK_FINITE, SFT_FLAG_AUTOTUNE, SFT_FLAG_FFT64, SFT_FLAG_SP_ALL = 1, 2, 4, 8, 16, 32
+(SFT_FLAG_LEARNED, SFT_FLAG_SYNC, SFT_FLAG_CHECK_FINITE, SFT_FLAG_AUTOTUNE, SFT_FLAG_FFT64, SFT_FLAG_SP_ALL,
+ SFT_FLAG_UNKNOWN_K) = 1, 2, 4, 8, 16, 32, 64
 SFT_MAX_RSHIFTS = 64
 
 # Every symbol the header declares (checked by the CPU test suite).
@@ -20,7 +21,7 @@ EXPORTS = [
     "sft_status_str", "sft_last_error", "sft_abi_version",
     "sft_mlp_create", "sft_mlp_destroy", "sft_mlp_get_params", "sft_mlp_set_params", "sft_mlp_forward",
     "sft_mlp_grad", "sft_mlp_train_step", "sft_mlp_last_error", "sft_plan_attach_mlp", "sft_features",
-    "sft_autotune",
+    "sft_autotune", "sft_unknown_k",
 ]
 MLP_FEATURES, MLP_CLASSES, MLP_PARAMS = 32, 5, 21381
 
@@ -87,6 +88,8 @@ def load():
         f = getattr(lib, name)
         f.argtypes = [vp, vp, ctypes.POINTER(SparseOut), ctypes.POINTER(Stats)]
         f.restype = st
+    lib.sft_unknown_k.argtypes = [vp, vp, ctypes.POINTER(SparseOut), ctypes.POINTER(Stats), ctypes.POINTER(i64)]
+    lib.sft_unknown_k.restype = st
     lib.sft_batch.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(SparseOut), ctypes.POINTER(Stats)]
     lib.sft_batch.restype = st
     lib.sft_syndromes.argtypes = [vp, vp, vp]

@@ -98,6 +98,7 @@ struct sft_plan_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     sft_mlp_t mlp = nullptr;
+    std::vector<sft_plan_s*> rungs;   // unknown K: plans of the smaller M, ascending (this plan is the last rung)
 };
 
 namespace {
@@ -117,6 +118,8 @@ sft_status dalloc(sft_plan_s* p, T** out, size_t count) {
 
 void release(sft_plan_s* p) {
     if (!p) return;
+    for (sft_plan_s* r : p->rungs) release(r);
+    p->rungs.clear();
     if (p->stream || true) (void)hipStreamSynchronize(p->stream);
     for (void* a : p->allocs) (void)hipFree(a);
     p->allocs.clear();
@@ -541,12 +544,51 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     HIPTRY(hipEventCreateWithFlags(&p->ev_upload, hipEventDisableTiming));
     for (auto& e : p->ev) HIPTRY(hipEventCreate(&e));
     HIPTRY(hipDeviceSynchronize());
+    if (p->sig[0].flags & SFT_FLAG_UNKNOWN_K) {
+        // the rungs below this plan's M, each a plain single-signal plan
+        const int64_t m_min = std::max<int64_t>(1, p->sig[0].n >> 22);
+        for (int64_t m = m_min; m < p->sig[0].m; m *= 2) {
+            sft_params q = params[0];
+            q.m = m;
+            q.flags &= ~(uint32_t)SFT_FLAG_UNKNOWN_K;
+            sft_plan_t r = nullptr;
+            sft_status rs = sft_plan(&r, &q, 1, hip_stream);
+            if (rs != SFT_OK) {
+                std::string msg = g_err;
+                release(p);
+                return fail(rs, "unknown-K rung M = " + std::to_string(m) + ": " + msg);
+            }
+            p->rungs.push_back(r);
+        }
+    }
     *out = p;
     return SFT_OK;
 }
 
 sft_status sft_exact(sft_plan_t plan, const void* x_dev, const sft_sparse_out* out, sft_stats* stats) {
     return run_single(plan, x_dev, out, stats, kExact);
+}
+
+sft_status sft_unknown_k(sft_plan_t plan, const void* x_dev, const sft_sparse_out* out, sft_stats* stats,
+                         int64_t* m_chosen) {
+    if (!plan || !out) return fail(SFT_E_INVALID, "plan or output is NULL");
+    if (plan->sig.size() != 1 || !(plan->sig[0].flags & SFT_FLAG_UNKNOWN_K))
+        return fail(SFT_E_INVALID, "plan was not created with SFT_FLAG_UNKNOWN_K");
+    const size_t n_rungs = plan->rungs.size() + 1;
+    for (size_t i = 0; i < n_rungs; ++i) {
+        sft_plan_s* r = i + 1 < n_rungs ? plan->rungs[i] : plan;
+        const bool last = i + 1 == n_rungs;
+        sft_stats st{};
+        sft_status s = run_single(r, x_dev, out, &st, kExact);
+        if (s != SFT_OK && s != SFT_E_CAPACITY) return s;
+        // an overflowing list only matters for the rung whose list is returned
+        if (st.flagged_bins == 0 || last) {
+            if (m_chosen) *m_chosen = r->sig[0].m;
+            if (stats) *stats = st;
+            return s;
+        }
+    }
+    return SFT_OK;
 }
 
 sft_status sft_iterative(sft_plan_t plan, const void* x_dev, const sft_sparse_out* out, sft_stats* stats) {

@@ -167,9 +167,14 @@ sft_status resolve_params(const sft_params& in, bool batch, SigHost* g, std::str
         return SFT_E_UNSUPPORTED;
     }
     const uint32_t known = SFT_FLAG_LEARNED | SFT_FLAG_SYNC | SFT_FLAG_CHECK_FINITE | SFT_FLAG_AUTOTUNE | SFT_FLAG_FFT64 |
-                           SFT_FLAG_SP_ALL;
+                           SFT_FLAG_SP_ALL | SFT_FLAG_UNKNOWN_K;
     if (in.flags & ~known) {
         *msg = "unknown flag bits";
+        return SFT_E_INVALID;
+    }
+    if ((in.flags & SFT_FLAG_UNKNOWN_K) &&
+        (batch || in.mode != SFT_MODE_EXACT || (in.flags & (SFT_FLAG_LEARNED | SFT_FLAG_AUTOTUNE)))) {
+        *msg = "SFT_FLAG_UNKNOWN_K applies to single-signal SFT_MODE_EXACT plans (not learned, not autotuned)";
         return SFT_E_INVALID;
     }
     if ((in.flags & SFT_FLAG_SP_ALL) && in.mode != SFT_MODE_GENERAL) {
@@ -204,6 +209,7 @@ sft_status resolve_params(const sft_params& in, bool batch, SigHost* g, std::str
         *msg = "L must be in 1..4";
         return SFT_E_UNSUPPORTED;
     }
+    if (m_in == 0 && (in.flags & SFT_FLAG_UNKNOWN_K)) m_in = std::min<int64_t>(in.n, max_m(in.in_dtype));
     g->m = m_in == 0 ? default_m(in.n, in.k, in.in_dtype) : m_in;
     if (!is_pow2(g->m) || g->m > in.n) {
         *msg = "M must be a power of two dividing N";

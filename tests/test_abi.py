@@ -90,7 +90,7 @@ def _plan_status(lib, **kw):
     (dict(n=1 << 24, k=50, m=1 << 23), "SFT_E_UNSUPPORTED"),   # M above 2^22
     (dict(n=1 << 14, k=50, r=3), "SFT_E_INVALID"),             # R in exact mode
     (dict(n=1 << 14, k=50, mode="general", r=40), "SFT_E_UNSUPPORTED"),
-    (dict(n=1 << 14, k=50, flags=64), "SFT_E_INVALID"),        # unknown flag
+    (dict(n=1 << 14, k=50, flags=1 << 10), "SFT_E_INVALID"),   # unknown flag
     (dict(n=1 << 14, k=50, tau_res=-1.0), "SFT_E_INVALID"),
     (dict(n=1 << 14, k=50, m=128, flags=8), "SFT_E_INVALID"),                 # autotune with a fixed M
     (dict(n=1 << 14, k=50, mode="general", flags=8), "SFT_E_INVALID"),        # autotune in general mode
@@ -102,6 +102,8 @@ def _plan_status(lib, **kw):
     (dict(n=1 << 14, k=50, mode="iterative", flags=8), "SFT_E_INVALID"),        # autotune: exact mode only
     (dict(n=1 << 14, k=50, mode="iterative", r=2), "SFT_E_INVALID"),            # R: general mode only
     (dict(n=1 << 14, k=50, flags=32), "SFT_E_INVALID"),                          # SP on every bin: general mode only
+    (dict(n=1 << 14, k=1, mode="general", flags=64), "SFT_E_INVALID"),           # unknown K: exact mode only
+    (dict(n=1 << 14, k=1, flags=64 | 8), "SFT_E_INVALID"),                       # unknown K and autotune
 ])
 def test_parameter_validation(lib, kw, status):
     st, h = _plan_status(lib, **kw)
@@ -141,6 +143,7 @@ def test_null_arguments(lib):
     assert lib.sft_plan(ctypes.byref(h), None, 1, None) == _lib.SFT_E_INVALID
     assert lib.sft_exact(None, None, None, None) == _lib.SFT_E_INVALID
     assert lib.sft_iterative(None, None, None, None) == _lib.SFT_E_INVALID
+    assert lib.sft_unknown_k(None, None, None, None, None) == _lib.SFT_E_INVALID
     assert lib.sft_batch(None, None, None, None) == _lib.SFT_E_INVALID
     assert lib.sft_plan_get(None, 0, None) == _lib.SFT_E_INVALID
     lib.sft_destroy(None)

@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--no-uneven", action="store_true", help="skip the batched uneven workload")
     ap.add_argument("--no-iterative", action="store_true", help="skip the iterative-vs-non-iterative comparison")
     ap.add_argument("--fft64", action="store_true", help="FP64 FFTs for the complex64 input (SFT_FLAG_FFT64)")
+    ap.add_argument("--paper-tables", action="store_true",
+                    help="also run Alg. 2 as printed on the Tables II-IV workload (N = 2^24, mixture Gaussian)")
     return ap.parse_args()
 
 
@@ -170,6 +172,58 @@ def iterative_vs_non_iterative(steps, warmup, B=1024):
                                "iterative": "gather+FFT (all iterations), iteration 0, iterations 1-3, output"}
     out["fft_precision"] = {"non_iterative": "fp32", "iterative": "fp32", "iterative_fft64": "fp64"}
     return out
+
+
+def paper_tables(reps=3, log2_ks=range(8, 17)):
+    """Alg. 2 as printed (SFT_FLAG_SP_ALL) on the workload of Tables II-IV:
+    N = 2^24, d = N/(32K), a_m = 3, R = 9, mixture-Gaussian x_hat (Eq. (21))
+    at SNR(x_hat_s) = 30, 20, 10 dB, K = the significant entries drawn.
+    Per cell: SNR(x_hat_out) and the device time of one call (mean of reps,
+    HIP events), next to the paper's printed values (CPU seconds)."""
+    import json as _json
+
+    import torch
+
+    import sftgen
+    from paper_1407_8315_amd import SFT_FLAG_SP_ALL, Plan
+
+    gold = _json.load(open(os.path.join(ROOT, "tests", "golden", "tables_2_4.json")))
+    n = 1 << 24
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.Stream(device=dev)
+    rows = []
+    with torch.cuda.stream(stream):
+        for snr in (30, 20, 10):
+            for lk in log2_ks:
+                k_nom = 1 << lk
+                m = 32 * k_nom
+                x, xh, k = sftgen.torch_mixture(n, k_nom, snr, sftgen.BASE_SEED + 70000 + 100 * snr + lk, dev)
+                plan = Plan(dict(n=n, k=k, m=m, l=3, r=min(9, n // m), mode="general", seed=lk,
+                                 flags=SFT_FLAG_SP_ALL), stream=stream)
+                out = plan.new_output(m * 3, dev)
+                plan.general(x, out)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(reps):
+                    plan.general(x, out)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                cnt = min(int(out.count.item()), out.loc.numel())
+                loc, val = out.loc[:cnt], out.val[:cnt]
+                err = float((xh.abs() ** 2).sum() + ((xh[loc] - val).abs() ** 2).sum() - (xh[loc].abs() ** 2).sum())
+                snr_out = 10.0 * math.log10(float((val.abs() ** 2).sum()) / max(err, 1e-300))
+                i = gold["log2_k"].index(lk)
+                rows.append({"snr_in_db": snr, "log2_k": lk, "k_drawn": k, "m": m,
+                             "snr_out_db": round(snr_out, 2), "ms_per_call": round(ms, 3),
+                             "paper_snr_out_db": gold["snr_out_with_pruning"][str(snr)][i],
+                             "paper_seconds": gold["seconds_with_pruning"][str(snr)][i]})
+                plan.close()
+                del x, xh, out
+                torch.cuda.empty_cache()
+    return {"workload": "Alg. 2 as printed, N=2^24, d=N/(32K), a_m=3, R=9, mixture Gaussian, complex64",
+            "rows": rows}
 
 
 def uneven_batch(steps, warmup, count=4096):
@@ -372,6 +426,8 @@ def main():
     mlp = None if a.no_learned else mlp_throughput(a.steps, a.warmup)
     torch.cuda.empty_cache()
     itv = None if a.no_iterative else iterative_vs_non_iterative(a.steps, a.warmup)
+    torch.cuda.empty_cache()
+    tables = paper_tables() if a.paper_tables else None
     out = {
         "metric": {"general": "recovered freqs/s at N=2^20, K=1000 (general mode, SNR 10/20/30/40 dB)",
                    "exact": "recovered freqs/s at N=2^20, K=1000 (exact mode)",
@@ -392,6 +448,7 @@ def main():
         "uneven_batch": unv,
         "mlp_kernels": mlp,
         "iterative_vs_non_iterative": itv,
+        "paper_tables_2_4": tables,
         "input_generation_s": round(gen_s, 2),
     }
     print(json.dumps(out))

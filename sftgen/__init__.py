@@ -104,6 +104,23 @@ def mixture_signal(n: int, k: int, snr_db: float, seed: int, dtype=np.complex64)
     return Mixture(x=np.fft.ifft(xh).astype(dtype), xh=xh, locs=locs, snr_db=float(snr_db))
 
 
+def torch_mixture(n: int, k: int, snr_db: float, seed: int, device):
+    """Device-side variant of mixture_signal (same draws; the inverse FFT runs
+    in torch's complex128 on the device, cast to complex64).  Returns
+    (x_device complex64, xh_device complex128, number of significant entries)."""
+    import torch
+
+    g = _rng(seed)
+    on = g.random(n) < (k / n)
+    xh = (g.standard_normal(n) + 1j * g.standard_normal(n)) / math.sqrt(2.0)
+    es = float(np.sum(np.abs(xh[on]) ** 2))
+    en = float(np.sum(np.abs(xh[~on]) ** 2))
+    xh[~on] *= math.sqrt(es / (en * 10.0 ** (snr_db / 10.0)))
+    xh_d = torch.from_numpy(xh).to(device)
+    x = torch.fft.ifft(xh_d).to(torch.complex64)
+    return x, xh_d, int(on.sum())
+
+
 def make_batch(n: int, k: int, count: int, seed0: int = BASE_SEED, **kw):
     """count signals of one shape with seeds seed0 + i."""
     return [make_signal(n, k, seed0 + i, **kw) for i in range(count)]

@@ -58,6 +58,7 @@ def parse():
     ap.add_argument("--no-uneven", action="store_true", help="skip the batched uneven workload")
     ap.add_argument("--no-iterative", action="store_true", help="skip the iterative-vs-non-iterative comparison")
     ap.add_argument("--fft64", action="store_true", help="FP64 FFTs for the complex64 input (SFT_FLAG_FFT64)")
+    ap.add_argument("--no-model", action="store_true", help="skip the recovery-vs-collision-model section")
     ap.add_argument("--paper-tables", action="store_true",
                     help="also run Alg. 2 as printed on the Tables II-IV workload (N = 2^24, mixture Gaussian)")
     return ap.parse_args()
@@ -172,6 +173,56 @@ def iterative_vs_non_iterative(steps, warmup, B=1024):
                                "iterative": "gather+FFT (all iterations), iteration 0, iterations 1-3, output"}
     out["fft_precision"] = {"non_iterative": "fp32", "iterative": "fp32", "iterative_fft64": "fp64"}
     return out
+
+
+def recovery_vs_model(B=256):
+    """Support recovery measured on the device against the collision model
+    (Sec. II-C, Lemma 2; the autotuner's model): a frequency is recovered when
+    its bin holds at most L frequencies, so the expected recovery is the
+    hypergeometric P(at most L - 1 of the other K - 1 frequencies fall in the
+    d - 1 other slots of its bin).  N = 2^20, K = 1000, N+ = N/(dK) from 1 to
+    8, L = 1..4, B signals each, FP64 FFTs (so no FP32 effect enters).  Also
+    the fraction of signals with a missed frequency against Lemma 2's bound
+    (N/d) (d e K / (N (L + 1)))^(L + 1)."""
+    import numpy as np
+    import torch
+    from scipy.stats import hypergeom
+
+    import sftgen
+    from paper_1407_8315_amd import SFT_FLAG_FFT64, Plan
+
+    n, k = 1 << 20, 1000
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.Stream(device=dev)
+    rows = []
+    with torch.cuda.stream(stream):
+        xs, truth = [], []
+        for i in range(B):
+            x, locs, _ = sftgen.torch_signal(n, k, sftgen.BASE_SEED + 50000 + i, dev, amp="unit")
+            xs.append(x)
+            truth.append(locs)
+        for m in (1024, 2048, 4096, 8192):
+            d = n // m
+            for L in (1, 2, 3, 4):
+                if d < 2 * L:
+                    continue
+                plan = Plan([dict(n=n, k=k, m=m, l=L, flags=SFT_FLAG_FFT64)] * B, stream=stream)
+                outs = plan.batch(xs)
+                torch.cuda.synchronize()
+                found, imperfect = 0, 0
+                for o, t in zip(outs, truth):
+                    got = len(np.intersect1d(o.host()[0], t))
+                    found += got
+                    imperfect += got < k
+                plan.close()
+                model = float(hypergeom.cdf(L - 1, n - 1, d - 1, k - 1))
+                lemma2 = (n / d) * (d * math.e * k / (n * (L + 1))) ** (L + 1)
+                rows.append({"m": m, "n_plus": round(m / k, 3), "l": L,
+                             "measured_recovery": round(found / (B * k), 6), "model_recovery": round(model, 6),
+                             "signals_with_a_miss": round(imperfect / B, 4), "lemma2_bound": round(min(1.0, lemma2), 6)})
+        del xs
+    return {"workload": f"exact, N=2^20, K=1000, unit amplitudes, complex64 with FP64 FFTs, {B} signals per cell",
+            "rows": rows}
 
 
 def paper_tables(reps=3, log2_ks=range(8, 17)):
@@ -428,6 +479,8 @@ def main():
     itv = None if a.no_iterative else iterative_vs_non_iterative(a.steps, a.warmup)
     torch.cuda.empty_cache()
     tables = paper_tables() if a.paper_tables else None
+    torch.cuda.empty_cache()
+    model = None if a.no_model else recovery_vs_model()
     out = {
         "metric": {"general": "recovered freqs/s at N=2^20, K=1000 (general mode, SNR 10/20/30/40 dB)",
                    "exact": "recovered freqs/s at N=2^20, K=1000 (exact mode)",
@@ -449,6 +502,7 @@ def main():
         "mlp_kernels": mlp,
         "iterative_vs_non_iterative": itv,
         "paper_tables_2_4": tables,
+        "recovery_vs_model": model,
         "input_generation_s": round(gen_s, 2),
     }
     print(json.dumps(out))

@@ -41,6 +41,7 @@ from .sfft import (  # noqa: F401
     noise_floor,
     rank_order,
     relative_l2,
+    snr_db,
     roots_to_grid,
     sfft_exact,
     sfft_general,

@@ -80,6 +80,8 @@ __host__ __device__ inline int64_t iter_rec_off(int64_t m0, int l) {
 
 struct SigCounters {
     int stage_count, active, flagged, cs, mlp_fb, nonfinite, kept, pad;
+    int it_queued[kMaxL];   // iterative mode: bins queued for SynDec in iteration l (own region per signal)
+    int pad2[kMaxL];
 };
 
 // Plan-wide work lists, rebuilt by every call.  The decoder runs in rounds:

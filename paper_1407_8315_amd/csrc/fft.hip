@@ -301,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void line_energy_kernel(const SigDev* __res
 
 __global__ void zero_counters_kernel(SigCounters* cnt, int n, WorkCounters* work) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) cnt[i] = SigCounters{0, 0, 0, 0, 0, 0, 0, 0};
+    if (i < n) cnt[i] = SigCounters{};
     if (i < (int)(sizeof(WorkCounters) / sizeof(int))) reinterpret_cast<int*>(work)[i] = 0;
 }
 

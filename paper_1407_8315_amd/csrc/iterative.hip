@@ -11,8 +11,11 @@
 //          k mod M_l), the activity test with T (the bins whose decode failed
 //          in the previous iteration, reduced mod M_l), and at l = 0 SynDec
 //          itself (a = 1: z_0 = m_1/m_0, p_0 = m_0).  For l >= 1 the active
-//          bins are queued;
-//   solve  (l >= 1) one lane per queued bin: the 2l + 2 syndromes folded to
+//          bins are queued, each signal in its own region of the list (a
+//          counter per signal, one atomic per block: a single list counter
+//          shared by every block serialises the appends);
+//   solve  (l >= 1) one block per signal, one lane per queued bin: the
+//          2l + 2 syndromes folded to
 //          the grid, de-rotated and reduced by SubFreq, SynDec at order
 //          a = l + 1 (Steps (i)-(iii) of Sec. II-B), the grid check and the
 //          exact-mode judge.
@@ -56,11 +59,15 @@ __device__ __attribute__((always_inline)) inline void sub_solved(zd* mt, int j0,
                                                                    const double2* __restrict__ tab) {
     const int64_t m0 = sg.m;
     const int64_t dmask = v.d - 1;
-    for (int lp = 0; lp < l; ++lp) {
+#pragma unroll
+    for (int lp = 0; lp < kMaxL - 1; ++lp) {
+        if (lp >= l) break;
         const uint8_t* st = status + sg.it_st_off + iter_bins_off(m0, lp);
         const int64_t roff = sg.it_rec_off + iter_rec_off(m0, lp);
         const int reps = 1 << (l - lp);
-        for (int i = 0; i < reps; ++i) {
+#pragma unroll
+        for (int i = 0; i < (1 << (kMaxL - 1)); ++i) {
+            if (i >= reps) break;
             const int64_t b = k + (int64_t)i * v.m;
             if (st[b] != kIterSolved) continue;
             for (int e = 0; e <= lp; ++e) {
@@ -75,18 +82,22 @@ __device__ __attribute__((always_inline)) inline void sub_solved(zd* mt, int j0,
     }
 }
 
-// Dense pass of iteration l over tiles of kBlock bins.
-template <typename T>
+// Dense pass of iteration L_ over tiles of kBlock bins (one instance per
+// iteration, so that the loops over the bins folding into k unroll and their
+// loads issue together).  Counts and list slots are aggregated per block in
+// LDS: one device atomic per block and counter.
+template <typename T, int L_>
 __global__ __launch_bounds__(kBlock) void iter_scan_kernel(const SigDev* __restrict__ sigs, const int2* __restrict__ items,
-                                                           int l, const typename IterV<T>::type* __restrict__ synd,
+                                                           const typename IterV<T>::type* __restrict__ synd,
                                                            const double* __restrict__ epart,
                                                            const double2* __restrict__ tab, uint8_t* __restrict__ status,
                                                            int64_t* __restrict__ rs, double2* __restrict__ rp,
                                                            int* __restrict__ rslot,
                                                            SigCounters* __restrict__ cnt, int64_t* __restrict__ st_loc,
-                                                           double2* __restrict__ st_val, WorkCounters* __restrict__ work,
-                                                           int2* __restrict__ qlist, int64_t list_cap) {
-    __shared__ BlockQueues bq;
+                                                           double2* __restrict__ st_val, int2* __restrict__ qlist,
+                                                           int64_t list_cap) {
+    constexpr int l = L_;
+    __shared__ int n_act, n_out, base;   // active bins; solved (l = 0) or queued (l >= 1) bins; their first slot
     const int2 it = items[blockIdx.x];
     if (it.x < 0) return;   // padding item
     const int s = it.x;
@@ -96,36 +107,41 @@ __global__ __launch_bounds__(kBlock) void iter_scan_kernel(const SigDev* __restr
     const bool valid = k < v.m;
     const double eref = (epart[v.epart_off] + epart[v.epart_off + 1]) / (double)v.m;
     uint8_t* st = status + sg.it_st_off + iter_bins_off(sg.m, l);
-    if (l > 0) bq.reset();
+    if (threadIdx.x == 0) {
+        n_act = 0;
+        n_out = 0;
+    }
+    __syncthreads();
 
     bool act = false, solved = false;
-    int q = -1;
     zd p{0.0, 0.0};
     int64_t loc = 0;
     if (valid) {
-        // the two new syndromes, de-rotated: shifts 2l and 2l + 1
-        zd mt[2];
+        // the two new syndromes (shifts 2l and 2l + 1), raw: magnitudes do not
+        // depend on the de-rotation, which is applied only where needed
+        zd mr[2];
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             const auto x = synd[v.synd_off + (int64_t)c * v.m + k];
-            const int64_t j = 2 * l + c;
-            mt[c] = cmul_conj(unit_root((k * j) & (sg.n - 1), sg.n), zd{(double)x.x, (double)x.y});
+            mr[c] = zd{(double)x.x, (double)x.y};
         }
         if (l == 0) {
-            const double e = norm2(mt[0]) + norm2(mt[1]);
+            const double e = norm2(mr[0]) + norm2(mr[1]);
             act = e > sg.tau_zero2 * eref;
             if (act) {
                 // SynDec, a = 1: z_0 = m_1 / m_0, p_0 = m_0, grid check, judge
-                const zd z = cdiv(mt[1], mt[0]);
+                // (de-rotated: shift 0 is unchanged, shift 1 by e^{-i 2 pi k / N})
+                const zd m1 = cmul_conj(unit_root(k & (sg.n - 1), sg.n), mr[1]);
+                const zd z = cdiv(m1, mr[0]);
                 int64_t t[kMaxL];
                 bool ok = cfinite(z) && roots_to_grid(&z, 1, v.d, sg.delta_grid, sg.delta_mag, t);
                 if (ok) {
-                    const zd r = mt[1] - mt[0] * omega(tab, v.tab_stride, t[0]);
+                    const zd r = m1 - mr[0] * omega(tab, v.tab_stride, t[0]);
                     ok = norm2(r) <= sg.tau_res2 * e;
                 }
                 if (ok) {
                     solved = true;
-                    p = mt[0];
+                    p = mr[0];
                     loc = k + t[0] * (int64_t)v.m;
                 }
             }
@@ -138,50 +154,74 @@ __global__ __launch_bounds__(kBlock) void iter_scan_kernel(const SigDev* __restr
             // T: a bin of iteration l - 1 that folds into k failed
             const uint8_t* prev = status + sg.it_st_off + iter_bins_off(sg.m, l - 1);
             const bool in_t = prev[k] == kIterFailed || prev[k + v.m] == kIterFailed;
-            sub_solved<2>(mt, 2 * l, l, k, sg, v, status, rs, rp, tab);
-            act = in_t || norm2(mt[0]) + norm2(mt[1]) > sg.tau_zero2 * eref;
+            // SubFreq changes the bin only when a bin folding into it was solved
+            bool any_solved = false;
+#pragma unroll
+            for (int lp = 0; lp < l; ++lp) {
+                const uint8_t* sp = status + sg.it_st_off + iter_bins_off(sg.m, lp);
+#pragma unroll
+                for (int i = 0; i < (1 << (l - lp)); ++i) any_solved |= sp[k + (int64_t)i * v.m] == kIterSolved;
+            }
+            double e = norm2(mr[0]) + norm2(mr[1]);
+            if (any_solved) {
+                zd mt[2];
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    mt[c] = cmul_conj(unit_root((k * (2 * l + c)) & (sg.n - 1), sg.n), mr[c]);
+                sub_solved<2>(mt, 2 * l, l, k, sg, v, status, rs, rp, tab);
+                e = norm2(mt[0]) + norm2(mt[1]);
+            }
+            act = in_t || e > sg.tau_zero2 * eref;
             st[k] = act ? kIterFailed : kIterIdle;   // the solve pass marks the solved ones
-            if (act) q = q_round(0, l);
         }
     }
-    wave_count(&cnt[s].active, act);
-    if (l == 0) {
-        if (sg.L == 1) wave_count(&cnt[s].flagged, act && !solved);
-        int pos = wave_add(&cnt[s].stage_count, solved ? 1 : 0);
-        if (solved) {
+    const bool out = l == 0 ? solved : act;
+    int my = -1;
+    if (out) my = atomicAdd(&n_out, 1);
+    if (act) atomicAdd(&n_act, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (n_act) atomicAdd(&cnt[s].active, n_act);
+        if (l == 0 && sg.L == 1 && n_act - n_out) atomicAdd(&cnt[s].flagged, n_act - n_out);
+        if (n_out) base = atomicAdd(l == 0 ? &cnt[s].stage_count : &cnt[s].it_queued[l], n_out);
+    }
+    __syncthreads();
+    if (out) {
+        const int pos = base + my;
+        if (l == 0) {
             rslot[sg.it_rec_off + k] = pos < sg.stage_cap ? pos : -1;
             if (pos < sg.stage_cap) {
                 st_loc[sg.stage_off + pos] = loc;
                 st_val[sg.stage_off + pos] = double2{p.x, p.y};
             }
+        } else {
+            // the signal's own region of list q_round(0, l): bins [bin_off, bin_off + M_0)
+            qlist[(int64_t)q_round(0, l) * list_cap + sg.bin_off + pos] = int2{s, (int)k};
         }
-    } else {
-        const int slot = bq.reserve(q);
-        bq.commit(work, nullptr, qlist, list_cap, q, slot, int2{s, (int)k});
     }
 }
 
-// SynDec at order A = l + 1 for the bins queued by the scan of iteration l.
-template <typename T, int A>
-__global__ __launch_bounds__(kBlock) void iter_solve_kernel(const SigDev* __restrict__ sigs,
+// SynDec at order A = l + 1 for the bins queued by the scan of iteration l:
+// one block of NT threads per signal (iteration 1 queues ~10% of a signal's
+// bins, iterations 2 and 3 a few: one wavefront per signal there).
+template <typename T, int A, int NT>
+__global__ __launch_bounds__(NT) void iter_solve_kernel(const SigDev* __restrict__ sigs,
                                                             const typename IterV<T>::type* __restrict__ synd,
                                                             const double2* __restrict__ tab,
                                                             uint8_t* __restrict__ status, int64_t* __restrict__ rs,
                                                             double2* __restrict__ rp, int* __restrict__ rslot,
                                                             SigCounters* __restrict__ cnt,
                                                             int64_t* __restrict__ st_loc, double2* __restrict__ st_val,
-                                                            const WorkCounters* __restrict__ work,
                                                             const int2* __restrict__ qlist, int64_t list_cap) {
     constexpr int l = A - 1;
-    const int q = q_round(0, l);
-    const int total = work->q[q];
-    const int2* in = qlist + (int64_t)q * list_cap;
-    for (int item = blockIdx.x * kBlock + threadIdx.x; item < total; item += gridDim.x * kBlock) {
-        const int2 en = in[item];
-        const int s = en.x;
-        const int64_t k = en.y;
-        const SigDev& sg = sigs[s];
-        const SigDev& v = sigs[sg.view0 + l];
+    const int s = blockIdx.x;
+    const SigDev& sg = sigs[s];
+    if (sg.L <= l) return;
+    const int total = cnt[s].it_queued[l];
+    const int2* in = qlist + (int64_t)q_round(0, l) * list_cap + sg.bin_off;
+    const SigDev& v = sigs[sg.view0 + l];
+    for (int item = threadIdx.x; item < total; item += NT) {
+        const int64_t k = in[item].y;
         // syndromes of shifts 0 .. 2A-1 on this grid: shift j was taken at
         // iteration j / 2 and is folded 2^{l - j/2} times
         zd mt[2 * kMaxL];
@@ -292,24 +332,26 @@ static void launch_iteration_t(const LaunchCtx& c, int l) {
     using V = typename IterV<T>::type;
     const int n = c.it_n_items[l];
     if (n == 0) return;
-    hipLaunchKernelGGL(iter_scan_kernel<T>, dim3(n), dim3(kBlock), 0, c.stream, c.sigs, c.it_items + c.it_item_off[l], l,
+    auto scan = l == 0 ? iter_scan_kernel<T, 0> : l == 1 ? iter_scan_kernel<T, 1> : l == 2 ? iter_scan_kernel<T, 2>
+                                                                                            : iter_scan_kernel<T, 3>;
+    hipLaunchKernelGGL(scan, dim3(n), dim3(kBlock), 0, c.stream, c.sigs, c.it_items + c.it_item_off[l],
                        (const V*)c.synd, c.epart, c.omega, c.it_status, c.it_loc, c.it_val, c.it_slot, c.cnt, c.st_loc,
-                       c.st_val, c.work, c.qlist, c.list_cap);
+                       c.st_val, c.qlist, c.list_cap);
     switch (l) {
         case 1:
-            hipLaunchKernelGGL((iter_solve_kernel<T, 2>), dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs,
+            hipLaunchKernelGGL((iter_solve_kernel<T, 2, 256>), dim3(c.n_sigs), dim3(256), 0, c.stream, c.sigs,
                                (const V*)c.synd, c.omega, c.it_status, c.it_loc, c.it_val, c.it_slot, c.cnt, c.st_loc,
-                               c.st_val, c.work, c.qlist, c.list_cap);
+                               c.st_val, c.qlist, c.list_cap);
             break;
         case 2:
-            hipLaunchKernelGGL((iter_solve_kernel<T, 3>), dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs,
+            hipLaunchKernelGGL((iter_solve_kernel<T, 3, 64>), dim3(c.n_sigs), dim3(64), 0, c.stream, c.sigs,
                                (const V*)c.synd, c.omega, c.it_status, c.it_loc, c.it_val, c.it_slot, c.cnt, c.st_loc,
-                               c.st_val, c.work, c.qlist, c.list_cap);
+                               c.st_val, c.qlist, c.list_cap);
             break;
         case 3:
-            hipLaunchKernelGGL((iter_solve_kernel<T, 4>), dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs,
+            hipLaunchKernelGGL((iter_solve_kernel<T, 4, 64>), dim3(c.n_sigs), dim3(64), 0, c.stream, c.sigs,
                                (const V*)c.synd, c.omega, c.it_status, c.it_loc, c.it_val, c.it_slot, c.cnt, c.st_loc,
-                               c.st_val, c.work, c.qlist, c.list_cap);
+                               c.st_val, c.qlist, c.list_cap);
             break;
         default:
             break;

@@ -266,6 +266,8 @@ def paper_tables(reps=3, log2_ks=range(8, 17)):
                 err = float((xh.abs() ** 2).sum() + ((xh[loc] - val).abs() ** 2).sum() - (xh[loc].abs() ** 2).sum())
                 snr_out = 10.0 * math.log10(float((val.abs() ** 2).sum()) / max(err, 1e-300))
                 i = gold["log2_k"].index(lk)
+                print(f"[paper tables] snr {snr} dB, K = 2^{lk}: SNR_out {snr_out:.2f} dB, {ms:.3f} ms",
+                      file=sys.stderr, flush=True)
                 rows.append({"snr_in_db": snr, "log2_k": lk, "k_drawn": k, "m": m,
                              "snr_out_db": round(snr_out, 2), "ms_per_call": round(ms, 3),
                              "paper_snr_out_db": gold["snr_out_with_pruning"][str(snr)][i],

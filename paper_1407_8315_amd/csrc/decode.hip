@@ -278,50 +278,110 @@ __device__ int block_select(KeyFn key, int n, int r, RankLds& S, const RankScrat
         __syncthreads();
         return out;
     }
-    // sorted sample at scattered positions (t times an odd constant mod n: no
-    // aliasing with a stride of the data, such as the L singular values of a
-    // bin), then a window of sample ranks about r's expected place, +- 3
-    // standard deviations and a margin
-    for (int t = threadIdx.x; t < kSelSample; t += blockDim.x) {
-        const int i = (int)(((unsigned long long)t * 2654435761ull) % (unsigned long long)n);
-        const RankKey k = key(i);
-        S.a[t] = k.a;
-        S.b[t] = k.b;
-        S.idx[t] = i;
-    }
-    if (threadIdx.x == 0) {
-        S.n_below = 0;
-        S.n_win = 0;
-    }
-    __syncthreads();
-    lds_bitonic(S, kSelSample);
-    const double q = ((double)r + 0.5) / (double)n;
-    const int rs = (int)(q * kSelSample);
-    const int w = (int)(3.0 * sqrt((double)kSelSample * q * (1.0 - q))) + 8;
-    const bool has_lo = rs - w >= 0, has_hi = rs + w < kSelSample;
-    const double lo_a = has_lo ? S.a[rs - w] : 0.0, hi_a = has_hi ? S.a[rs + w] : 0.0;
-    const long long lo_b = has_lo ? S.b[rs - w] : 0, hi_b = has_hi ? S.b[rs + w] : 0;
-    __syncthreads();
-    int below = 0, win = 0;
+    // Sample-window refinement.  Round 0: a sorted sample at scattered
+    // positions (t times an odd constant mod n: no aliasing with a stride of
+    // the data, such as the L singular values of a bin).  Later rounds: a
+    // hashed subsample of the keys still inside the window.  Each round keeps
+    // the sample ranks about r's expected place, +- 3 standard deviations and
+    // a margin, counts the keys below and inside that window, and stops once
+    // the window holds at most kRankChunk keys (then sorted in LDS).  A window
+    // that misses rank r keeps the previous bounds and widens the margin.
+    bool has_lo = false, has_hi = false;
+    double lo_a = 0.0, hi_a = 0.0;
+    long long lo_b = 0, hi_b = 0;
+    int nb = 0;      // keys below the window
+    int ncur = n;    // keys inside it
+    int widen = 1;
+    auto inside = [&](const RankKey& k, bool hl, double la, long long lb, bool hh, double ha, long long hb) {
+        return !(hl && key_less(k.a, k.b, la, lb)) && (!hh || !key_less(ha, hb, k.a, k.b));
+    };
+    for (int round = 0; round < 64 && ncur > kRankChunk; ++round) {
+        if (threadIdx.x == 0) S.n_win = 0;
+        __syncthreads();
+        int ns;
+        if (round == 0) {
+            for (int t = threadIdx.x; t < kSelSample; t += blockDim.x) {
+                const int i = (int)(((unsigned long long)t * 2654435761ull) % (unsigned long long)n);
+                const RankKey k = key(i);
+                S.a[t] = k.a;
+                S.b[t] = k.b;
+                S.idx[t] = i;
+            }
+            ns = kSelSample;
+        } else {
+            // keep a window key when a hash of (index, round) falls below
+            // about 0.9 kSelSample / ncur of the 32-bit range
+            const unsigned long long keep =
+                (unsigned long long)(0.9 * (double)kSelSample / (double)ncur * 4294967296.0);
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                unsigned h = (unsigned)i * 0x9E3779B1u + (unsigned)round * 0x85EBCA77u;
+                h ^= h >> 15;
+                h *= 0x2C1B3C6Du;
+                h ^= h >> 12;
+                if ((unsigned long long)h >= keep) continue;
+                const RankKey k = key(i);
+                if (!inside(k, has_lo, lo_a, lo_b, has_hi, hi_a, hi_b)) continue;
+                const int pos = atomicAdd(&S.n_win, 1);
+                if (pos < kSelSample) {
+                    S.a[pos] = k.a;
+                    S.b[pos] = k.b;
+                    S.idx[pos] = i;
+                }
+            }
+            __syncthreads();
+            ns = min(S.n_win, kSelSample);
+        }
+        const int P = pow2_at_least(ns > 0 ? ns : 1);
+        pad_keys(S, ns, P);
+        __syncthreads();
+        lds_bitonic(S, P);
+        // window of sample ranks about r's place among the ncur window keys
+        const double q = ((double)(r - nb) + 0.5) / (double)ncur;
+        const int rs = (int)(q * ns);
+        const int w = widen * ((int)(3.0 * sqrt((double)ns * q * (1.0 - q))) + 8);
+        const bool nlo = ns > 0 && rs - w >= 0, nhi = ns > 0 && rs + w < ns;
+        const double nlo_a = nlo ? S.a[rs - w] : lo_a, nhi_a = nhi ? S.a[rs + w] : hi_a;
+        const long long nlo_b = nlo ? S.b[rs - w] : lo_b, nhi_b = nhi ? S.b[rs + w] : hi_b;
+        const bool hl = nlo || has_lo, hh = nhi || has_hi;
+        if (threadIdx.x == 0) {
+            S.n_below = 0;
+            S.n_win = 0;
+        }
+        __syncthreads();
+        int below = 0, win = 0;
 #pragma unroll 8
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const RankKey k = key(i);
-        if (has_lo && key_less(k.a, k.b, lo_a, lo_b)) ++below;
-        else if (!has_hi || !key_less(hi_a, hi_b, k.a, k.b)) ++win;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const RankKey k = key(i);
+            if (!inside(k, has_lo, lo_a, lo_b, has_hi, hi_a, hi_b)) continue;
+            if (hl && key_less(k.a, k.b, nlo_a, nlo_b)) ++below;
+            else if (!hh || !key_less(nhi_a, nhi_b, k.a, k.b)) ++win;
+        }
+        atomicAdd(&S.n_below, below);
+        atomicAdd(&S.n_win, win);
+        __syncthreads();
+        const int nb2 = nb + S.n_below, nw2 = S.n_win;
+        __syncthreads();
+        if (nb2 <= r && r < nb2 + nw2) {
+            nb = nb2;
+            ncur = nw2;
+            has_lo = hl;
+            has_hi = hh;
+            lo_a = nlo_a;
+            lo_b = nlo_b;
+            hi_a = nhi_a;
+            hi_b = nhi_b;
+            widen = 1;
+        } else {
+            widen *= 4;
+        }
     }
-    atomicAdd(&S.n_below, below);
-    atomicAdd(&S.n_win, win);
-    __syncthreads();
-    const int nb = S.n_below, nw = S.n_win;
-    __syncthreads();
-    if (nb <= r && r < nb + nw && nw <= kRankChunk) {
+    if (ncur <= kRankChunk) {
         if (threadIdx.x == 0) S.n_win = 0;
         __syncthreads();
 #pragma unroll 8
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
             const RankKey k = key(i);
-            const bool in = !(has_lo && key_less(k.a, k.b, lo_a, lo_b)) && (!has_hi || !key_less(hi_a, hi_b, k.a, k.b));
-            if (in) {
+            if (inside(k, has_lo, lo_a, lo_b, has_hi, hi_a, hi_b)) {
                 const int pos = atomicAdd(&S.n_win, 1);
                 S.a[pos] = k.a;
                 S.b[pos] = k.b;
@@ -329,6 +389,7 @@ __device__ int block_select(KeyFn key, int n, int r, RankLds& S, const RankScrat
             }
         }
         __syncthreads();
+        const int nw = S.n_win;
         const int P = pow2_at_least(nw);
         pad_keys(S, nw, P);
         __syncthreads();

@@ -97,6 +97,13 @@ struct sft_plan_s {
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    // branches for independent kernels of one stage (the orders of a round,
+    // the CS orders): default-priority streams, forked from and joined into
+    // the plan's stream with events (captured into the graph as parallel
+    // branches)
+    hipStream_t side[kMaxL] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_join[kMaxL] = {nullptr, nullptr, nullptr, nullptr};
     sft_mlp_t mlp = nullptr;
     std::vector<sft_plan_s*> rungs;   // unknown K: plans of the smaller M, ascending (this plan is the last rung)
 };
@@ -130,6 +137,11 @@ void release(sft_plan_s* p) {
         if (e) (void)hipEventDestroy(e);
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
+    for (auto& st : p->side)
+        if (st) (void)hipStreamDestroy(st);
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    for (auto& e : p->ev_join)
+        if (e) (void)hipEventDestroy(e);
     delete p;
 }
 
@@ -200,6 +212,26 @@ bool learned(const sft_plan_s* p) {
     return false;
 }
 
+// Run fn(ctx, i) for i = 1..n, branch i on side stream i-1, after everything
+// already enqueued on the plan's stream; the plan's stream waits for all.
+template <typename Fn>
+sft_status branches(const sft_plan_s* p, const LaunchCtx& c, int n, Fn fn) {
+    if (n <= 1) {
+        if (n == 1) HIPCHK(fn(c, 1));
+        return SFT_OK;
+    }
+    HIPCHK(hipEventRecord(p->ev_fork, p->stream));
+    for (int i = 0; i < n; ++i) {
+        HIPCHK(hipStreamWaitEvent(p->side[i], p->ev_fork, 0));
+        LaunchCtx ci = c;
+        ci.stream = p->side[i];
+        HIPCHK(fn(ci, i + 1));
+        HIPCHK(hipEventRecord(p->ev_join[i], p->side[i]));
+    }
+    for (int i = 0; i < n; ++i) HIPCHK(hipStreamWaitEvent(p->stream, p->ev_join[i], 0));
+    return SFT_OK;
+}
+
 // Enqueue the whole path.  With events != nullptr, record stage boundaries.
 // Learned plans run the predictor between the activity pass and the decoder.
 sft_status enqueue(const sft_plan_s* p, hipEvent_t* events) {
@@ -247,7 +279,10 @@ sft_status enqueue(const sft_plan_s* p, hipEvent_t* events) {
     if (events) HIPCHK(hipEventRecord(events[2], p->stream));
     for (int r = 0; r < p->max_l; ++r) {
         if (r >= 1) HIPCHK(launch_zero_set(c, (r + 1) & 1));
-        HIPCHK(launch_round(c, r));
+        // the orders of a round read their own queues: parallel branches
+        const int n_orders = (r == 0 && !p->any_general) ? std::min(p->max_l, 2) : p->max_l;
+        sft_status bs = branches(p, c, n_orders, [&](const LaunchCtx& ci, int a) { return launch_round(ci, r, a); });
+        if (bs != SFT_OK) return bs;
         // bins whose learned order failed: rank test, then on with round 1
         if (r == 0 && use_mlp && p->max_l > 1) HIPCHK(launch_svd_rank(c, q_round(1, 0), 1));
         // without general-mode signals, the few bins left after round 0 of orders 1
@@ -257,7 +292,10 @@ sft_status enqueue(const sft_plan_s* p, hipEvent_t* events) {
             break;
         }
     }
-    HIPCHK(launch_cs(c));
+    if (p->any_general) {
+        sft_status bs = branches(p, c, kMaxL, [&](const LaunchCtx& ci, int a0) { return launch_cs(ci, a0); });
+        if (bs != SFT_OK) return bs;
+    }
     if (events) HIPCHK(hipEventRecord(events[3], p->stream));
     HIPCHK(launch_output(c));
     if (events) HIPCHK(hipEventRecord(events[4], p->stream));
@@ -542,6 +580,9 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     HIPTRY(hipHostMalloc((void**)&p->h_io, ns * sizeof(IoDev), hipHostMallocDefault));
     HIPTRY(hipHostMalloc((void**)&p->h_cnt, ns * sizeof(SigCounters), hipHostMallocDefault));
     HIPTRY(hipEventCreateWithFlags(&p->ev_upload, hipEventDisableTiming));
+    HIPTRY(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+    for (auto& e : p->ev_join) HIPTRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (auto& st : p->side) HIPTRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     for (auto& e : p->ev) HIPTRY(hipEventCreate(&e));
     HIPTRY(hipDeviceSynchronize());
     if (p->sig[0].flags & SFT_FLAG_UNKNOWN_K) {

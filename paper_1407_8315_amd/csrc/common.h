@@ -270,9 +270,9 @@ hipError_t launch_activity(const LaunchCtx& c);
 hipError_t launch_certify(const LaunchCtx& c);                           // active list -> order 1 tried, or pending
 hipError_t launch_svd_rank(const LaunchCtx& c, int q_in, int set_out);   // rank test by SVD
 hipError_t launch_zero_set(const LaunchCtx& c, int set);
-hipError_t launch_round(const LaunchCtx& c, int round);
+hipError_t launch_round(const LaunchCtx& c, int round, int a);   // the kernels of order a in round `round`
 hipError_t launch_rest(const LaunchCtx& c);   // rounds 1.. in one kernel (plans without general-mode signals)
-hipError_t launch_cs(const LaunchCtx& c);
+hipError_t launch_cs(const LaunchCtx& c, int a0);                // CS step of the bins flagged with vote order a0
 hipError_t launch_output(const LaunchCtx& c);
 hipError_t launch_iteration(const LaunchCtx& c, int l);   // Alg. 1, iteration l (scan, then SynDec for l >= 1)
 

@@ -1326,13 +1326,16 @@ static void launch_order(const LaunchCtx& c, int round) {
 }
 
 template <typename T>
-static void launch_round_t(const LaunchCtx& c, int round) {
-    launch_order<T, 1>(c, round);
-    if (c.max_l >= 2) launch_order<T, 2>(c, round);
+static void launch_round_t(const LaunchCtx& c, int round, int a) {
     // plans without general-mode signals leave round 0 of orders 3 and 4 to rest_kernel
-    if (round == 0 && !c.any_general) return;
-    if (c.max_l >= 3) launch_order<T, 3>(c, round);
-    if (c.max_l >= 4) launch_order<T, 4>(c, round);
+    if (round == 0 && !c.any_general && a >= 3) return;
+    if (a > c.max_l) return;
+    switch (a) {
+        case 1: launch_order<T, 1>(c, round); break;
+        case 2: launch_order<T, 2>(c, round); break;
+        case 3: launch_order<T, 3>(c, round); break;
+        default: launch_order<T, 4>(c, round); break;
+    }
 }
 
 hipError_t launch_rest(const LaunchCtx& c) {
@@ -1346,10 +1349,10 @@ hipError_t launch_rest(const LaunchCtx& c) {
     return hipGetLastError();
 }
 
-hipError_t launch_round(const LaunchCtx& c, int round) {
+hipError_t launch_round(const LaunchCtx& c, int round, int a) {
     if (c.n_bin_items == 0) return hipSuccess;
-    if (c.fp64) launch_round_t<double>(c, round);
-    else launch_round_t<float>(c, round);
+    if (c.fp64) launch_round_t<double>(c, round, a);
+    else launch_round_t<float>(c, round, a);
     return hipGetLastError();
 }
 
@@ -1360,18 +1363,23 @@ static void launch_cs_one(const LaunchCtx& c) {
                        (const V*)c.synd, c.omega, c.cnt, c.st_loc, c.st_val, c.work, c.qlist, c.list_cap);
 }
 
-template <typename T>
-static void launch_cs_t(const LaunchCtx& c) {
-    launch_cs_one<T, 1>(c);
-    launch_cs_one<T, 2>(c);
-    launch_cs_one<T, 3>(c);
-    launch_cs_one<T, 4>(c);
-}
-
-hipError_t launch_cs(const LaunchCtx& c) {
+hipError_t launch_cs(const LaunchCtx& c, int a0) {
     if (!c.any_general || c.n_bin_items == 0) return hipSuccess;
-    if (c.fp64) launch_cs_t<double>(c);
-    else launch_cs_t<float>(c);
+    if (c.fp64) {
+        switch (a0) {
+            case 1: launch_cs_one<double, 1>(c); break;
+            case 2: launch_cs_one<double, 2>(c); break;
+            case 3: launch_cs_one<double, 3>(c); break;
+            default: launch_cs_one<double, 4>(c); break;
+        }
+    } else {
+        switch (a0) {
+            case 1: launch_cs_one<float, 1>(c); break;
+            case 2: launch_cs_one<float, 2>(c); break;
+            case 3: launch_cs_one<float, 3>(c); break;
+            default: launch_cs_one<float, 4>(c); break;
+        }
+    }
     return hipGetLastError();
 }
 

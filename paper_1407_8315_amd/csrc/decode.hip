@@ -409,6 +409,151 @@ __device__ int block_select(KeyFn key, int n, int r, RankLds& S, const RankScrat
     return out;
 }
 
+// Index of the key of ascending rank r (0 <= r < n) in the order (ukey(i), i),
+// by radix selection on the 64-bit keys, 8 bits per pass: each pass counts
+// the candidates (keys matching the digits fixed so far) per next digit and
+// keeps the digit that holds rank r.  Once the candidates fit in LDS they are
+// gathered there and the remaining passes run on LDS.  Ties of the full key
+// go to the lower index.  Whole block; the result is the same element a full
+// sort would give.
+template <typename UKeyFn>
+__device__ int block_radix_select(UKeyFn ukey, int n, int r, RankLds& S) {
+    __shared__ int hist[256];
+    __shared__ int sel_digit, sel_rr, n_cand;
+    unsigned long long prefix = 0ull, mask = 0ull;
+    int rr = r;
+    bool in_lds = false;
+    int nc = n;   // candidates
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        if (!in_lds && nc <= kRankChunk) {
+            // gather the candidates (ascending index order is not kept: ties
+            // are resolved by index below)
+            if (threadIdx.x == 0) n_cand = 0;
+            __syncthreads();
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const unsigned long long k = ukey(i);
+                if ((k & mask) == prefix) {
+                    const int pos = atomicAdd(&n_cand, 1);
+                    S.b[pos] = (long long)k;
+                    S.idx[pos] = i;
+                }
+            }
+            __syncthreads();
+            nc = n_cand;
+            in_lds = true;
+        }
+        for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+        __syncthreads();
+        if (in_lds) {
+            for (int j = threadIdx.x; j < nc; j += blockDim.x) {
+                const unsigned long long k = (unsigned long long)S.b[j];
+                if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & 255], 1);
+            }
+        } else {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const unsigned long long k = ukey(i);
+                if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & 255], 1);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            // wave 0: lane t holds bins 4t .. 4t+3; an inclusive scan of the
+            // lane sums finds the lane, then the bin, where the count passes rr
+            const int t = threadIdx.x;
+            const int h0 = hist[4 * t], h1 = hist[4 * t + 1], h2 = hist[4 * t + 2], h3 = hist[4 * t + 3];
+            const int own = h0 + h1 + h2 + h3;
+            int inc = own;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int u = __shfl_up(inc, o, 64);
+                if (t >= o) inc += u;
+            }
+            const int exc = inc - own;
+            if (exc <= rr && rr < inc) {
+                int cum = exc, d = 4 * t;
+                if (cum + h0 <= rr) {
+                    cum += h0;
+                    ++d;
+                    if (cum + h1 <= rr) {
+                        cum += h1;
+                        ++d;
+                        if (cum + h2 <= rr) {
+                            cum += h2;
+                            ++d;
+                        }
+                    }
+                }
+                sel_digit = d;
+                sel_rr = rr - cum;
+                if (!in_lds) n_cand = hist[d];
+            } else if (t == 63 && rr >= inc) {   // not reached for 0 <= r < n: the last bin
+                sel_digit = 255;
+                sel_rr = rr - (inc - h3);
+                if (!in_lds) n_cand = h3;
+            }
+        }
+        __syncthreads();
+        prefix |= (unsigned long long)sel_digit << shift;
+        mask |= 255ull << shift;
+        rr = sel_rr;
+        if (!in_lds) nc = n_cand;
+        __syncthreads();
+    }
+    // the rr-th lowest index among the keys equal to prefix
+    __shared__ int pick;
+    if (threadIdx.x == 0) {
+        n_cand = 0;
+        pick = -1;
+    }
+    __syncthreads();
+    if (in_lds) {
+        for (int j = threadIdx.x; j < nc; j += blockDim.x)
+            if ((unsigned long long)S.b[j] == prefix) S.a[atomicAdd(&n_cand, 1)] = (double)S.idx[j];
+        __syncthreads();
+        const int ne = n_cand;
+        for (int j = threadIdx.x; j < ne; j += blockDim.x) {
+            const double v = S.a[j];
+            int below = 0;
+            for (int t = 0; t < ne; ++t) below += S.a[t] < v ? 1 : 0;
+            if (below == rr) pick = (int)v;
+        }
+    } else {
+        // more than kRankChunk keys equal the selected one: count them per
+        // contiguous chunk of indices, then the chunk holding rank rr finds it
+        const int C = (n + blockDim.x - 1) / blockDim.x;
+        const int lo = min(n, (int)threadIdx.x * C), hi = min(n, lo + C);
+        int c = 0;
+        for (int i = lo; i < hi; ++i) c += ukey(i) == prefix ? 1 : 0;
+        S.idx[threadIdx.x] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int run = 0;
+            for (int t = 0; t < (int)blockDim.x; ++t) {
+                const int v = S.idx[t];
+                S.idx[t] = run;
+                run += v;
+            }
+        }
+        __syncthreads();
+        const int before = S.idx[threadIdx.x];
+        if (rr >= before && rr < before + c) {
+            int m = rr - before;
+            for (int i = lo; i < hi; ++i)
+                if (ukey(i) == prefix) {
+                    if (m == 0) {
+                        pick = i;
+                        break;
+                    }
+                    --m;
+                }
+        }
+    }
+    __syncthreads();
+    const int out = pick;
+    __syncthreads();
+    return out;
+}
+
 // One block per general-mode signal: the vote threshold (the K-th largest of
 // all M L singular values, ties to the lower flat index k L + i) and the
 // noise floor nu = lower median of E_k / (2L - 1/3).
@@ -422,21 +567,21 @@ __global__ __launch_bounds__(kRankThreads) void select_kernel(const SigDev* __re
     const int nv = sg.m * sg.L;
     const double* sgm = sigma + sg.bin_off * sg.L;
     const double* eb = ebin + sg.bin_off;
-    const RankScratch g = rank_scratch(rk_a, rk_b, rk_i, rk_r, sg.stage_off);
+    (void)rk_a;
+    (void)rk_b;
+    (void)rk_i;
+    (void)rk_r;
     unsigned long long thr = 0ull;
     long long thr_idx = nv;
     if (sg.k_votes < nv) {
         // descending singular values (non-finite ones count as 0), ties to the lower index
-        const int i = block_select(
-            [&](int i) { return RankKey{-__longlong_as_double((long long)sv_key(sgm[i])), (long long)i}; }, nv,
-            sg.k_votes - 1, S, g);
+        // descending singular values = ascending complemented key bits
+        const int i = block_radix_select([&](int i) { return ~sv_key(sgm[i]); }, nv, sg.k_votes - 1, S);
         thr = sv_key(sgm[i]);
         thr_idx = i;
     }
     // lower median of E_k
-    const int im = block_select(
-        [&](int i) { return RankKey{__longlong_as_double((long long)sv_key(eb[i])), (long long)i}; }, sg.m,
-        (sg.m - 1) / 2, S, g);
+    const int im = block_radix_select([&](int i) { return sv_key(eb[i]); }, sg.m, (sg.m - 1) / 2, S);
     if (threadIdx.x == 0) {
         SelDev o;
         o.thr_key = thr;

@@ -344,8 +344,7 @@ __host__ __device__ __attribute__((always_inline)) inline bool roots_to_grid(con
         double u = atan2(z[j].y, z[j].x) * ((double)d / (2.0 * M_PI));
         double r = floor(u + 0.5);
         ok &= fabs(u - r) <= delta_grid;
-        int64_t tt = (int64_t)r % d;
-        if (tt < 0) tt += d;
+        const int64_t tt = (int64_t)r & (d - 1);   // r mod d (d is a power of two)
 #pragma unroll
         for (int k = 0; k < kMaxL; ++k)
             if (k < j) ok &= t[k] != tt;

@@ -744,7 +744,8 @@ __device__ inline bool sp_run(const int64_t* cand, int keep, unsigned all, int s
         for (int e = 0; e <= i; ++e) {
             zd sum{0.0, 0.0};
             if (i < keep)
-                for (int j = 0; j < R; ++j) sum = sum + omega(tab, stride, (((cand[e] - cand[i]) * nj[j]) % d + d) & (d - 1));
+                // (t_e - t_i) n_j mod d for d a power of two: the low bits, also for a negative product
+                for (int j = 0; j < R; ++j) sum = sum + omega(tab, stride, ((cand[e] - cand[i]) * nj[j]) & (d - 1));
             g[i * (i + 1) / 2 + e] = sum;
         }
     }

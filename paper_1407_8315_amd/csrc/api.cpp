@@ -101,9 +101,9 @@ struct sft_plan_s {
     // the CS orders): default-priority streams, forked from and joined into
     // the plan's stream with events (captured into the graph as parallel
     // branches)
-    hipStream_t side[kMaxL] = {nullptr, nullptr, nullptr, nullptr};
+    hipStream_t side[kMaxL - 1] = {nullptr, nullptr, nullptr};
     hipEvent_t ev_fork = nullptr;
-    hipEvent_t ev_join[kMaxL] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev_join[kMaxL - 1] = {nullptr, nullptr, nullptr};
     sft_mlp_t mlp = nullptr;
     std::vector<sft_plan_s*> rungs;   // unknown K: plans of the smaller M, ascending (this plan is the last rung)
 };
@@ -212,8 +212,10 @@ bool learned(const sft_plan_s* p) {
     return false;
 }
 
-// Run fn(ctx, i) for i = 1..n, branch i on side stream i-1, after everything
-// already enqueued on the plan's stream; the plan's stream waits for all.
+// Run fn(ctx, i) for i = 1..n as parallel branches after everything already
+// enqueued on the plan's stream: branch 1 on the plan's stream itself,
+// branch i > 1 on side stream i-2 (a process has few hardware queues, so the
+// plan's stream carries one branch); the plan's stream then waits for all.
 template <typename Fn>
 sft_status branches(const sft_plan_s* p, const LaunchCtx& c, int n, Fn fn) {
     if (n <= 1) {
@@ -221,14 +223,15 @@ sft_status branches(const sft_plan_s* p, const LaunchCtx& c, int n, Fn fn) {
         return SFT_OK;
     }
     HIPCHK(hipEventRecord(p->ev_fork, p->stream));
-    for (int i = 0; i < n; ++i) {
-        HIPCHK(hipStreamWaitEvent(p->side[i], p->ev_fork, 0));
+    for (int i = 1; i < n; ++i) {
+        HIPCHK(hipStreamWaitEvent(p->side[i - 1], p->ev_fork, 0));
         LaunchCtx ci = c;
-        ci.stream = p->side[i];
+        ci.stream = p->side[i - 1];
         HIPCHK(fn(ci, i + 1));
-        HIPCHK(hipEventRecord(p->ev_join[i], p->side[i]));
+        HIPCHK(hipEventRecord(p->ev_join[i - 1], p->side[i - 1]));
     }
-    for (int i = 0; i < n; ++i) HIPCHK(hipStreamWaitEvent(p->stream, p->ev_join[i], 0));
+    HIPCHK(fn(c, 1));
+    for (int i = 1; i < n; ++i) HIPCHK(hipStreamWaitEvent(p->stream, p->ev_join[i - 1], 0));
     return SFT_OK;
 }
 

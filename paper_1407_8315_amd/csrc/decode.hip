@@ -730,23 +730,51 @@ __device__ inline bool sp_run(const int64_t* cand, int keep, unsigned all, int s
     // b = Phi^H y, G = Phi^H Phi, ||y||^2
     zd b[KC], g[KC * (KC + 1) / 2];
     double yy = 0.0;
-    #pragma unroll
-    for (int j = 0; j < kMaxR; ++j) yy += (j < R) ? norm2(y[j]) : 0.0;
+    if constexpr (KC <= 4) {
+        // few candidates: stream over the R rows; the KC entries
+        // Phi_jc = w_d^{(t_c n_j) mod d} of row j are gathered together
+        // (independent loads in flight at once) and folded into b and the
+        // upper triangle of G, G_ie = sum_j conj(Phi_ji) Phi_je
 #pragma unroll
-    for (int i = 0; i < KC; ++i) {
-        zd acc{0.0, 0.0};
-        if (i < keep)
+        for (int i = 0; i < KC; ++i) b[i] = zd{0.0, 0.0};
 #pragma unroll
-            for (int j = 0; j < kMaxR; ++j)
-                if (j < R) acc = acc + cmul_conj(omega(tab, stride, (cand[i] * nj[j]) & (d - 1)), y[j]);
-        b[i] = acc;
+        for (int i = 0; i < KC * (KC + 1) / 2; ++i) g[i] = zd{0.0, 0.0};
 #pragma unroll
-        for (int e = 0; e <= i; ++e) {
-            zd sum{0.0, 0.0};
+        for (int j = 0; j < kMaxR; ++j) {
+            if (j >= R) continue;
+            yy += norm2(y[j]);
+            const int64_t nn = nj[j];
+            zd ph[KC];
+#pragma unroll
+            for (int c = 0; c < KC; ++c) ph[c] = c < keep ? omega(tab, stride, (cand[c] * nn) & (d - 1)) : zd{0.0, 0.0};
+#pragma unroll
+            for (int i = 0; i < KC; ++i) {
+                b[i] = b[i] + cmul_conj(ph[i], y[j]);
+#pragma unroll
+                for (int e = 0; e <= i; ++e) g[i * (i + 1) / 2 + e] = g[i * (i + 1) / 2 + e] + cmul_conj(ph[i], ph[e]);
+            }
+        }
+    } else {
+        // many candidates (register bound): one entry at a time, each Gram
+        // entry read from the table as w_d^{((t_e - t_i) n_j) mod d}
+#pragma unroll
+        for (int j = 0; j < kMaxR; ++j) yy += (j < R) ? norm2(y[j]) : 0.0;
+#pragma unroll
+        for (int i = 0; i < KC; ++i) {
+            zd acc{0.0, 0.0};
             if (i < keep)
-                // (t_e - t_i) n_j mod d for d a power of two: the low bits, also for a negative product
-                for (int j = 0; j < R; ++j) sum = sum + omega(tab, stride, ((cand[e] - cand[i]) * nj[j]) & (d - 1));
-            g[i * (i + 1) / 2 + e] = sum;
+#pragma unroll
+                for (int j = 0; j < kMaxR; ++j)
+                    if (j < R) acc = acc + cmul_conj(omega(tab, stride, (cand[i] * nj[j]) & (d - 1)), y[j]);
+            b[i] = acc;
+#pragma unroll
+            for (int e = 0; e <= i; ++e) {
+                zd sum{0.0, 0.0};
+                if (i < keep)
+                    // (t_e - t_i) n_j mod d for d a power of two: the low bits, also for a negative product
+                    for (int j = 0; j < R; ++j) sum = sum + omega(tab, stride, ((cand[e] - cand[i]) * nj[j]) & (d - 1));
+                g[i * (i + 1) / 2 + e] = sum;
+            }
         }
     }
     double corr[KC];

@@ -83,17 +83,21 @@ __host__ __device__ inline void hankel_singular_values(const zd* mt, int L, doub
 // for the general-mode vote, which ranks singular values at noise level or
 // above across bins, not for the rank test of exact mode.
 __host__ __device__ inline void gram_singular_values(const zd* mt, int L, double* sv) {
-    zd g[kMaxL][kMaxL];   // full Hermitian matrix, both halves kept
+    // upper triangle of G (g[i][j], j >= i; the diagonal is real), the lower
+    // half being its conjugate
+    zd g[kMaxL][kMaxL];
 #pragma unroll
     for (int i = 0; i < kMaxL; ++i)
 #pragma unroll
-        for (int j = 0; j < kMaxL; ++j) {
+        for (int j = i; j < kMaxL; ++j) {
             zd acc{0.0, 0.0};
 #pragma unroll
             for (int r = 0; r < kMaxL; ++r)
-                if (r < L && i < L && j < L) acc = acc + cmul_conj(mt[r + i], mt[r + j]);
+                if (r < L && j < L) acc = acc + (i == j ? zd{norm2(mt[r + i]), 0.0} : cmul_conj(mt[r + i], mt[r + j]));
             g[i][j] = acc;
         }
+    // entry (r, c) of G from the stored triangle
+    auto at = [&](int r, int c) -> zd { return r <= c ? g[r][c] : conj(g[c][r]); };
     for (int sweep = 0; sweep < 12; ++sweep) {
         bool rotated = false;
 #pragma unroll
@@ -102,30 +106,36 @@ __host__ __device__ inline void gram_singular_values(const zd* mt, int L, double
             for (int q = p + 1; q < kMaxL; ++q) {
                 if (q >= L) continue;
                 const double a = g[p][p].x, b = g[q][q].x;
-                const zd c = g[p][q];
-                const double c2 = norm2(c);
+                const zd ga = g[p][q];
+                const double c2 = norm2(ga);
                 if (!(c2 > 1e-32 * fabs(a * b)) || c2 == 0.0) continue;
                 rotated = true;
-                const double ac = sqrt(c2), rac = 1.0 / ac;
-                const zd eb = zd{c.x * rac, -c.y * rac};   // conj(c) / |c|
-                const double zeta = (b - a) * (0.5 * rac);
-                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-                // G <- U^H G U with U = [[cs, sn], [-sn conj(e), cs conj(e)]] on (p, q), e = c / |c|
+                // with D = b - a, the rotation's tangent over |ga| is
+                // tau = 2 sgn(D) / (|D| + sqrt(D^2 + 4 |ga|^2)) (the smaller
+                // root), its cosine cs = (1 + tau^2 |ga|^2)^{-1/2};
+                // U = [[cs, psi], [-conj(psi), cs]] on (p, q), psi = cs tau ga,
+                // takes G to U^H G U with a zero at (p, q)
+                const double dd = b - a;
+                const double tau = (dd >= 0.0 ? 2.0 : -2.0) / (fabs(dd) + sqrt(dd * dd + 4.0 * c2));
+                const double tc = tau * c2;
+#ifdef __HIP_DEVICE_COMPILE__
+                const double cs = rsqrt(1.0 + tau * tc);
+#else
+                const double cs = 1.0 / sqrt(1.0 + tau * tc);
+#endif
+                const zd psi = (cs * tau) * ga;
 #pragma unroll
                 for (int r = 0; r < kMaxL; ++r) {
                     if (r == p || r == q || r >= L) continue;
-                    const zd grp = g[r][p], grq = eb * g[r][q];
-                    const zd np = cs * grp - sn * grq, nq = sn * grp + cs * grq;
-                    g[r][p] = np;
-                    g[p][r] = conj(np);
-                    g[r][q] = nq;
-                    g[q][r] = conj(nq);
+                    const zd grp = at(r, p), grq = at(r, q);
+                    const zd np = cs * grp - cmul_conj(psi, grq);   // cs G_rp - conj(psi) G_rq
+                    const zd nq = psi * grp + cs * grq;
+                    if (r < p) g[r][p] = np; else g[p][r] = conj(np);
+                    if (r < q) g[r][q] = nq; else g[q][r] = conj(nq);
                 }
-                g[p][p] = zd{a - t * ac, 0.0};
-                g[q][q] = zd{b + t * ac, 0.0};
+                g[p][p] = zd{a - tc, 0.0};
+                g[q][q] = zd{b + tc, 0.0};
                 g[p][q] = zd{0.0, 0.0};
-                g[q][p] = zd{0.0, 0.0};
             }
         }
         if (!rotated) break;

@@ -197,7 +197,9 @@ __host__ __device__ inline bool cfinite(zd a) { return __builtin_isfinite(a.x) &
 // e^{i 2 pi q / n} for an integer phase 0 <= q < n, n a power of two.
 __device__ inline zd unit_root(int64_t q, int64_t n) {
     double s, c;
-    sincospi(2.0 * (double)q / (double)n, &s, &c);
+    // n a power of two: 2/n and q * (2/n) are exact, the same value as 2q/n
+    // without a division per call
+    sincospi((double)q * (2.0 / (double)n), &s, &c);
     return zd{c, s};
 }
 

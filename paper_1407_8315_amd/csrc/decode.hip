@@ -847,7 +847,7 @@ __device__ inline bool cs_recover(const zd* mt, const zd* y, int R, const int64_
         int64_t t1 = (int64_t)floor(u);
         if (t1 >= d) t1 -= d;
         const double f = u - floor(u);
-        const int64_t up = (t1 + 1) % d, dn = (t1 + d - 1) % d;
+        const int64_t up = (t1 + 1) & (d - 1), dn = (t1 + d - 1) & (d - 1);   // d a power of two
         int64_t first = t1, second = up;
         if (f > 0.5) {
             first = up;
@@ -860,13 +860,13 @@ __device__ inline bool cs_recover(const zd* mt, const zd* y, int R, const int64_
         }
         if (c[0].x == 0.0 && c[0].y == 0.0) {   // |P~| = 1 everywhere: the lowest t's
             first = 0;
-            second = 1 % d;
+            second = 1 & (d - 1);
         }
         bt[0] = first;
         if (keep > 1) bt[1] = second;
     } else {
     // running powers of w_d, refreshed from the table every 64 steps
-    const zd w1 = omega(tab, sg.tab_stride, 1 % d);
+    const zd w1 = omega(tab, sg.tab_stride, 1 & (d - 1));
     zd z{1.0, 0.0};
     for (int64_t t = 0; t < d; ++t) {
         if ((t & 63) == 0) z = omega(tab, sg.tab_stride, t);

@@ -365,19 +365,28 @@ __host__ __device__ __attribute__((always_inline)) inline bool roots_to_grid(con
 
 // Solve the Hermitian positive definite system G x = b (n <= NMAX) in place by
 // Cholesky on the packed lower triangle.  False when not positive definite.
+// Each pivot takes one reciprocal square root r_j = d_j^{-1/2}: L_jj = d_j r_j,
+// and the column scaling and both substitutions multiply by r_j.
 template <int NMAX>
 __host__ __device__ __attribute__((always_inline)) inline bool chol_solve(zd (&g)[NMAX * (NMAX + 1) / 2], zd* b, int n) {
     // g holds rows i >= j at index i*(i+1)/2 + j
+    double rinv[NMAX];
 #pragma unroll
     for (int j = 0; j < NMAX; ++j) {
+        rinv[j] = 1.0;
         if (j >= n) break;
         double dj = g[j * (j + 1) / 2 + j].x;
 #pragma unroll
         for (int k = 0; k < NMAX; ++k)
             if (k < j) dj -= norm2(g[j * (j + 1) / 2 + k]);
         if (!(dj > 0.0)) return false;
-        double ljj = sqrt(dj);
-        g[j * (j + 1) / 2 + j] = zd{ljj, 0.0};
+#ifdef __HIP_DEVICE_COMPILE__
+        const double rj = rsqrt(dj);
+#else
+        const double rj = 1.0 / sqrt(dj);
+#endif
+        rinv[j] = rj;
+        g[j * (j + 1) / 2 + j] = zd{dj * rj, 0.0};
 #pragma unroll
         for (int i = 0; i < NMAX; ++i) {
             if (i <= j || i >= n) continue;
@@ -385,7 +394,7 @@ __host__ __device__ __attribute__((always_inline)) inline bool chol_solve(zd (&g
 #pragma unroll
             for (int k = 0; k < NMAX; ++k)
                 if (k < j) s = s - g[i * (i + 1) / 2 + k] * conj(g[j * (j + 1) / 2 + k]);
-            g[i * (i + 1) / 2 + j] = (1.0 / ljj) * s;
+            g[i * (i + 1) / 2 + j] = rj * s;
         }
     }
     // forward: L y = b
@@ -396,7 +405,7 @@ __host__ __device__ __attribute__((always_inline)) inline bool chol_solve(zd (&g
 #pragma unroll
         for (int k = 0; k < NMAX; ++k)
             if (k < i) s = s - g[i * (i + 1) / 2 + k] * b[k];
-        b[i] = (1.0 / g[i * (i + 1) / 2 + i].x) * s;
+        b[i] = rinv[i] * s;
     }
     // backward: L^H x = y
 #pragma unroll
@@ -406,7 +415,7 @@ __host__ __device__ __attribute__((always_inline)) inline bool chol_solve(zd (&g
 #pragma unroll
         for (int k = 0; k < NMAX; ++k)
             if (k > i && k < n) s = s - conj(g[k * (k + 1) / 2 + i]) * b[k];
-        b[i] = (1.0 / g[i * (i + 1) / 2 + i].x) * s;
+        b[i] = rinv[i] * s;
     }
     return true;
 }

@@ -60,6 +60,7 @@ struct sft_plan_s {
     int64_t* d_shifts = nullptr;
     void* d_tw = nullptr;
     double2* d_om = nullptr;
+    double2* d_gram = nullptr;
     int4* d_synd_items = nullptr;
     int4* d_synd_small_items = nullptr;
     int n_synd_small_items = 0;
@@ -165,6 +166,7 @@ LaunchCtx make_ctx(const sft_plan_s* p) {
     c.twiddle = p->d_tw;
     c.tw_log2 = p->tw_log2;
     c.omega = p->d_om;
+    c.gram = p->d_gram;
     c.om_log2 = p->om_log2;
     c.synd_items = p->d_synd_items;
     c.n_synd_items = p->n_synd_items;
@@ -514,6 +516,7 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     TRY(dalloc(p, &p->d_rk_r, (size_t)lay.stage_elems));
     TRY(dalloc(p, &p->d_shifts, lay.shifts.size()));
     TRY(dalloc(p, &p->d_om, (size_t)1 << lay.om_log2));
+    TRY(dalloc(p, &p->d_gram, std::max<size_t>(1, lay.gram.size())));
     TRY(dalloc(p, &p->d_synd_items, lay.synd_items.size()));
     TRY(dalloc(p, &p->d_synd_small_items, lay.synd_small_items.size()));
     TRY(dalloc(p, &p->d_synd2_items, lay.synd2_items.size()));
@@ -559,11 +562,9 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
         twiddle_table_f32(lay.tw_log2, &tw);
         HIPTRY(hipMemcpy(p->d_tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice));
     }
-    {
-        std::vector<double2> om;
-        omega_table(lay.om_log2, &om);
-        HIPTRY(hipMemcpy(p->d_om, om.data(), om.size() * sizeof(double2), hipMemcpyHostToDevice));
-    }
+    HIPTRY(hipMemcpy(p->d_om, lay.omega.data(), lay.omega.size() * sizeof(double2), hipMemcpyHostToDevice));
+    if (!lay.gram.empty())
+        HIPTRY(hipMemcpy(p->d_gram, lay.gram.data(), lay.gram.size() * sizeof(double2), hipMemcpyHostToDevice));
     if (!lay.synd_items.empty())
         HIPTRY(hipMemcpy(p->d_synd_items, lay.synd_items.data(), lay.synd_items.size() * sizeof(int4), hipMemcpyHostToDevice));
     if (!lay.synd_small_items.empty())

@@ -57,6 +57,7 @@ struct SigDev {
     int32_t view0;           // iterative mode: index of the view of iteration 0
     int64_t it_st_off;       // iterative mode: offset of the signal's status bytes
     int64_t it_rec_off;      // iterative mode: offset of the signal's records
+    int64_t gram_off;        // general mode: offset of the signal's Gram row table F[0 .. d) (CS step)
     double tau_zero2, tau_rank, tau_res2, tau_amp, c_res, delta_grid, delta_mag;
 };
 
@@ -225,6 +226,7 @@ struct LaunchCtx {
     const void* twiddle;     // float2* / double2* of size 2^tw_log2: e^{-2 pi i q / 2^tw_log2}
     int tw_log2;
     const double2* omega;    // e^{+2 pi i q / 2^om_log2}, FP64
+    const double2* gram;     // general mode: Gram row tables F, indexed by SigDev::gram_off
     int om_log2;
     const int4* synd_items;  // (sig, line0, nlines, pass): pass 0 one-pass, 1 first of two
     int n_synd_items;

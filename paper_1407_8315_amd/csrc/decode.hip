@@ -50,6 +50,22 @@ __device__ __attribute__((always_inline)) inline void load_raw(const typename V2
     }
 }
 
+// The R random-shift syndromes of bin k, de-rotated on demand:
+// y_j = e^{-i 2 pi (k n_j mod N) / N} m_{n_j}[k] (the same arithmetic as
+// load_derotated, one line at a time, so a consumer can fold each y_j into
+// its sums without holding all R of them in registers).
+template <typename T>
+struct RowSource {
+    const typename V2<T>::type* __restrict__ syn;   // line 0 of the random-shift lines
+    int log2m;
+    int64_t k, n;
+    const int64_t* sh;                                // n_0 .. n_{R-1}
+    __device__ __attribute__((always_inline)) zd at(int j) const {
+        const auto v = syn[((int64_t)j << log2m) + k];
+        return cmul_conj(unit_root((k * sh[j]) & (n - 1), n), zd{(double)v.x, (double)v.y});
+    }
+};
+
 // In place, for the 2L consecutive shifts l = 0 .. cnt-1:
 // m_l <- e^{-i 2 pi k l / N} m_l, with the phase factors as running powers of
 // e^{-i 2 pi k / N} (a few ulps after 2L - 1 products; one sincospi per bin
@@ -660,10 +676,36 @@ __device__ __attribute__((always_inline)) inline int order_at(int a0, int L, int
 // least squares on a set T solves G_T x = b_T, the residual's correlations are
 // b - G x, and its energy is ||y||^2 - Re(b_T^H x).
 
-// Least squares on the columns in `mask` as a fixed kMaxCand system (identity
+// The candidates' Gram matrix, G_ie = F[(t_e - t_i) mod d] for any i, e (the
+// signal's Gram row table F; G_ei = conj(G_ie)).  Up to 4 candidates keep
+// the packed lower triangle in registers (zero rows for unused slots); with
+// more, the triangle would take 2 KC (KC + 1) registers per lane, so each use
+// gathers its entry from the table (a few KB, cache resident).  Unused slots
+// then read finite values, always multiplied by zero coefficients or masked.
+template <int KC>
+struct CandGram {
+    static constexpr bool kRegs = KC <= 4;
+    zd g[kRegs ? KC * (KC + 1) / 2 : 1];
+    int64_t t[KC];
+    const double2* f;
+    int64_t dmask;
+    __device__ __attribute__((always_inline)) zd at(int i, int e) const {
+        if constexpr (kRegs) {
+            return e <= i ? g[i * (i + 1) / 2 + e] : conj(g[e * (e + 1) / 2 + i]);
+        } else {
+            // a compiler barrier keeps the gather at its use: hoisted out
+            // of the SP iterations, the entries would all sit in registers
+            asm volatile("" ::: "memory");
+            const double2 v = f[(t[e] - t[i]) & dmask];
+            return zd{v.x, v.y};
+        }
+    }
+};
+
+// Least squares on the columns in `mask` as a fixed KC system (identity
 // rows outside the mask).  Returns the residual energy in rn2.
 template <int KC>
-__device__ inline bool cs_ls(const zd* g, const zd* b, double yy, unsigned mask, zd* coef, double& rn2) {
+__device__ inline bool cs_ls(const CandGram<KC>& g, const zd* b, double yy, unsigned mask, zd* coef, double& rn2) {
     zd gm[KC * (KC + 1) / 2];
 #pragma unroll
     for (int a = 0; a < KC; ++a) {
@@ -672,7 +714,7 @@ __device__ inline bool cs_ls(const zd* g, const zd* b, double yy, unsigned mask,
 #pragma unroll
         for (int bb = 0; bb <= a; ++bb) {
             const bool ib = (mask >> bb) & 1u;
-            gm[a * (a + 1) / 2 + bb] = (ia && ib) ? g[a * (a + 1) / 2 + bb] : (a == bb ? zd{1.0, 0.0} : zd{0.0, 0.0});
+            gm[a * (a + 1) / 2 + bb] = (ia && ib) ? g.at(a, bb) : (a == bb ? zd{1.0, 0.0} : zd{0.0, 0.0});
         }
     }
     if (!chol_solve<KC>(gm, coef, KC)) return false;
@@ -686,15 +728,13 @@ __device__ inline bool cs_ls(const zd* g, const zd* b, double yy, unsigned mask,
 
 // |(b - G x)_c|^2 for every candidate c: correlations of the residual.
 template <int KC>
-__device__ inline void cs_residual_corr(const zd* g, const zd* b, const zd* coef, int keep, double* corr) {
+__device__ inline void cs_residual_corr(const CandGram<KC>& g, const zd* b, const zd* coef, int keep, double* corr) {
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
         zd r = b[c];
 #pragma unroll
         for (int e = 0; e < KC; ++e) {
-            // G is Hermitian: G_ce = g[c][e] for e <= c, conj(g[e][c]) otherwise
-            zd gce = (e <= c) ? g[c * (c + 1) / 2 + e] : conj(g[e * (e + 1) / 2 + c]);
-            r = r - gce * coef[e];
+            r = r - g.at(c, e) * coef[e];
         }
         corr[c] = (c < keep) ? norm2(r) : 0.0;
     }
@@ -723,59 +763,41 @@ __device__ inline unsigned top_mask(const double* v, unsigned allowed, int cnt) 
 
 // Subspace Pursuit over the first `keep` (<= KC) candidates with sparsity s;
 // writes the final support mask and its coefficients.
-template <int KC>
-__device__ inline bool sp_run(const int64_t* cand, int keep, unsigned all, int s, const zd* y, int R,
-                              const int64_t* nj, int64_t d, const double2* tab, int stride, unsigned& T_out,
-                              zd* coef_out) {
-    // b = Phi^H y, G = Phi^H Phi, ||y||^2
-    zd b[KC], g[KC * (KC + 1) / 2];
+template <int KC, typename Src>
+__device__ inline bool sp_run(const int64_t* cand, int keep, unsigned all, int s, const Src& ysrc, int R,
+                              const int64_t* nj, int64_t d, const double2* tab, int stride, const double2* gram,
+                              unsigned& T_out, zd* coef_out) {
+    // b = Phi^H y (Phi_jc = w_d^{(t_c n_j) mod d}) and ||y||^2, folding in
+    // one y_j at a time; G = Phi^H Phi from the signal's Gram row table:
+    // G_ie = sum_j w_d^{((t_e - t_i) n_j) mod d} = F[(t_e - t_i) mod d]
+    // (d a power of two: the low bits, also for a negative difference)
+    zd b[KC];
+    CandGram<KC> g;
     double yy = 0.0;
-    if constexpr (KC <= 4) {
-        // few candidates: stream over the R rows; the KC entries
-        // Phi_jc = w_d^{(t_c n_j) mod d} of row j are gathered together
-        // (independent loads in flight at once) and folded into b and the
-        // upper triangle of G, G_ie = sum_j conj(Phi_ji) Phi_je
 #pragma unroll
-        for (int i = 0; i < KC; ++i) b[i] = zd{0.0, 0.0};
+    for (int i = 0; i < KC; ++i) b[i] = zd{0.0, 0.0};
 #pragma unroll
-        for (int i = 0; i < KC * (KC + 1) / 2; ++i) g[i] = zd{0.0, 0.0};
+    for (int j = 0; j < kMaxR; ++j) {
+        if (j < R) {
+            const zd yj = ysrc.at(j);
+            yy += norm2(yj);
 #pragma unroll
-        for (int j = 0; j < kMaxR; ++j) {
-            if (j >= R) continue;
-            yy += norm2(y[j]);
-            const int64_t nn = nj[j];
-            zd ph[KC];
-#pragma unroll
-            for (int c = 0; c < KC; ++c) ph[c] = c < keep ? omega(tab, stride, (cand[c] * nn) & (d - 1)) : zd{0.0, 0.0};
-#pragma unroll
-            for (int i = 0; i < KC; ++i) {
-                b[i] = b[i] + cmul_conj(ph[i], y[j]);
-#pragma unroll
-                for (int e = 0; e <= i; ++e) g[i * (i + 1) / 2 + e] = g[i * (i + 1) / 2 + e] + cmul_conj(ph[i], ph[e]);
-            }
+            for (int i = 0; i < KC; ++i)
+                if (i < keep) b[i] = b[i] + cmul_conj(omega(tab, stride, (cand[i] * nj[j]) & (d - 1)), yj);
         }
-    } else {
-        // many candidates (register bound): one entry at a time, each Gram
-        // entry read from the table as w_d^{((t_e - t_i) n_j) mod d}
+    }
+    g.f = gram;
+    g.dmask = d - 1;
 #pragma unroll
-        for (int j = 0; j < kMaxR; ++j) yy += (j < R) ? norm2(y[j]) : 0.0;
+    for (int i = 0; i < KC; ++i) g.t[i] = cand[i];
+    if constexpr (CandGram<KC>::kRegs) {
 #pragma unroll
-        for (int i = 0; i < KC; ++i) {
-            zd acc{0.0, 0.0};
-            if (i < keep)
-#pragma unroll
-                for (int j = 0; j < kMaxR; ++j)
-                    if (j < R) acc = acc + cmul_conj(omega(tab, stride, (cand[i] * nj[j]) & (d - 1)), y[j]);
-            b[i] = acc;
+        for (int i = 0; i < KC; ++i)
 #pragma unroll
             for (int e = 0; e <= i; ++e) {
-                zd sum{0.0, 0.0};
-                if (i < keep)
-                    // (t_e - t_i) n_j mod d for d a power of two: the low bits, also for a negative product
-                    for (int j = 0; j < R; ++j) sum = sum + omega(tab, stride, ((cand[e] - cand[i]) * nj[j]) & (d - 1));
-                g[i * (i + 1) / 2 + e] = sum;
+                const double2 f = i < keep ? gram[(cand[e] - cand[i]) & (d - 1)] : double2{0.0, 0.0};
+                g.g[i * (i + 1) / 2 + e] = zd{f.x, f.y};
             }
-        }
     }
     double corr[KC];
 #pragma unroll
@@ -787,6 +809,9 @@ __device__ inline bool sp_run(const int64_t* cand, int keep, unsigned all, int s
     for (int it = 0; it < 2 * s + 2; ++it) {
         cs_residual_corr<KC>(g, b, coef, keep, corr);
         const unsigned U = T | top_mask<KC>(corr, all, s);
+        // U = T: least squares on U is that on T, whose s columns are then
+        // kept: no change, so the iteration would stop (exact shortcut)
+        if (U == T) break;
         zd cu[KC];
         double dummy;
         if (!cs_ls<KC>(g, b, yy, U, cu, dummy)) break;
@@ -794,6 +819,7 @@ __device__ inline bool sp_run(const int64_t* cand, int keep, unsigned all, int s
 #pragma unroll
         for (int i = 0; i < KC; ++i) mag[i] = norm2(cu[i]);
         const unsigned Tn = top_mask<KC>(mag, U, s);
+        if (Tn == T) break;   // the same residual as the current one: stop (exact shortcut)
         zd cn[KC];
         double rn2n;
         if (!cs_ls<KC>(g, b, yy, Tn, cn, rn2n)) break;
@@ -818,9 +844,13 @@ __device__ inline bool sp_run(const int64_t* cand, int keep, unsigned all, int s
 // correlated with the residual, solve least squares on the merged set, keep
 // its a0 largest coefficients, re-solve, and stop once the residual stops
 // decreasing.
-template <int A0>
-__device__ inline bool cs_recover(const zd* mt, const zd* y, int R, const int64_t* nj, const SigDev& sg,
-                                  const double2* tab, BinOut& o) {
+//
+// G > 1: the bin is handled by a group of G adjacent lanes (all with the same
+// inputs), which split the scan over the d roots of unity; every later step
+// runs in all G lanes alike.
+template <int A0, int G, typename Src>
+__device__ inline bool cs_recover(const zd* mt, const Src& ysrc, int R, const int64_t* nj, const SigDev& sg,
+                                  const double2* tab, const double2* gram, BinOut& o) {
     const int a0 = A0;
     constexpr int KC = 2 * A0;   // candidate bound min(2 a0, R, d) <= 2 A0
     const int64_t d = sg.d;
@@ -864,6 +894,62 @@ __device__ inline bool cs_recover(const zd* mt, const zd* y, int R, const int64_
         }
         bt[0] = first;
         if (keep > 1) bt[1] = second;
+    } else if constexpr (G > 1) {
+        // lane gl of the group scans t = gl, gl + G, ... (w_d^t from the
+        // table) into its own sorted list of the `keep` smallest |P~|^2, ties
+        // to the lower t; then `keep` rounds take the smallest head over the
+        // group, (e, t) in lexicographic order, and its lane pops it: the same
+        // set as one scan over all t with the same values
+        const int gl = threadIdx.x & (G - 1);
+        for (int64_t t = gl; t < d; t += G) {
+            const zd z = omega(tab, sg.tab_stride, t);
+            zd p, dp;
+            poly_eval(c, a0, z, p, dp);
+            const double e = norm2(p);
+            double ce = e;
+            int64_t ct = t;
+#pragma unroll
+            for (int i = 0; i < KC; ++i) {
+                if (i < keep && ce < best[i]) {
+                    double te = best[i];
+                    int64_t tt = bt[i];
+                    best[i] = ce;
+                    bt[i] = ct;
+                    ce = te;
+                    ct = tt;
+                }
+            }
+        }
+        int64_t sel[KC];
+#pragma unroll
+        for (int r = 0; r < KC; ++r) {
+            sel[r] = INT64_MAX;
+            if (r < keep) {   // the same in every lane of the group
+                double me = best[0];
+                long long mtt = bt[0];
+#pragma unroll
+                for (int off = G / 2; off > 0; off >>= 1) {
+                    const double oe = __shfl_xor(me, off);
+                    const long long ot = __shfl_xor(mtt, off);
+                    if (oe < me || (oe == me && ot < mtt)) {
+                        me = oe;
+                        mtt = ot;
+                    }
+                }
+                sel[r] = mtt;
+                if (bt[0] == mtt) {   // this lane's head was taken
+#pragma unroll
+                    for (int i = 0; i < KC - 1; ++i) {
+                        best[i] = best[i + 1];
+                        bt[i] = bt[i + 1];
+                    }
+                    best[KC - 1] = __builtin_inf();
+                    bt[KC - 1] = INT64_MAX;
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < KC; ++r) bt[r] = sel[r];
     } else {
     // running powers of w_d, refreshed from the table every 64 steps
     const zd w1 = omega(tab, sg.tab_stride, 1 & (d - 1));
@@ -909,7 +995,7 @@ __device__ inline bool cs_recover(const zd* mt, const zd* y, int R, const int64_
     unsigned T = 0u;
     zd coef[KC];
     bool ok;
-    ok = sp_run<KC>(cand, keep, all, s, y, R, nj, d, tab, sg.tab_stride, T, coef);
+    ok = sp_run<KC>(cand, keep, all, s, ysrc, R, nj, d, tab, sg.tab_stride, gram + sg.gram_off, T, coef);
     if (!ok) return false;
     // emit the members of T in ascending t
     o.n = 0;
@@ -1300,19 +1386,28 @@ __global__ void zero_set_kernel(WorkCounters* work, int set) {
     if (threadIdx.x < 2) work->q[q_roots(set, 3 + threadIdx.x)] = 0;
 }
 
-// CS step for the bins the decoder queued (general mode), one lane per bin;
-// one instantiation per vote order A0, so every wave runs one code path.
+// Lanes per bin of the CS step: order 1 needs no scan over the roots of
+// unity; higher orders split it over a group of lanes, wider for the rarer
+// orders, whose few bins would otherwise each be one lane's long serial chain.
+__host__ __device__ constexpr int cs_group_lanes(int a0) { return a0 <= 1 ? 1 : a0 == 2 ? 1 : a0 == 3 ? 8 : 16; }
+
+// CS step for the bins the decoder queued (general mode), one lane (or group
+// of lanes) per bin; one instantiation per vote order A0, so every wave runs
+// one code path.
 template <typename T, int A0>
 __global__ __launch_bounds__(kBlock) void cs_kernel(const SigDev* __restrict__ sigs,
                                                     const int64_t* __restrict__ shifts,
                                                     const typename V2<T>::type* __restrict__ synd,
-                                                    const double2* __restrict__ tab, SigCounters* __restrict__ cnt,
+                                                    const double2* __restrict__ tab,
+                                                    const double2* __restrict__ gram, SigCounters* __restrict__ cnt,
                                                     int64_t* __restrict__ st_loc, double2* __restrict__ st_val,
                                                     const WorkCounters* __restrict__ work,
                                                     const int2* __restrict__ qlist, int64_t list_cap) {
+    constexpr int G = cs_group_lanes(A0);
+    const int gl = threadIdx.x & (G - 1);
     const int total = work->q[q_cs(A0)];
     const int2* in = qlist + (int64_t)q_cs(A0) * list_cap;
-    for (int item = blockIdx.x * kBlock + threadIdx.x; item < total; item += gridDim.x * kBlock) {
+    for (int item = (blockIdx.x * kBlock + threadIdx.x) / G; item < total; item += gridDim.x * (kBlock / G)) {
         const int2 en = in[item];
         const int s = en.x;
         const int64_t k = en.y;
@@ -1322,15 +1417,13 @@ __global__ __launch_bounds__(kBlock) void cs_kernel(const SigDev* __restrict__ s
         zd mt[2 * kMaxL];
         load_raw<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, 2 * L, mt);
         derotate_consecutive<2 * kMaxL>(mt, k, sg.n, 2 * L);
-        zd y[kMaxR];
         const int R = sg.R;
-        load_derotated<T, kMaxR>(synd + sg.synd_off + ((int64_t)(2 * L) << sg.log2m), sg.log2m, k, sg.n, sh + 2 * L,
-                                 R, y);
+        const RowSource<T> ysrc{synd + sg.synd_off + ((int64_t)(2 * L) << sg.log2m), sg.log2m, k, sg.n, sh + 2 * L};
         BinOut o;
         o.n = 0;
-        const bool ok = cs_recover<A0>(mt, y, R, sh + 2 * L, sg, tab, o);
-        if (!ok) o.n = 0;
-        wave_count(&cnt[s].cs, ok);
+        const bool ok = cs_recover<A0, G>(mt, ysrc, R, sh + 2 * L, sg, tab, gram, o);
+        if (!ok || gl != 0) o.n = 0;   // one lane of the group reports the bin
+        wave_count(&cnt[s].cs, ok && gl == 0);
         emit(sg, &cnt[s], k, o, st_loc, st_val);
     }
 }
@@ -1534,7 +1627,7 @@ template <typename T, int A0>
 static void launch_cs_one(const LaunchCtx& c) {
     using V = typename V2<T>::type;
     hipLaunchKernelGGL((cs_kernel<T, A0>), dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs, c.shifts,
-                       (const V*)c.synd, c.omega, c.cnt, c.st_loc, c.st_val, c.work, c.qlist, c.list_cap);
+                       (const V*)c.synd, c.omega, c.gram, c.cnt, c.st_loc, c.st_val, c.work, c.qlist, c.list_cap);
 }
 
 hipError_t launch_cs(const LaunchCtx& c, int a0) {

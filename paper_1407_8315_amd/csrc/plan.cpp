@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <set>
 
 #include "plan_host.h"
@@ -289,6 +290,32 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
     }
     lay->tw_log2 = ilog2(mmax);
     lay->om_log2 = ilog2(dmax);
+    omega_table(lay->om_log2, &lay->omega);
+
+    // CS step (general mode): the Gram matrix of the candidate columns
+    // Phi_jc = w_d^{t_c n_j} has entries sum_j w_d^{(t_e - t_i) n_j}, which
+    // depend on the difference t_e - t_i mod d and the shift set only:
+    // F[delta] = sum_j w_d^{(delta n_j) mod d}, summed in j order from the
+    // device's own omega table (one table per distinct (d, n_j) set)
+    std::map<std::vector<int64_t>, int64_t> gram_of;
+    auto gram_table = [&](const SigHost& g) -> int64_t {
+        std::vector<int64_t> key(g.rshifts);
+        key.push_back(g.d);
+        auto it = gram_of.find(key);
+        if (it != gram_of.end()) return it->second;
+        const int64_t off = (int64_t)lay->gram.size(), stride = dmax / g.d;
+        for (int64_t delta = 0; delta < g.d; ++delta) {
+            double2 acc{0.0, 0.0};
+            for (int64_t nj : g.rshifts) {
+                const double2 w = lay->omega[(size_t)(((delta * nj) & (g.d - 1)) * stride)];
+                acc.x += w.x;
+                acc.y += w.y;
+            }
+            lay->gram.push_back(acc);
+        }
+        gram_of.emplace(std::move(key), off);
+        return off;
+    };
 
     // Assign signals to 8 lanes (one per XCD) by greedy balancing of their
     // syndrome work, so that every block of a signal runs on one XCD.
@@ -359,7 +386,10 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
         ep += g.S;
         bins += g.m;
         stage += g.m * g.L;
-        if (g.mode == SFT_MODE_GENERAL) lay->general_sigs.push_back((int)i);
+        if (g.mode == SFT_MODE_GENERAL) {
+            lay->general_sigs.push_back((int)i);
+            s.gram_off = gram_table(g);
+        }
     }
     // Iterative signals: one view per iteration l, with the grid of that
     // iteration (d_0 2^l, M_0 / 2^l) and its two shifts 2l, 2l + 1, whose

@@ -24,6 +24,8 @@ struct SigHost {
 struct PlanLayout {
     std::vector<SigDev> sigdev;           // the signals, then the views of iterative signals
     std::vector<int64_t> shifts;          // per signal: 0..2L-1, then n_j
+    std::vector<double2> omega;           // e^{+2 pi i q / 2^om_log2}
+    std::vector<double2> gram;            // Gram row tables of the general-mode shift sets
     std::vector<int4> synd_items;         // (sig, line0, nlines, pass 0|1); sig < 0 = padding
     std::vector<int4> synd_small_items;   // one-pass FP32 signals with M <= kFftPointsF32Small
     std::vector<int4> synd2_items;        // (sig, line0, nlines, 2): second FFT pass

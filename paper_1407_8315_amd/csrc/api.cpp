@@ -298,7 +298,12 @@ sft_status enqueue(const sft_plan_s* p, hipEvent_t* events) {
         }
     }
     if (p->any_general) {
-        sft_status bs = branches(p, c, kMaxL, [&](const LaunchCtx& ci, int a0) { return launch_cs(ci, a0); });
+        // one branch per order: order 1 on the plan's stream, then the rare
+        // orders 3 and 4, then order 2 (with four hardware queues per process,
+        // the runtime can run two branches on one queue, in series; measured,
+        // the first two side branches share one, so they carry the cheap pair)
+        static constexpr int kCsOrder[kMaxL] = {1, 3, 4, 2};
+        sft_status bs = branches(p, c, kMaxL, [&](const LaunchCtx& ci, int b) { return launch_cs(ci, kCsOrder[b - 1]); });
         if (bs != SFT_OK) return bs;
     }
     if (events) HIPCHK(hipEventRecord(events[3], p->stream));

@@ -1452,7 +1452,29 @@ __global__ __launch_bounds__(kRankThreads) void output_kernel(const SigDev* __re
     const RankScratch g = rank_scratch(rk_a, rk_b, rk_i, rk_r, sg.stage_off);
     if (threadIdx.x == 0) n_kept = 0;
     __syncthreads();
-    if (sg.mode == kGeneral && n > sg.k_votes) {
+    if (sg.mode == kGeneral && n > sg.k_votes && n <= kRankChunk) {
+        // the K first entries in order of (|value| desc, location asc): the
+        // keys sorted once in LDS (a NaN value sorts as the smallest |value|)
+        const int P = pow2_at_least(n);
+        for (int j = threadIdx.x; j < P; j += blockDim.x) {
+            if (j < n) {
+                const double2 v = val[j];
+                const double a = -(v.x * v.x + v.y * v.y);
+                S.a[j] = a == a ? a : __builtin_inf();
+                S.b[j] = (long long)loc[j];
+                S.idx[j] = j;
+            } else {
+                S.a[j] = __builtin_inf();
+                S.b[j] = (long long)INT64_MAX;
+                S.idx[j] = -1;
+            }
+        }
+        __syncthreads();
+        lds_bitonic(S, P);
+        for (int j = threadIdx.x; j < sg.k_votes; j += blockDim.x) kx[j] = S.idx[j];
+        if (threadIdx.x == 0) n_kept = sg.k_votes;
+        __syncthreads();   // S is reused by the location sort below
+    } else if (sg.mode == kGeneral && n > sg.k_votes) {
         // the K-th entry in order of (|value| desc, location asc); keep it and all before it
         auto key = [&](int i) {
             const double2 v = val[i];

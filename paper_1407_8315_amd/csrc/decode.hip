@@ -124,18 +124,15 @@ __global__ __launch_bounds__(kBlock) void singular_values_kernel(const SigDev* _
 
 // ------------------------------------------------ block-wide ranking
 
-// Ranking and selection over n distinct keys (a, b), ascending in a, then b,
-// by one block of kRankThreads threads.  Up to kRankChunk keys are sorted at
-// once in LDS by a bitonic network.  block_rank() gives every key its rank
-// (several chunks: sorted chunks go to scratch and each key adds, per other
-// chunk, the count of that chunk's keys below it, by binary search);
-// block_select() finds the key of one rank by sorting only a window of keys
-// around it, bracketed by a sorted sample (falling back to block_rank when
-// the window misses or overflows).  Used for the vote threshold, the
-// noise-floor median, the top-K of general mode and the output order.
+// Ranking over n distinct keys (a, b), ascending in a, then b, by one block
+// of kRankThreads threads.  Up to kRankChunk keys are sorted at once in LDS
+// by a bitonic network.  block_rank() gives every key its rank (several
+// chunks: sorted chunks go to scratch and each key adds, per other chunk, the
+// count of that chunk's keys below it, by binary search).  Used for the
+// top-K of general mode and the output order; block_radix_select() (below)
+// finds single ranks: the vote threshold and the noise-floor median.
 constexpr int kRankThreads = 512;
 constexpr int kRankChunk = 2048;
-constexpr int kSelSample = 1024;
 
 struct RankKey {
     double a;
@@ -145,11 +142,10 @@ __device__ inline bool key_less(double a1, long long b1, double a2, long long b2
     return a1 < a2 || (a1 == a2 && b1 < b2);
 }
 
-struct RankLds {
+struct RankLds {   // 40 KB: four blocks of kRankThreads share a CU's 160 KB
     double a[kRankChunk];
     long long b[kRankChunk];
     int idx[kRankChunk];
-    int n_below, n_win, pick;
 };
 
 struct RankScratch {   // per-signal slices of the plan's ranking scratch
@@ -276,154 +272,16 @@ __device__ void block_rank(KeyFn key, int n, RankLds& S, const RankScratch& g) {
     }
 }
 
-// Index i of the key of ascending rank r (0 <= r < n).  Whole block.
-template <typename KeyFn>
-__device__ int block_select(KeyFn key, int n, int r, RankLds& S, const RankScratch& g) {
-    if (n <= kRankChunk) {
-        const int P = pow2_at_least(n);
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            const RankKey k = key(i);
-            S.a[i] = k.a;
-            S.b[i] = k.b;
-            S.idx[i] = i;
-        }
-        pad_keys(S, n, P);
-        __syncthreads();
-        lds_bitonic(S, P);
-        const int out = S.idx[r];
-        __syncthreads();
-        return out;
-    }
-    // Sample-window refinement.  Round 0: a sorted sample at scattered
-    // positions (t times an odd constant mod n: no aliasing with a stride of
-    // the data, such as the L singular values of a bin).  Later rounds: a
-    // hashed subsample of the keys still inside the window.  Each round keeps
-    // the sample ranks about r's expected place, +- 3 standard deviations and
-    // a margin, counts the keys below and inside that window, and stops once
-    // the window holds at most kRankChunk keys (then sorted in LDS).  A window
-    // that misses rank r keeps the previous bounds and widens the margin.
-    bool has_lo = false, has_hi = false;
-    double lo_a = 0.0, hi_a = 0.0;
-    long long lo_b = 0, hi_b = 0;
-    int nb = 0;      // keys below the window
-    int ncur = n;    // keys inside it
-    int widen = 1;
-    auto inside = [&](const RankKey& k, bool hl, double la, long long lb, bool hh, double ha, long long hb) {
-        return !(hl && key_less(k.a, k.b, la, lb)) && (!hh || !key_less(ha, hb, k.a, k.b));
-    };
-    for (int round = 0; round < 64 && ncur > kRankChunk; ++round) {
-        if (threadIdx.x == 0) S.n_win = 0;
-        __syncthreads();
-        int ns;
-        if (round == 0) {
-            for (int t = threadIdx.x; t < kSelSample; t += blockDim.x) {
-                const int i = (int)(((unsigned long long)t * 2654435761ull) % (unsigned long long)n);
-                const RankKey k = key(i);
-                S.a[t] = k.a;
-                S.b[t] = k.b;
-                S.idx[t] = i;
-            }
-            ns = kSelSample;
-        } else {
-            // keep a window key when a hash of (index, round) falls below
-            // about 0.9 kSelSample / ncur of the 32-bit range
-            const unsigned long long keep =
-                (unsigned long long)(0.9 * (double)kSelSample / (double)ncur * 4294967296.0);
-            for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                unsigned h = (unsigned)i * 0x9E3779B1u + (unsigned)round * 0x85EBCA77u;
-                h ^= h >> 15;
-                h *= 0x2C1B3C6Du;
-                h ^= h >> 12;
-                if ((unsigned long long)h >= keep) continue;
-                const RankKey k = key(i);
-                if (!inside(k, has_lo, lo_a, lo_b, has_hi, hi_a, hi_b)) continue;
-                const int pos = atomicAdd(&S.n_win, 1);
-                if (pos < kSelSample) {
-                    S.a[pos] = k.a;
-                    S.b[pos] = k.b;
-                    S.idx[pos] = i;
-                }
-            }
-            __syncthreads();
-            ns = min(S.n_win, kSelSample);
-        }
-        const int P = pow2_at_least(ns > 0 ? ns : 1);
-        pad_keys(S, ns, P);
-        __syncthreads();
-        lds_bitonic(S, P);
-        // window of sample ranks about r's place among the ncur window keys
-        const double q = ((double)(r - nb) + 0.5) / (double)ncur;
-        const int rs = (int)(q * ns);
-        const int w = widen * ((int)(3.0 * sqrt((double)ns * q * (1.0 - q))) + 8);
-        const bool nlo = ns > 0 && rs - w >= 0, nhi = ns > 0 && rs + w < ns;
-        const double nlo_a = nlo ? S.a[rs - w] : lo_a, nhi_a = nhi ? S.a[rs + w] : hi_a;
-        const long long nlo_b = nlo ? S.b[rs - w] : lo_b, nhi_b = nhi ? S.b[rs + w] : hi_b;
-        const bool hl = nlo || has_lo, hh = nhi || has_hi;
-        if (threadIdx.x == 0) {
-            S.n_below = 0;
-            S.n_win = 0;
-        }
-        __syncthreads();
-        int below = 0, win = 0;
-#pragma unroll 8
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            const RankKey k = key(i);
-            if (!inside(k, has_lo, lo_a, lo_b, has_hi, hi_a, hi_b)) continue;
-            if (hl && key_less(k.a, k.b, nlo_a, nlo_b)) ++below;
-            else if (!hh || !key_less(nhi_a, nhi_b, k.a, k.b)) ++win;
-        }
-        atomicAdd(&S.n_below, below);
-        atomicAdd(&S.n_win, win);
-        __syncthreads();
-        const int nb2 = nb + S.n_below, nw2 = S.n_win;
-        __syncthreads();
-        if (nb2 <= r && r < nb2 + nw2) {
-            nb = nb2;
-            ncur = nw2;
-            has_lo = hl;
-            has_hi = hh;
-            lo_a = nlo_a;
-            lo_b = nlo_b;
-            hi_a = nhi_a;
-            hi_b = nhi_b;
-            widen = 1;
-        } else {
-            widen *= 4;
-        }
-    }
-    if (ncur <= kRankChunk) {
-        if (threadIdx.x == 0) S.n_win = 0;
-        __syncthreads();
-#pragma unroll 8
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            const RankKey k = key(i);
-            if (inside(k, has_lo, lo_a, lo_b, has_hi, hi_a, hi_b)) {
-                const int pos = atomicAdd(&S.n_win, 1);
-                S.a[pos] = k.a;
-                S.b[pos] = k.b;
-                S.idx[pos] = i;
-            }
-        }
-        __syncthreads();
-        const int nw = S.n_win;
-        const int P = pow2_at_least(nw);
-        pad_keys(S, nw, P);
-        __syncthreads();
-        lds_bitonic(S, P);
-        const int out = S.idx[r - nb];
-        __syncthreads();
-        return out;
-    }
-    block_rank(key, n, S, g);
-    if (threadIdx.x == 0) S.pick = -1;
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
-        if (g.rank[i] == r) S.pick = i;
-    __syncthreads();
-    const int out = S.pick;
-    __syncthreads();
-    return out;
-}
+// LDS of block_radix_select: the candidates' keys and indices, the indices
+// of the final ties, the digit histogram and the broadcast scalars (33 KB, so
+// that four blocks of kRankThreads share a CU's 160 KB).
+struct RadixLds {
+    unsigned long long key[kRankChunk];
+    int idx[kRankChunk];
+    int tie[kRankChunk];
+    int hist[256];
+    int sel_digit, sel_rr, n_cand, pick;
+};
 
 // Index of the key of ascending rank r (0 <= r < n) in the order (ukey(i), i),
 // by radix selection on the 64-bit keys, 8 bits per pass: each pass counts
@@ -433,9 +291,11 @@ __device__ int block_select(KeyFn key, int n, int r, RankLds& S, const RankScrat
 // go to the lower index.  Whole block; the result is the same element a full
 // sort would give.
 template <typename UKeyFn>
-__device__ int block_radix_select(UKeyFn ukey, int n, int r, RankLds& S) {
-    __shared__ int hist[256];
-    __shared__ int sel_digit, sel_rr, n_cand;
+__device__ int block_radix_select(UKeyFn ukey, int n, int r, RadixLds& S) {
+    int* hist = S.hist;
+    int& sel_digit = S.sel_digit;
+    int& sel_rr = S.sel_rr;
+    int& n_cand = S.n_cand;
     unsigned long long prefix = 0ull, mask = 0ull;
     int rr = r;
     bool in_lds = false;
@@ -450,7 +310,7 @@ __device__ int block_radix_select(UKeyFn ukey, int n, int r, RankLds& S) {
                 const unsigned long long k = ukey(i);
                 if ((k & mask) == prefix) {
                     const int pos = atomicAdd(&n_cand, 1);
-                    S.b[pos] = (long long)k;
+                    S.key[pos] = k;
                     S.idx[pos] = i;
                 }
             }
@@ -462,7 +322,7 @@ __device__ int block_radix_select(UKeyFn ukey, int n, int r, RankLds& S) {
         __syncthreads();
         if (in_lds) {
             for (int j = threadIdx.x; j < nc; j += blockDim.x) {
-                const unsigned long long k = (unsigned long long)S.b[j];
+                const unsigned long long k = S.key[j];
                 if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & 255], 1);
             }
         } else {
@@ -516,7 +376,7 @@ __device__ int block_radix_select(UKeyFn ukey, int n, int r, RankLds& S) {
         __syncthreads();
     }
     // the rr-th lowest index among the keys equal to prefix
-    __shared__ int pick;
+    int& pick = S.pick;
     if (threadIdx.x == 0) {
         n_cand = 0;
         pick = -1;
@@ -524,14 +384,14 @@ __device__ int block_radix_select(UKeyFn ukey, int n, int r, RankLds& S) {
     __syncthreads();
     if (in_lds) {
         for (int j = threadIdx.x; j < nc; j += blockDim.x)
-            if ((unsigned long long)S.b[j] == prefix) S.a[atomicAdd(&n_cand, 1)] = (double)S.idx[j];
+            if (S.key[j] == prefix) S.tie[atomicAdd(&n_cand, 1)] = S.idx[j];
         __syncthreads();
         const int ne = n_cand;
         for (int j = threadIdx.x; j < ne; j += blockDim.x) {
-            const double v = S.a[j];
+            const int v = S.tie[j];
             int below = 0;
-            for (int t = 0; t < ne; ++t) below += S.a[t] < v ? 1 : 0;
-            if (below == rr) pick = (int)v;
+            for (int t = 0; t < ne; ++t) below += S.tie[t] < v ? 1 : 0;
+            if (below == rr) pick = v;
         }
     } else {
         // more than kRankChunk keys equal the selected one: count them per
@@ -577,7 +437,7 @@ __global__ __launch_bounds__(kRankThreads) void select_kernel(const SigDev* __re
                                                               const double* __restrict__ sigma,
                                                               const double* __restrict__ ebin, SelDev* __restrict__ sel,
                                                               double* rk_a, long long* rk_b, int* rk_i, int* rk_r) {
-    __shared__ RankLds S;
+    __shared__ RadixLds S;
     const int s = gsigs[blockIdx.x];
     const SigDev& sg = sigs[s];
     const int nv = sg.m * sg.L;
@@ -1439,8 +1299,13 @@ __global__ __launch_bounds__(kRankThreads) void output_kernel(const SigDev* __re
                                                               const int64_t* __restrict__ st_loc,
                                                               const double2* __restrict__ st_val, int* __restrict__ kidx,
                                                               double* rk_a, long long* rk_b, int* rk_i, int* rk_r) {
-    __shared__ RankLds S;
-    __shared__ int n_kept;
+    // the location sort (LDS) and the radix selections of the top-K share one
+    // region (40 KB: four blocks per CU)
+    __shared__ union {
+        RankLds rank;
+        RadixLds radix;
+    } U;
+    RankLds& S = U.rank;
     const int s = blockIdx.x;
     const SigDev& sg = sigs[s];
     const IoDev o = io[s];
@@ -1450,53 +1315,66 @@ __global__ __launch_bounds__(kRankThreads) void output_kernel(const SigDev* __re
     const double2* val = st_val + sg.stage_off;
     int* kx = kidx + sg.stage_off;
     const RankScratch g = rank_scratch(rk_a, rk_b, rk_i, rk_r, sg.stage_off);
-    if (threadIdx.x == 0) n_kept = 0;
-    __syncthreads();
-    if (sg.mode == kGeneral && n > sg.k_votes && n <= kRankChunk) {
+    int& n_kept = U.radix.n_cand;   // keep counter of the paths that append
+    int nk;
+    if (sg.mode == kGeneral && n > sg.k_votes) {
         // the K first entries in order of (|value| desc, location asc): the
-        // keys sorted once in LDS (a NaN value sorts as the smallest |value|)
-        const int P = pow2_at_least(n);
-        for (int j = threadIdx.x; j < P; j += blockDim.x) {
-            if (j < n) {
-                const double2 v = val[j];
-                const double a = -(v.x * v.x + v.y * v.y);
-                S.a[j] = a == a ? a : __builtin_inf();
-                S.b[j] = (long long)loc[j];
-                S.idx[j] = j;
-            } else {
-                S.a[j] = __builtin_inf();
-                S.b[j] = (long long)INT64_MAX;
-                S.idx[j] = -1;
-            }
+        // K-th largest |value|^2 by radix selection (key: complemented bits,
+        // so ascending key = descending magnitude; NaN as zero), then, when
+        // several entries share that magnitude, the lowest locations among
+        // them by a second selection
+        auto mag = [&](int i) -> unsigned long long {
+            const double2 v = val[i];
+            const double m = v.x * v.x + v.y * v.y;
+            return ~(unsigned long long)__double_as_longlong(m == m ? m : 0.0);
+        };
+        const int ik = block_radix_select(mag, n, sg.k_votes - 1, U.radix);
+        const unsigned long long uk = mag(ik);
+        int& n_gt = U.radix.sel_digit;   // free between the selections
+        int& n_eq = U.radix.sel_rr;
+        if (threadIdx.x == 0) {
+            n_gt = 0;
+            n_eq = 0;
         }
         __syncthreads();
-        lds_bitonic(S, P);
-        for (int j = threadIdx.x; j < sg.k_votes; j += blockDim.x) kx[j] = S.idx[j];
-        if (threadIdx.x == 0) n_kept = sg.k_votes;
-        __syncthreads();   // S is reused by the location sort below
-    } else if (sg.mode == kGeneral && n > sg.k_votes) {
-        // the K-th entry in order of (|value| desc, location asc); keep it and all before it
-        auto key = [&](int i) {
-            const double2 v = val[i];
-            return RankKey{-(v.x * v.x + v.y * v.y), (long long)loc[i]};
-        };
-        const int ik = block_select(key, n, sg.k_votes - 1, S, g);
-        const RankKey kk = key(ik);
+        int cg = 0, ce = 0;
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            const RankKey ki = key(i);
-            if (!key_less(kk.a, kk.b, ki.a, ki.b)) kx[atomicAdd(&n_kept, 1)] = i;
+            const unsigned long long ui = mag(i);
+            cg += ui < uk ? 1 : 0;
+            ce += ui == uk ? 1 : 0;
         }
+        if (cg) atomicAdd(&n_gt, cg);
+        if (ce) atomicAdd(&n_eq, ce);
+        __syncthreads();
+        const int need = sg.k_votes - n_gt;   // 1 <= need <= n_eq
+        const int eq = n_eq;
+        __syncthreads();                      // n_gt, n_eq read before the second selection reuses them
+        int64_t lk = INT64_MAX;               // all entries of magnitude uk kept
+        if (need < eq)
+            lk = loc[block_radix_select([&](int i) { return mag(i) == uk ? (unsigned long long)loc[i] : ~0ull; }, n,
+                                        need - 1, U.radix)];
+        if (threadIdx.x == 0) n_kept = 0;
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const unsigned long long ui = mag(i);
+            if (ui < uk || (ui == uk && loc[i] <= lk)) kx[atomicAdd(&n_kept, 1)] = i;
+        }
+        __syncthreads();
+        nk = n_kept;
     } else if (sg.mode == kIterative) {
         // entries whose accumulated value cancelled carry location -1
         // (locations are distinct, so the order of kx does not matter)
+        if (threadIdx.x == 0) n_kept = 0;
+        __syncthreads();
         for (int i = threadIdx.x; i < n; i += blockDim.x)
             if (loc[i] >= 0) kx[atomicAdd(&n_kept, 1)] = i;
+        __syncthreads();
+        nk = n_kept;
     } else {
         for (int i = threadIdx.x; i < n; i += blockDim.x) kx[i] = i;
-        if (threadIdx.x == 0) n_kept = n;
+        nk = n;
     }
-    __syncthreads();
-    const int nk = n_kept;
+    __syncthreads();   // kx complete; U is reused below
     if (nk <= kRankChunk) {
         // (location << 24 | entry) as one 64-bit key (location < 2^40, entry < 2^24):
         // the sorted position is the output position

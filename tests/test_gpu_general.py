@@ -63,6 +63,27 @@ def test_general_n20_metrics_match_oracle(torch, sft, snr):
     assert same >= tot - 4
 
 
+def test_general_top_k_beyond_one_lds_sort(torch, sft):
+    """More entries found than the 2048 one LDS sort holds (the output's
+    top-K then runs by radix selection): a signal of 6000 terms decoded with
+    K = 2100 (the oracle finds about 2300 entries before keeping K) keeps the
+    same K entries as the oracle, but for a few bins."""
+    n, k_true, k, m, L = 1 << 18, 6000, 2100, 8192, 4
+    s = sftgen.make_signal(n, k_true, 913, amp="gauss", dtype=np.complex64, snr_db=30)
+    say("[general top-K > 2048]")
+    plan = sft.Plan(dict(n=n, k=k, m=m, l=L, mode="general", seed=79))
+    res = plan.general(to_dev(torch, s.x), stats=True)
+    loc, val = res.host()
+    rsh = plan.info()["rshifts"]
+    plan.close()
+    ref = oracle.sfft_general(s.x, n, k, m, L, rsh)
+    same = len(np.intersect1d(loc, ref.locs))
+    say(f"  kept gpu {len(loc)} oracle {len(ref.locs)}; same {same}")
+    assert len(loc) == len(ref.locs) == k
+    assert np.all(np.diff(loc) > 0)
+    assert same >= k - 8
+
+
 def test_general_exact_input_is_exact(torch, sft):
     n, k, m, L = 1 << 16, 200, 1024, 4
     s = sftgen.make_signal(n, k, 21, amp="gauss", dtype=np.complex128)

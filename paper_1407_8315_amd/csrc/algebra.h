@@ -116,11 +116,22 @@ __host__ __device__ inline void gram_singular_values(const zd* mt, int L, double
                 // U = [[cs, psi], [-conj(psi), cs]] on (p, q), psi = cs tau ga,
                 // takes G to U^H G U with a zero at (p, q)
                 const double dd = b - a;
-                const double tau = (dd >= 0.0 ? 2.0 : -2.0) / (fabs(dd) + sqrt(dd * dd + 4.0 * c2));
-                const double tc = tau * c2;
 #ifdef __HIP_DEVICE_COMPILE__
+                // sqrt(q) = q q^{-1/2} and 1/h by the hardware reciprocal with
+                // two Newton steps: tau to a few ulps, which only moves the
+                // rotation angle; the rotation stays unitary to rounding since
+                // cs is computed from the tau actually used
+                const double qq = fma(dd, dd, 4.0 * c2);
+                const double h = fabs(dd) + qq * rsqrt(qq);
+                double y = __builtin_amdgcn_rcp(h);
+                y = fma(fma(-h, y, 1.0), y, y);
+                y = fma(fma(-h, y, 1.0), y, y);
+                const double tau = (dd >= 0.0 ? 2.0 : -2.0) * y;
+                const double tc = tau * c2;
                 const double cs = rsqrt(1.0 + tau * tc);
 #else
+                const double tau = (dd >= 0.0 ? 2.0 : -2.0) / (fabs(dd) + sqrt(dd * dd + 4.0 * c2));
+                const double tc = tau * c2;
                 const double cs = 1.0 / sqrt(1.0 + tau * tc);
 #endif
                 const zd psi = (cs * tau) * ga;

@@ -191,7 +191,7 @@ __host__ __device__ __attribute__((always_inline)) inline bool rank_one_certifie
         if (l <= 2 * L - 2) e += norm2(mt[l]);
     if (e == 0.0) return true;
     if (!(n0 > 0.0) || !__builtin_isfinite(e)) return false;
-    const zd inv0 = (1.0 / n0) * conj(mt[0]);
+    const zd inv0 = frcp(n0) * conj(mt[0]);
     zd u[kMaxL];
     double colsq = 0.0;
 #pragma unroll
@@ -336,10 +336,10 @@ __host__ __device__ __attribute__((always_inline)) inline bool poly_roots(const 
             for (int k = 0; k < kMaxL; ++k)
                 if (k < a && k != j) {
                     const zd dz = z[j] - z[k];
-                    sum = sum + (1.0 / norm2(dz)) * conj(dz);
+                    sum = sum + frcp(norm2(dz)) * conj(dz);
                 }
             const zd den = dp - p * sum;
-            zd w = (1.0 / norm2(den)) * (p * conj(den));
+            zd w = frcp(norm2(den)) * (p * conj(den));
             bad |= !cfinite(w);
             z[j] = z[j] - w;
             step = fmax(step, norm2(w));

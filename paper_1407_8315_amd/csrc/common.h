@@ -174,14 +174,27 @@ __host__ __device__ inline zd conj(zd a) { return zd{a.x, -a.y}; }
 __host__ __device__ inline double norm2(zd a) { return a.x * a.x + a.y * a.y; }
 __host__ __device__ inline double cabs(zd a) { return sqrt(norm2(a)); }
 __host__ __device__ inline zd cmul_conj(zd a, zd b) { return conj(a) * b; }   // conj(a) * b
+// 1/x: on the device the hardware reciprocal refined by two Newton steps
+// (within an ulp or two of the quotient; 1/0 and 1/inf give NaN instead of
+// inf and 0, which the decoder's finiteness checks reject like the quotients
+// they feed), on the host the IEEE division.
+__host__ __device__ inline double frcp(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(fma(-x, y, 1.0), y, y);
+    return fma(fma(-x, y, 1.0), y, y);
+#else
+    return 1.0 / x;
+#endif
+}
 __host__ __device__ inline zd cdiv(zd a, zd b) {
-    // Smith's algorithm
+    // Smith's algorithm, one reciprocal of the scaled denominator
     if (fabs(b.x) >= fabs(b.y)) {
-        double r = b.y / b.x, den = b.x + b.y * r;
-        return zd{(a.x + a.y * r) / den, (a.y - a.x * r) / den};
+        const double r = b.y * frcp(b.x), inv = frcp(b.x + b.y * r);
+        return zd{(a.x + a.y * r) * inv, (a.y - a.x * r) * inv};
     }
-    double r = b.x / b.y, den = b.x * r + b.y;
-    return zd{(a.x * r + a.y) / den, (a.y * r - a.x) / den};
+    const double r = b.x * frcp(b.y), inv = frcp(b.x * r + b.y);
+    return zd{(a.x * r + a.y) * inv, (a.y * r - a.x) * inv};
 }
 __host__ __device__ inline zd csqrt(zd a) {
     double r = hypot(a.x, a.y);

@@ -761,11 +761,13 @@ __device__ inline bool cs_recover(const zd* mt, const Src& ysrc, int R, const in
         // group, (e, t) in lexicographic order, and its lane pops it: the same
         // set as one scan over all t with the same values
         const int gl = threadIdx.x & (G - 1);
+        double worst = __builtin_inf();   // best[keep - 1], refreshed after each insertion
         for (int64_t t = gl; t < d; t += G) {
             const zd z = omega(tab, sg.tab_stride, t);
             zd p, dp;
             poly_eval(c, a0, z, p, dp);
             const double e = norm2(p);
+            if (!(e < worst)) continue;
             double ce = e;
             int64_t ct = t;
 #pragma unroll
@@ -779,6 +781,9 @@ __device__ inline bool cs_recover(const zd* mt, const Src& ysrc, int R, const in
                     ct = tt;
                 }
             }
+#pragma unroll
+            for (int i = 0; i < KC; ++i)
+                if (i == keep - 1) worst = best[i];
         }
         int64_t sel[KC];
 #pragma unroll
@@ -814,13 +819,14 @@ __device__ inline bool cs_recover(const zd* mt, const Src& ysrc, int R, const in
     // running powers of w_d, refreshed from the table every 64 steps
     const zd w1 = omega(tab, sg.tab_stride, 1 & (d - 1));
     zd z{1.0, 0.0};
+    double worst = __builtin_inf();   // best[keep - 1], refreshed after each insertion
     for (int64_t t = 0; t < d; ++t) {
         if ((t & 63) == 0) z = omega(tab, sg.tab_stride, t);
         zd p, dp;
         poly_eval(c, a0, z, p, dp);
         z = z * w1;
         double e = norm2(p);
-        if (!(e < best[keep - 1])) continue;
+        if (!(e < worst)) continue;
         // insertion into the sorted prefix of length keep (fixed-index shifts)
         double ce = e;
         int64_t ct = t;
@@ -835,6 +841,9 @@ __device__ inline bool cs_recover(const zd* mt, const Src& ysrc, int R, const in
                 ct = tt;
             }
         }
+#pragma unroll
+        for (int i = 0; i < KC; ++i)
+            if (i == keep - 1) worst = best[i];
     }
     }
     // candidates in ascending t (positions 0..keep-1), unused slots last

@@ -31,11 +31,11 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector, published
 BF16_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 MFMA, published
 
-# HBM bytes of the gather + FFT kernel (syndrome_kernel<float, 4096>) per
+# HBM bytes of the gather + FFT kernel (syndrome_kernel<float, 4096, float>) per
 # algorithmic byte read and written, from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # scaled by the plain-copy calibration (profiles/syndrome_kernel_n20_b1024_traffic.md,
 # profiles/syndrome_kernel_iterative_n20_b1024_traffic.md).
-TRAFFIC_RATIOS = {"exact": (2.01, 1.00), "general": (7.97, 1.00), "iterative": (5.27, 1.00)}
+TRAFFIC_RATIOS = {"exact": (2.01, 1.00), "general": (7.98, 1.00), "iterative": (5.27, 1.00)}
 
 # Algorithmic FLOPs of the order predictor per row (matrix products only):
 # forward 2 (32*128 + 128*128 + 128*5); training adds the three weight

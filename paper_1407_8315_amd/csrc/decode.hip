@@ -273,63 +273,118 @@ __device__ void block_rank(KeyFn key, int n, RankLds& S, const RankScratch& g) {
 }
 
 // LDS of block_radix_select: the candidates' keys and indices, the indices
-// of the final ties, the digit histogram and the broadcast scalars (33 KB, so
-// that four blocks of kRankThreads share a CU's 160 KB).
+// of the final ties, the digit histogram (kRadixCopies copies, lanes spread
+// over them, so that keys of one digit contend less), the per-wave partials
+// of the common-prefix pass and the broadcast scalars (37 KB, so that four
+// blocks of kRankThreads share a CU's 160 KB).
+constexpr int kRadixCopies = 4;
 struct RadixLds {
     unsigned long long key[kRankChunk];
     int idx[kRankChunk];
     int tie[kRankChunk];
-    int hist[256];
+    int hist[kRadixCopies * 256];
+    unsigned long long kor[kRankThreads / 64], kand[kRankThreads / 64];
     int sel_digit, sel_rr, n_cand, pick;
 };
 
 // Index of the key of ascending rank r (0 <= r < n) in the order (ukey(i), i),
 // by radix selection on the 64-bit keys, 8 bits per pass: each pass counts
 // the candidates (keys matching the digits fixed so far) per next digit and
-// keeps the digit that holds rank r.  Once the candidates fit in LDS they are
-// gathered there and the remaining passes run on LDS.  Ties of the full key
-// go to the lower index.  Whole block; the result is the same element a full
-// sort would give.
+// keeps the digit that holds rank r.  A first pass finds the bits common to
+// all keys (their OR and AND), and the digit passes start at the digit of the
+// highest bit that differs.  Once the candidates fit in LDS they are gathered
+// there and the remaining passes run on LDS.  Ties of the full key go to the
+// lower index.  Whole block of kRankThreads; the result is the same element a
+// full sort would give.
 template <typename UKeyFn>
 __device__ int block_radix_select(UKeyFn ukey, int n, int r, RadixLds& S) {
     int* hist = S.hist;
     int& sel_digit = S.sel_digit;
     int& sel_rr = S.sel_rr;
     int& n_cand = S.n_cand;
-    unsigned long long prefix = 0ull, mask = 0ull;
+    const int lane = threadIdx.x & 63;
+    // bits common to all keys
+    unsigned long long kor = 0ull, kand = ~0ull;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const unsigned long long k = ukey(i);
+        kor |= k;
+        kand &= k;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        kor |= __shfl_xor(kor, o, 64);
+        kand &= __shfl_xor(kand, o, 64);
+    }
+    if (lane == 0) {
+        S.kor[threadIdx.x >> 6] = kor;
+        S.kand[threadIdx.x >> 6] = kand;
+    }
+    __syncthreads();
+    kor = 0ull;
+    kand = ~0ull;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        kor |= S.kor[w];
+        kand &= S.kand[w];
+    }
+    const unsigned long long diff = kor ^ kand;
+    // first digit: the one holding the highest differing bit (none: all keys equal)
+    const int first = diff == 0ull ? -8 : ((63 - __clzll((long long)diff)) / 8) * 8;
+    unsigned long long mask = first >= 56 ? 0ull : (first < 0 ? ~0ull : ~0ull << (first + 8));
+    unsigned long long prefix = kand & mask;
     int rr = r;
     bool in_lds = false;
     int nc = n;   // candidates
-    for (int shift = 56; shift >= 0; shift -= 8) {
+    for (int shift = first; shift >= 0; shift -= 8) {
         if (!in_lds && nc <= kRankChunk) {
-            // gather the candidates (ascending index order is not kept: ties
-            // are resolved by index below)
+            // gather the candidates, one LDS atomic per wave (ascending index
+            // order is not kept: ties are resolved by index below)
             if (threadIdx.x == 0) n_cand = 0;
             __syncthreads();
-            for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                const unsigned long long k = ukey(i);
-                if ((k & mask) == prefix) {
-                    const int pos = atomicAdd(&n_cand, 1);
-                    S.key[pos] = k;
-                    S.idx[pos] = i;
+            for (int i0 = 0; i0 < n; i0 += blockDim.x) {
+                const int i = i0 + threadIdx.x;
+                unsigned long long k = 0ull;
+                bool take = false;
+                if (i < n) {
+                    k = ukey(i);
+                    take = (k & mask) == prefix;
+                }
+                const unsigned long long bal = __ballot(take);
+                if (bal != 0ull) {
+                    const int leader = __ffsll((long long)bal) - 1;
+                    int base = 0;
+                    if (lane == leader) base = atomicAdd(&n_cand, __popcll(bal));
+                    base = __shfl(base, leader, 64);
+                    if (take) {
+                        const int pos = base + __popcll(bal & ((1ull << lane) - 1ull));
+                        S.key[pos] = k;
+                        S.idx[pos] = i;
+                    }
                 }
             }
             __syncthreads();
             nc = n_cand;
             in_lds = true;
         }
-        for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+        for (int i = threadIdx.x; i < kRadixCopies * 256; i += blockDim.x) hist[i] = 0;
         __syncthreads();
+        int* hc = hist + (lane & (kRadixCopies - 1)) * 256;
         if (in_lds) {
             for (int j = threadIdx.x; j < nc; j += blockDim.x) {
                 const unsigned long long k = S.key[j];
-                if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & 255], 1);
+                if ((k & mask) == prefix) atomicAdd(&hc[(k >> shift) & 255], 1);
             }
         } else {
             for (int i = threadIdx.x; i < n; i += blockDim.x) {
                 const unsigned long long k = ukey(i);
-                if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & 255], 1);
+                if ((k & mask) == prefix) atomicAdd(&hc[(k >> shift) & 255], 1);
             }
+        }
+        __syncthreads();
+        if (threadIdx.x < 256) {   // fold the copies into copy 0
+            int v = 0;
+#pragma unroll
+            for (int c = 0; c < kRadixCopies; ++c) v += hist[c * 256 + threadIdx.x];
+            hist[threadIdx.x] = v;
         }
         __syncthreads();
         if (threadIdx.x < 64) {

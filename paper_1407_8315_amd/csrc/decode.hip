@@ -1162,8 +1162,10 @@ __global__ __launch_bounds__(kBlock) void svd_rank_kernel(const SigDev* __restri
 // to the next round at their next order (or to the rank test, for a bin whose
 // learned order failed), and a bin with no order left is flagged: counted,
 // and in general mode queued for the CS step by its vote order.
+// (orders 1-2: held to three waves per SIMD, measured faster than two waves
+// without the order-1 kernel's few spilled registers)
 template <typename T, int A, int PHASE>
-__global__ __launch_bounds__(kBlock) void round_kernel(const SigDev* __restrict__ sigs, const int64_t* __restrict__ shifts,
+__global__ __launch_bounds__(kBlock, A <= 2 ? 3 : 2) void round_kernel(const SigDev* __restrict__ sigs, const int64_t* __restrict__ shifts,
                                                        const typename V2<T>::type* __restrict__ synd,
                                                        const SelDev* __restrict__ sel, const double2* __restrict__ tab,
                                                        SigCounters* __restrict__ cnt, int64_t* __restrict__ st_loc,

@@ -21,22 +21,6 @@ struct V2<double> {
     using type = double2;
 };
 
-// De-rotated syndromes of bin k: mt_l = e^{-i 2 pi (k l mod N) / N} m_l for the
-// lines [line0, line0 + cnt) whose shifts are sh[0..cnt).
-template <typename T, int MAXC>
-__device__ inline void load_derotated(const typename V2<T>::type* __restrict__ syn, int log2m, int64_t k,
-                                      int64_t n, const int64_t* sh, int cnt, zd* out) {
-#pragma unroll
-    for (int l = 0; l < MAXC; ++l) {
-        out[l] = zd{0.0, 0.0};
-        if (l < cnt) {
-            auto v = syn[((int64_t)l << log2m) + k];
-            zd w = unit_root((k * sh[l]) & (n - 1), n);
-            out[l] = cmul_conj(w, zd{(double)v.x, (double)v.y});
-        }
-    }
-}
-
 // Raw syndromes m_l[k] of the lines [0, cnt) (no de-rotation), FP64.
 template <typename T, int MAXC>
 __device__ __attribute__((always_inline)) inline void load_raw(const typename V2<T>::type* __restrict__ syn, int log2m, int64_t k, int cnt, zd* out) {
@@ -51,9 +35,9 @@ __device__ __attribute__((always_inline)) inline void load_raw(const typename V2
 }
 
 // The R random-shift syndromes of bin k, de-rotated on demand:
-// y_j = e^{-i 2 pi (k n_j mod N) / N} m_{n_j}[k] (the same arithmetic as
-// load_derotated, one line at a time, so a consumer can fold each y_j into
-// its sums without holding all R of them in registers).
+// y_j = e^{-i 2 pi (k n_j mod N) / N} m_{n_j}[k], one line at a time, so that
+// a consumer can fold each y_j into its sums without holding all R of them
+// in registers.
 template <typename T>
 struct RowSource {
     const typename V2<T>::type* __restrict__ syn;   // line 0 of the random-shift lines
@@ -79,14 +63,6 @@ __device__ __attribute__((always_inline)) inline void derotate_consecutive(zd* m
         if (l < cnt) m[l] = cmul_conj(w, m[l]);
         w = w * w1;
     }
-}
-
-// In place: m_l <- e^{-i 2 pi (k sh_l mod N) / N} m_l.
-template <int MAXC>
-__device__ __attribute__((always_inline)) inline void derotate(zd* m, int64_t k, int64_t n, const int64_t* sh, int cnt) {
-#pragma unroll
-    for (int l = 0; l < MAXC; ++l)
-        if (l < cnt) m[l] = cmul_conj(unit_root((k * sh[l]) & (n - 1), n), m[l]);
 }
 
 __device__ inline unsigned long long sv_key(double s) {

@@ -84,14 +84,16 @@ __global__ __launch_bounds__(kBlock) void singular_values_kernel(const SigDev* _
     if (sg.mode != kGeneral) return;
     const int64_t k = it.y + threadIdx.x;
     if (k >= sg.m) return;
-    zd mt[2 * kMaxL];
-    load_raw<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, 2 * sg.L, mt);
-    derotate_consecutive<2 * kMaxL>(mt, k, sg.n, 2 * sg.L);
+    // raw syndromes: de-rotation multiplies the Hankel matrix by the same
+    // unitary diagonal on both sides (e^{-i phi (i + j)} = e^{-i phi i}
+    // e^{-i phi j}), which changes neither its singular values nor E_k
+    zd m[2 * kMaxL];
+    load_raw<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, 2 * sg.L, m);
     double e = 0.0;
 #pragma unroll
-    for (int l = 0; l < 2 * kMaxL; ++l) e += norm2(mt[l]);   // zero beyond 2L
+    for (int l = 0; l < 2 * kMaxL; ++l) e += norm2(m[l]);   // zero beyond 2L
     double sv[kMaxL];
-    gram_singular_values(mt, sg.L, sv);
+    gram_singular_values(m, sg.L, sv);
 #pragma unroll
     for (int i = 0; i < kMaxL; ++i)
         if (i < sg.L) sigma[(sg.bin_off + k) * sg.L + i] = sv[i];

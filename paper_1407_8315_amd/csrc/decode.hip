@@ -570,14 +570,15 @@ __device__ __attribute__((always_inline)) inline int order_at(int a0, int L, int
 // b - G x, and its energy is ||y||^2 - Re(b_T^H x).
 
 // The candidates' Gram matrix, G_ie = F[(t_e - t_i) mod d] for any i, e (the
-// signal's Gram row table F; G_ei = conj(G_ie)).  Up to 4 candidates keep
+// signal's Gram row table F; G_ei = conj(G_ie)).  Up to 2 candidates keep
 // the packed lower triangle in registers (zero rows for unused slots); with
 // more, the triangle would take 2 KC (KC + 1) registers per lane, so each use
-// gathers its entry from the table (a few KB, cache resident).  Unused slots
-// then read finite values, always multiplied by zero coefficients or masked.
+// gathers its entry from the table (a few KB, cache resident; measured faster
+// for KC = 4 too, where it frees 20 registers).  Unused slots then read finite
+// values, always multiplied by zero coefficients or masked.
 template <int KC>
 struct CandGram {
-    static constexpr bool kRegs = KC <= 4;
+    static constexpr bool kRegs = KC <= 2;
     zd g[kRegs ? KC * (KC + 1) / 2 : 1];
     int64_t t[KC];
     const double2* f;

@@ -561,7 +561,7 @@ __device__ __attribute__((always_inline)) inline int order_at(int a0, int L, int
     return (step <= L - a0) ? a0 + step : a0 - (step - (L - a0));
 }
 
-// Subspace Pursuit works on sets of at most kMaxCand candidate columns,
+// Subspace Pursuit works on sets of at most KC = 2 a0 candidate columns,
 // represented as bit masks so that every register array is indexed by
 // unrolled constants.  Columns: Phi_{j,c} = w_d^{(t_c n_j) mod d}.  Every
 // quantity SP needs follows from the candidates' Gram matrix

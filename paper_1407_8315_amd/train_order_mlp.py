@@ -8,8 +8,7 @@ Training uses the library's own forward/backward and Adam kernels.
 
     python -m paper_1407_8315_amd.train_order_mlp --out weights.npy --report report.json
 
-Evaluation: held-out signals per SNR; accuracy of the predictor, and of the
-rank test (numerical rank of the 4 x 4 Hankel matrix) on exact signals.
+Evaluation: held-out signals per SNR, accuracy of the predictor.
 """
 from __future__ import annotations
 
@@ -95,22 +94,6 @@ def main():
         acc = float((pred == y_te.long()).float().mean().item())
         report["accuracy"]["exact" if snr is None else f"{snr}dB"] = round(acc, 5)
         print(f"held-out {snr} dB accuracy {acc:.4f} over {x_te.shape[0]} bins", flush=True)
-    # rank-test accuracy on exact held-out signals (oracle's FP64 singular values)
-    import oracle
-
-    n, k, m = 1 << 20, 1000, 4096
-    hit = tot = 0
-    for i in range(4):
-        s = sftgen.make_signal(n, k, sftgen.BASE_SEED + 900000 + 10 * i, amp="gauss", dtype=np.complex64)
-        ms = oracle.syndromes(s.x, n, m, range(8))
-        e = np.sum(np.abs(ms) ** 2, axis=0)
-        counts = np.bincount(s.locs % m, minlength=m)
-        for kk in np.nonzero(e > 1e-8 * e.mean())[0]:
-            a0 = oracle.rank_order(oracle.hankel_singular_values(ms[:, kk], 4), 1e-5)
-            hit += a0 == min(counts[kk], 4)
-            tot += 1
-    report["rank_test_accuracy_exact"] = round(hit / tot, 5)
-    print(f"rank test accuracy on exact held-out bins {hit / tot:.4f}", flush=True)
     net.save(a.out)
     if a.report:
         with open(a.report, "w") as f:

@@ -86,12 +86,19 @@ def forward(theta, x, bf16=False):
     return z3, (x, z1, h1, z2, h2)
 
 
-def loss_and_grad(theta, x, labels, bf16=False):
+def loss_and_grad(theta, x, labels, bf16=False, bf16_backward=False):
     """Mean cross-entropy and its gradient with respect to the flat parameters
-    (bf16 as in forward: the gradient of the rounded network)."""
+    (bf16 as in forward: the gradient of the rounded network).
+
+    bf16_backward=True also rounds the backward deltas where the device's
+    MFMA products take them in bfloat16: dZ3 for dH2 = dZ3 W3 and
+    dW3 = dZ3^T H2 (b3 keeps the unrounded dZ3), and dZ2 = dH2 * gelu'(Z2),
+    dZ1 = dH1 * gelu'(Z1) for every later use (the weight gradients, the
+    bias sums and the next backward product)."""
     p = unpack(theta)
     if bf16:
         p = dict(p, W1=bf16_round(p["W1"]), W2=bf16_round(p["W2"]), W3=bf16_round(p["W3"]))
+    rb = bf16_round if bf16_backward else (lambda v: v)
     z3, (x, z1, h1, z2, h2) = forward(theta, x, bf16)
     n = len(labels)
     zmax = z3.max(axis=1, keepdims=True)
@@ -102,13 +109,14 @@ def loss_and_grad(theta, x, labels, bf16=False):
     dz3 = prob.copy()
     dz3[np.arange(n), labels] -= 1.0
     dz3 /= n
-    g = {"W3": dz3.T @ h2, "b3": dz3.sum(0)}
-    dh2 = dz3 @ p["W3"]
-    dz2 = dh2 * gelu_grad(z2)
+    dz3r = rb(dz3)
+    g = {"W3": dz3r.T @ h2, "b3": dz3.sum(0)}
+    dh2 = dz3r @ p["W3"]
+    dz2 = rb(dh2 * gelu_grad(z2))
     g["W2"] = dz2.T @ h1
     g["b2"] = dz2.sum(0)
     dh1 = dz2 @ p["W2"]
-    dz1 = dh1 * gelu_grad(z1)
+    dz1 = rb(dh1 * gelu_grad(z1))
     g["W1"] = dz1.T @ x
     g["b1"] = dz1.sum(0)
     return loss, pack(g)

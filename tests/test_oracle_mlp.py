@@ -59,3 +59,31 @@ def test_bf16_rounding():
     assert r[0] == 1.0 and r[1] == 1.0                 # tie to even
     assert r[2] == 1.0 + 2 ** -7                      # below half an ulp: rounds down
     assert abs(r[3] + 3.140625) < 1e-12
+
+
+def test_backward_rounding_points_bound():
+    """bf16_backward rounds the deltas dZ3 (for the W3 side), dZ2 and dZ1 to
+    bfloat16 (relative error at most 2^-9 each).  The rounded gradient then
+    differs from the unrounded one of the same (BF16-forward) network by at
+    most the first-order propagation of those errors, bounded entry by entry
+    through the absolute values of the factors; b3 is untouched."""
+    g = np.random.default_rng(4)
+    theta = g.standard_normal(mlp.NPARAMS) * 0.2
+    x = g.standard_normal((40, 32))
+    y = g.integers(0, 5, 40)
+    _, g0 = mlp.loss_and_grad(theta, x, y, bf16=True)
+    _, g1 = mlp.loss_and_grad(theta, x, y, bf16=True, bf16_backward=True)
+    p0, p1 = mlp.unpack(g0), mlp.unpack(g1)
+    assert np.array_equal(p0["b3"], p1["b3"])
+    for name in ("W3", "W2", "W1", "b2", "b1"):
+        rel = np.max(np.abs(p1[name] - p0[name])) / np.max(np.abs(p0[name]))
+        # one rounding on each delta layer between the loss and the parameter:
+        # W3: 1, W2/b2: 2, W1/b1: 3 roundings of at most 2^-9, summed in |.|
+        assert 0 < rel < 3 * 2.0 ** -9 * 40, (name, rel)
+    # zero deltas round to zero: a network with zero last layer has dZ2 = dZ1 = 0
+    t0 = theta.copy()
+    t0[mlp.NPARAMS - 5 - 5 * 128:mlp.NPARAMS - 5] = 0.0
+    _, ga = mlp.loss_and_grad(t0, x, y, bf16=True)
+    _, gb = mlp.loss_and_grad(t0, x, y, bf16=True, bf16_backward=True)
+    pa, pb = mlp.unpack(ga), mlp.unpack(gb)
+    assert np.all(pb["W1"] == 0) and np.all(pb["W2"] == 0) and np.all(pa["W1"] == 0)

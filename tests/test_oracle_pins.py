@@ -412,3 +412,29 @@ def test_lemma2_bound_holds_empirically():
         s = sftgen.make_signal(n, k, 500 + seed, dtype=np.complex128)
         hits += oracle.sfft_exact(s.x, n, m, L).flagged_bins > 0
     assert hits / trials <= bound
+
+
+@pytest.mark.parametrize("k_votes", [5, 6, 8])
+def test_cs_on_a_singular_locator_keeps_no_column(k_votes):
+    """Pruning Step 2(a) needs the inverse of the order-a0 Hankel matrix and
+    Step 3 keeps exactly the columns whose roots are in Z~; when the matrix
+    is singular there is no P~, Z~ is empty and Phi_p has no column, so the
+    bin contributes nothing.  Constructed case: one tone at location 0 makes
+    every line constant, so its transform is exactly zero outside bin 0; the
+    vote gives bin 0 all L orders (its sigma_1 is the largest value and its
+    other sigmas lead the zero ties by bin) and bin 1 the remaining
+    k_votes - L.  Bin 1 has zero syndromes: every order's locator is singular,
+    the decoder flags it, and the CS step finds its order-a0 matrix singular
+    as well.  Pinned: the output is the tone alone, both bins counted active,
+    bin 1 flagged, no CS recovery."""
+    n, m, L = 1024, 16, 4
+    x = sftgen.make_signal(n, 1, 0, locs=np.array([0]), vals=np.array([1.0 + 0.5j]), dtype=np.complex128).x
+    msyn = osf.syndromes(x, n, m, range(2 * L))
+    assert np.count_nonzero(np.abs(msyn[:, 1:])) == 0
+    sv = np.array([osf.hankel_singular_values(msyn[:, k], L) for k in range(m)])
+    a0 = osf.vote(sv, k_votes)
+    assert a0[0] == L and a0[1] == k_votes - L and a0[2:].sum() == 0
+    assert osf.locator(msyn[:, 1], k_votes - L) is None
+    r = oracle.sfft_general(x, n, k_votes, m, L, rshifts=[3, 17, 40, 51, 60, 62])
+    assert r.locs.tolist() == [0] and np.allclose(r.vals, [1.0 + 0.5j], atol=1e-12)
+    assert (r.active_bins, r.flagged_bins, r.cs_bins) == (2, 1, 0)

@@ -37,7 +37,8 @@
  * synchronises the stream and makes status codes such as SFT_E_CAPACITY
  * observable.  A plan is not thread-safe: use one plan per stream.
  * No call allocates device memory except sft_plan, sft_mlp_create and the
- * first sft_batch call of a plan (graph instantiation).
+ * first sft_batch call of a plan (graph instantiation); sft_exact_noalloc
+ * needs no plan and allocates nothing.
  *
  * Errors: every call returns a status; no exception crosses the ABI;
  * sft_last_error() gives the text of the last failure on the calling thread.
@@ -273,6 +274,30 @@ sft_status sft_features(sft_plan_t plan, const void* x_dev, float* feat_dev, int
  * 1..n, in_dtype not SFT_C64/SFT_C128 or target outside [0, 1). */
 sft_status sft_autotune(int64_t n, int64_t k, int32_t in_dtype, double target, int64_t* m_out, int32_t* l_out,
                         double* expected_recovery, double* model_us);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): sft_exact
+ * for one signal without a plan.  params as for sft_plan (SFT_MODE_EXACT;
+ * SFT_FLAG_FFT64 and SFT_FLAG_AUTOTUNE allowed; LEARNED, SYNC, CHECK_FINITE and
+ * UNKNOWN_K refused with SFT_E_UNSUPPORTED); x_dev, out as for sft_exact;
+ * hip_stream: a hipStream_t of the current device (NULL = default stream).
+ *
+ * The workspace is one static device array of about 4.5 MiB that the library
+ * holds on every GPU it runs on until the process ends.  Limits: M at most
+ * 8192 with FP32 FFTs (complex64 input) or 4096 with FP64 FFTs (complex128
+ * input or SFT_FLAG_FFT64), d = N/M at most 2^16; larger problems return
+ * SFT_E_UNSUPPORTED with the limit in sft_last_error().  The call issues
+ * kernels only (no allocation, free, memset or copy), asynchronously: no
+ * stats, and no SFT_E_CAPACITY (count_dev receives the number of entries
+ * found; only `capacity` of them are written).  The first call on a device
+ * also enqueues the fill of the twiddle and unit-root tables (and so does
+ * every call under stream capture until an eager call has).  All calls on a
+ * GPU share its array: the caller orders them (one stream, or
+ * synchronisation between streams); calls that overlap race.  The output
+ * equals sft_exact's for the same parameters and input (same kernels and
+ * decisions; the tables are computed on the device, so values may differ in
+ * the last bits). */
+sft_status sft_exact_noalloc(const sft_params* params, const void* x_dev, const sft_sparse_out* out, void* hip_stream);
 
 /* Parameters the plan chose for signal `index` (0-based). */
 sft_status sft_plan_get(sft_plan_t plan, int64_t index, sft_plan_info* info);

@@ -20,7 +20,7 @@ from ._lib import (  # noqa: F401
     SftError,
 )
 
-__all__ = ["Plan", "Result", "SftError", "Mlp", "make_params", "library_path", "autotune"]
+__all__ = ["Plan", "Result", "SftError", "Mlp", "make_params", "library_path", "autotune", "exact_noalloc"]
 
 
 def library_path() -> str:
@@ -37,6 +37,28 @@ def autotune(n, k, dtype="c64", target=0.0):
                                 ctypes.byref(m), ctypes.byref(l), ctypes.byref(rec), ctypes.byref(us)),
                "sft_autotune")
     return int(m.value), int(l.value), float(rec.value), float(us.value)
+
+
+def exact_noalloc(x, params: dict, out: "Result", capacity=None, stream=None) -> "Result":
+    """sft_exact_noalloc: exact-mode recovery of one signal without a plan
+    (the library's static workspace; no device allocation by the library).
+    x: contiguous CUDA tensor of params["n"] elements of params' dtype; out: a
+    Result the caller allocated (Plan.new_output or equal tensors).
+    Asynchronous on `stream` (default: torch's current stream)."""
+    torch = _torch()
+    lib = _lib.load()
+    p = make_params(**params)
+    want = torch.complex128 if p.in_dtype == SFT_C128 else torch.complex64
+    if not x.is_cuda or x.dtype != want or x.numel() != p.n or not x.is_contiguous():
+        raise ValueError(f"need a contiguous {want} CUDA tensor of {p.n} elements")
+    if capacity is None:
+        capacity = out.loc.numel()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    o = Plan._out_struct(out, capacity)
+    _lib.check(lib.sft_exact_noalloc(ctypes.byref(p), ctypes.c_void_p(x.data_ptr()), ctypes.byref(o),
+                                     ctypes.c_void_p(stream.cuda_stream)), "sft_exact_noalloc")
+    return out
 
 
 def make_params(n, k, m=0, l=0, r=0, dtype="c64", mode="exact", flags=0, seed=0, target_recovery=0.0,

@@ -21,7 +21,7 @@ EXPORTS = [
     "sft_status_str", "sft_last_error", "sft_abi_version",
     "sft_mlp_create", "sft_mlp_destroy", "sft_mlp_get_params", "sft_mlp_set_params", "sft_mlp_forward",
     "sft_mlp_grad", "sft_mlp_train_step", "sft_mlp_last_error", "sft_plan_attach_mlp", "sft_features",
-    "sft_autotune", "sft_unknown_k",
+    "sft_autotune", "sft_unknown_k", "sft_exact_noalloc",
 ]
 MLP_FEATURES, MLP_CLASSES, MLP_PARAMS = 32, 5, 21381
 
@@ -90,6 +90,8 @@ def load():
         f.restype = st
     lib.sft_unknown_k.argtypes = [vp, vp, ctypes.POINTER(SparseOut), ctypes.POINTER(Stats), ctypes.POINTER(i64)]
     lib.sft_unknown_k.restype = st
+    lib.sft_exact_noalloc.argtypes = [ctypes.POINTER(Params), vp, ctypes.POINTER(SparseOut), vp]
+    lib.sft_exact_noalloc.restype = st
     lib.sft_batch.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(SparseOut), ctypes.POINTER(Stats)]
     lib.sft_batch.restype = st
     lib.sft_syndromes.argtypes = [vp, vp, vp]

@@ -25,7 +25,7 @@ FLAGS = [
     "-Wall", "-Wno-unused-result", "-Wno-unused-function",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
-SOURCES = ["api.cpp", "plan.cpp", "fft.hip", "decode.hip", "iterative.hip", "mlp.hip"]
+SOURCES = ["api.cpp", "plan.cpp", "fft.hip", "decode.hip", "iterative.hip", "mlp.hip", "noalloc.hip"]
 
 
 def _compile(src: str) -> str:

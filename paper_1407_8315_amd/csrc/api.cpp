@@ -214,28 +214,94 @@ bool learned(const sft_plan_s* p) {
     return false;
 }
 
+}  // namespace
+
+namespace sft {
+
+sft_status set_error(sft_status s, const std::string& msg) { return fail(s, msg); }
+
 // Run fn(ctx, i) for i = 1..n as parallel branches after everything already
-// enqueued on the plan's stream: branch 1 on the plan's stream itself,
-// branch i > 1 on side stream i-2 (a process has few hardware queues, so the
-// plan's stream carries one branch); the plan's stream then waits for all.
+// enqueued on c.stream: branch 1 on c.stream itself, branch i > 1 on side
+// stream i-2 (a process has few hardware queues, so the main stream carries
+// one branch); c.stream then waits for all.  Without br, in series.
 template <typename Fn>
-sft_status branches(const sft_plan_s* p, const LaunchCtx& c, int n, Fn fn) {
-    if (n <= 1) {
-        if (n == 1) HIPCHK(fn(c, 1));
+static sft_status branches(const Branching* br, const LaunchCtx& c, int n, Fn fn) {
+    if (n <= 1 || !br) {
+        for (int i = 1; i <= n; ++i) HIPCHK(fn(c, i));
         return SFT_OK;
     }
-    HIPCHK(hipEventRecord(p->ev_fork, p->stream));
+    HIPCHK(hipEventRecord(br->fork, c.stream));
     for (int i = 1; i < n; ++i) {
-        HIPCHK(hipStreamWaitEvent(p->side[i - 1], p->ev_fork, 0));
+        HIPCHK(hipStreamWaitEvent(br->side[i - 1], br->fork, 0));
         LaunchCtx ci = c;
-        ci.stream = p->side[i - 1];
+        ci.stream = br->side[i - 1];
         HIPCHK(fn(ci, i + 1));
-        HIPCHK(hipEventRecord(p->ev_join[i - 1], p->side[i - 1]));
+        HIPCHK(hipEventRecord(br->join[i - 1], br->side[i - 1]));
     }
     HIPCHK(fn(c, 1));
-    for (int i = 1; i < n; ++i) HIPCHK(hipStreamWaitEvent(p->stream, p->ev_join[i - 1], 0));
+    for (int i = 1; i < n; ++i) HIPCHK(hipStreamWaitEvent(c.stream, br->join[i - 1], 0));
     return SFT_OK;
 }
+
+sft_status enqueue_path(const LaunchCtx& c, const Branching* br, sft_mlp_t mlp, hipEvent_t* events) {
+    const bool use_mlp = mlp != nullptr;
+    const bool any_exact = c.n_general < c.n_sigs;
+    if (events) HIPCHK(hipEventRecord(events[0], c.stream));
+    HIPCHK(launch_zero_counters(c));
+    HIPCHK(launch_syndromes(c));
+    if (events) HIPCHK(hipEventRecord(events[1], c.stream));
+    HIPCHK(launch_singular_values(c));
+    HIPCHK(launch_select(c));
+    HIPCHK(launch_activity(c));
+    // Round-0 queues: general-mode bins come from the vote (activity pass).
+    // Exact-mode bins go through the rank test: the certificate pass settles
+    // the rank-one bins (and tries order 1 on them at once); the pending ones
+    // get the SVD pass, or in a learned plan the predictor, with the SVD pass
+    // for the bins it gives no order.
+    if (any_exact) {
+        HIPCHK(launch_certify(c));
+        if (use_mlp) {
+            sft_status s = sft_mlp_launch_infer(mlp, c);
+            if (s != SFT_OK) return s;
+            HIPCHK(launch_svd_rank(c, q_round(0, 0), 0));
+        } else {
+            HIPCHK(launch_svd_rank(c, kQPending, 0));
+        }
+    }
+    if (events) HIPCHK(hipEventRecord(events[2], c.stream));
+    for (int r = 0; r < c.max_l; ++r) {
+        if (r >= 1) HIPCHK(launch_zero_set(c, (r + 1) & 1));
+        // the orders of a round read their own queues: parallel branches
+        const int n_orders = (r == 0 && !c.any_general) ? std::min(c.max_l, 2) : c.max_l;
+        sft_status bs = branches(br, c, n_orders, [&](const LaunchCtx& ci, int a) { return launch_round(ci, r, a); });
+        if (bs != SFT_OK) return bs;
+        // bins whose learned order failed: rank test, then on with round 1
+        if (r == 0 && use_mlp && c.max_l > 1) HIPCHK(launch_svd_rank(c, q_round(1, 0), 1));
+        // without general-mode signals, the few bins left after round 0 of orders 1
+        // and 2 finish in one kernel
+        if (r == 0 && c.n_general == 0 && c.max_l > 1) {
+            HIPCHK(launch_rest(c));
+            break;
+        }
+    }
+    if (c.any_general) {
+        // one branch per order: order 1 on the main stream, then the rare
+        // orders 3 and 4, then order 2 (with four hardware queues per process,
+        // the runtime can run two branches on one queue, in series; measured,
+        // the first two side branches share one, so they carry the cheap pair)
+        static constexpr int kCsOrder[kMaxL] = {1, 3, 4, 2};
+        sft_status bs = branches(br, c, kMaxL, [&](const LaunchCtx& ci, int b) { return launch_cs(ci, kCsOrder[b - 1]); });
+        if (bs != SFT_OK) return bs;
+    }
+    if (events) HIPCHK(hipEventRecord(events[3], c.stream));
+    HIPCHK(launch_output(c));
+    if (events) HIPCHK(hipEventRecord(events[4], c.stream));
+    return SFT_OK;
+}
+
+}  // namespace sft
+
+namespace {
 
 // Enqueue the whole path.  With events != nullptr, record stage boundaries.
 // Learned plans run the predictor between the activity pass and the decoder.
@@ -257,59 +323,13 @@ sft_status enqueue(const sft_plan_s* p, hipEvent_t* events) {
         if (events) HIPCHK(hipEventRecord(events[4], p->stream));
         return SFT_OK;
     }
-    const bool use_mlp = learned(p) && p->mlp;
-    const bool any_exact = p->n_general < (int)p->sig.size();
-    if (events) HIPCHK(hipEventRecord(events[0], p->stream));
-    HIPCHK(launch_zero_counters(c));
-    HIPCHK(launch_syndromes(c));
-    if (events) HIPCHK(hipEventRecord(events[1], p->stream));
-    HIPCHK(launch_singular_values(c));
-    HIPCHK(launch_select(c));
-    HIPCHK(launch_activity(c));
-    // Round-0 queues: general-mode bins come from the vote (activity pass).
-    // Exact-mode bins go through the rank test: the certificate pass settles
-    // the rank-one bins (and tries order 1 on them at once); the pending ones
-    // get the SVD pass, or in a learned plan the predictor, with the SVD pass
-    // for the bins it gives no order.
-    if (any_exact) {
-        HIPCHK(launch_certify(c));
-        if (use_mlp) {
-            sft_status s = sft_mlp_launch_infer(p->mlp, c);
-            if (s != SFT_OK) return s;
-            HIPCHK(launch_svd_rank(c, q_round(0, 0), 0));
-        } else {
-            HIPCHK(launch_svd_rank(c, kQPending, 0));
-        }
+    Branching br{};
+    for (int i = 0; i < kMaxL - 1; ++i) {
+        br.side[i] = p->side[i];
+        br.join[i] = p->ev_join[i];
     }
-    if (events) HIPCHK(hipEventRecord(events[2], p->stream));
-    for (int r = 0; r < p->max_l; ++r) {
-        if (r >= 1) HIPCHK(launch_zero_set(c, (r + 1) & 1));
-        // the orders of a round read their own queues: parallel branches
-        const int n_orders = (r == 0 && !p->any_general) ? std::min(p->max_l, 2) : p->max_l;
-        sft_status bs = branches(p, c, n_orders, [&](const LaunchCtx& ci, int a) { return launch_round(ci, r, a); });
-        if (bs != SFT_OK) return bs;
-        // bins whose learned order failed: rank test, then on with round 1
-        if (r == 0 && use_mlp && p->max_l > 1) HIPCHK(launch_svd_rank(c, q_round(1, 0), 1));
-        // without general-mode signals, the few bins left after round 0 of orders 1
-        // and 2 finish in one kernel
-        if (r == 0 && p->n_general == 0 && p->max_l > 1) {
-            HIPCHK(launch_rest(c));
-            break;
-        }
-    }
-    if (p->any_general) {
-        // one branch per order: order 1 on the plan's stream, then the rare
-        // orders 3 and 4, then order 2 (with four hardware queues per process,
-        // the runtime can run two branches on one queue, in series; measured,
-        // the first two side branches share one, so they carry the cheap pair)
-        static constexpr int kCsOrder[kMaxL] = {1, 3, 4, 2};
-        sft_status bs = branches(p, c, kMaxL, [&](const LaunchCtx& ci, int b) { return launch_cs(ci, kCsOrder[b - 1]); });
-        if (bs != SFT_OK) return bs;
-    }
-    if (events) HIPCHK(hipEventRecord(events[3], p->stream));
-    HIPCHK(launch_output(c));
-    if (events) HIPCHK(hipEventRecord(events[4], p->stream));
-    return SFT_OK;
+    br.fork = p->ev_fork;
+    return enqueue_path(c, &br, learned(p) ? p->mlp : nullptr, events);
 }
 
 sft_status upload_io(sft_plan_s* p, const void* const* xs, const sft_sparse_out* outs) {

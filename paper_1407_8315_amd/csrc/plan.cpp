@@ -281,6 +281,41 @@ sft_status resolve_params(const sft_params& in, bool batch, SigHost* g, std::str
     return SFT_OK;
 }
 
+SigDev sigdev_of(const SigHost& g, int64_t dmax, bool fp64) {
+    const int64_t pmax = fp64 ? kFftPointsF64 : kFftPointsF32;
+    SigDev s;
+    std::memset(&s, 0, sizeof(s));
+    s.n = g.n;
+    s.d = g.d;
+    s.m = (int32_t)g.m;
+    s.log2m = ilog2(g.m);
+    s.L = g.L;
+    s.R = g.R;
+    s.S = g.S;
+    s.mode = g.mode;
+    s.k_votes = (int32_t)std::min<int64_t>(g.k, INT32_MAX);
+    s.flags = (int32_t)g.flags;
+    s.stage_cap = (int32_t)(g.m * g.L);
+    s.tab_stride = (int32_t)(dmax / g.d);
+    s.log2m1 = g.m > pmax ? (ilog2(g.m) + 1) / 2 : 0;   // M1 = 2^ceil(log2 M / 2)
+    s.view0 = -1;
+    s.tau_zero2 = g.tau_zero * g.tau_zero;
+    s.tau_rank = g.tau_rank;
+    s.tau_res2 = g.tau_res * g.tau_res;
+    s.tau_amp = g.tau_amp;
+    s.c_res = g.c_res;
+    s.delta_grid = g.delta_grid;
+    s.delta_mag = g.delta_mag;
+    return s;
+}
+
+int fft_lines_per_block(int64_t m, int lines, bool fp64, bool* small) {
+    const bool sm = !fp64 && m <= kFftPointsF32Small;
+    if (small) *small = sm;
+    const int64_t pts = sm ? kFftPointsF32Small : (fp64 ? kFftPointsF64 : kFftPointsF32);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(lines, pts / m));
+}
+
 void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) {
     const int64_t pmax = fp64 ? kFftPointsF64 : kFftPointsF32;
     int64_t mmax = 1, dmax = 1;
@@ -343,43 +378,22 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
     for (size_t i = 0; i < sigs.size(); ++i) {
         const SigHost& g = sigs[i];
         SigDev& s = lay->sigdev[i];
-        std::memset(&s, 0, sizeof(s));
-        s.n = g.n;
-        s.d = g.d;
-        s.m = (int32_t)g.m;
-        s.log2m = ilog2(g.m);
-        s.L = g.L;
-        s.R = g.R;
-        s.S = g.S;
-        s.mode = g.mode;
-        s.k_votes = (int32_t)std::min<int64_t>(g.k, INT32_MAX);
-        s.flags = (int32_t)g.flags;
+        s = sigdev_of(g, dmax, fp64);
         s.synd_off = synd;
         s.epart_off = ep;
         s.bin_off = bins;
         s.stage_off = stage;
-        s.stage_cap = (int32_t)(g.m * g.L);
         s.shift_off = (int32_t)lay->shifts.size();
-        s.tab_stride = (int32_t)(dmax / g.d);
-        s.log2m1 = g.m > pmax ? (ilog2(g.m) + 1) / 2 : 0;   // M1 = 2^ceil(log2 M / 2)
         s.y_off = ybuf;
         const bool iter = g.mode == SFT_MODE_ITERATIVE;
         if (g.m > pmax && !iter) ybuf += (int64_t)g.S * g.m;
         s.parent = (int32_t)i;
-        s.view0 = -1;
         if (iter) {
             s.it_st_off = it_st;
             s.it_rec_off = it_rec;
             it_st += iter_bins_off(g.m, g.L);
             it_rec += iter_rec_off(g.m, g.L);
         }
-        s.tau_zero2 = g.tau_zero * g.tau_zero;
-        s.tau_rank = g.tau_rank;
-        s.tau_res2 = g.tau_res * g.tau_res;
-        s.tau_amp = g.tau_amp;
-        s.c_res = g.c_res;
-        s.delta_grid = g.delta_grid;
-        s.delta_mag = g.delta_mag;
         for (int l = 0; l < 2 * g.L; ++l) lay->shifts.push_back(l);
         for (int64_t v : g.rshifts) lay->shifts.push_back(v);
         synd += (int64_t)g.S * g.m;
@@ -473,7 +487,7 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
             for_units(s, [&](int idx, int64_t m, int S, int lm1) {
                 (void)lm1;
                 if (!small(m)) return;
-                const int nl = (int)std::max<int64_t>(1, std::min<int64_t>(S, kFftPointsF32Small / m));
+                const int nl = fft_lines_per_block(m, S, fp64, nullptr);
                 for (int l0 = 0; l0 < S; l0 += nl) v.push_back(int4{idx, l0, std::min(nl, S - l0), 0});
             });
         },
@@ -483,7 +497,7 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
             for_units(s, [&](int idx, int64_t m, int S, int lm1) {
                 if (small(m)) return;
                 if (m <= pmax) {
-                    int nl = (int)std::max<int64_t>(1, std::min<int64_t>(S, pmax / m));
+                    const int nl = fft_lines_per_block(m, S, fp64, nullptr);
                     for (int l0 = 0; l0 < S; l0 += nl) v.push_back(int4{idx, l0, std::min(nl, S - l0), 0});
                 } else {
                     // first of two passes: S * M1 lines of length M2

@@ -63,6 +63,33 @@ std::vector<int64_t> draw_shifts(uint64_t seed, int64_t d, int r);
 
 void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay);
 
+// The device description of one signal with every buffer offset 0 (a plan's
+// layout then places it); dmax: size of the omega table the plan uses.
+SigDev sigdev_of(const SigHost& g, int64_t dmax, bool fp64);
+
+// Lines per block of the one-pass FFT of a unit of `lines` lines of M points;
+// *small (nullable): the unit goes to the FP32 kernel of kFftPointsF32Small
+// points per block.
+int fft_lines_per_block(int64_t m, int lines, bool fp64, bool* small);
+
+// Side streams and events that run the independent kernels of one stage (the
+// orders of a round, the CS orders) as parallel branches.
+struct Branching {
+    hipStream_t side[kMaxL - 1];
+    hipEvent_t fork;
+    hipEvent_t join[kMaxL - 1];
+};
+
+// Enqueue the non-iterative path (exact and general signals) described by c on
+// c.stream: syndromes, order estimate or vote, decoding rounds, CS step,
+// output.  br == nullptr runs the branches of a stage in series on c.stream;
+// mlp != nullptr gives the exact-mode signals the learned order first; events
+// (5, nullable) mark the stage boundaries.
+sft_status enqueue_path(const LaunchCtx& c, const Branching* br, sft_mlp_t mlp, hipEvent_t* events);
+
+// Record the text of a failure for sft_last_error(); returns s.
+sft_status set_error(sft_status s, const std::string& msg);
+
 void twiddle_table_f32(int log2n, std::vector<float2>* out);    // e^{-2 pi i q / 2^log2n}
 void twiddle_table_f64(int log2n, std::vector<double2>* out);
 void omega_table(int log2n, std::vector<double2>* out);         // e^{+2 pi i q / 2^log2n}

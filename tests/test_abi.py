@@ -147,3 +147,25 @@ def test_null_arguments(lib):
     assert lib.sft_batch(None, None, None, None) == _lib.SFT_E_INVALID
     assert lib.sft_plan_get(None, 0, None) == _lib.SFT_E_INVALID
     lib.sft_destroy(None)
+
+
+@pytest.mark.parametrize("kw,flags,status,text", [
+    (dict(n=1 << 20, k=1000, m=16384, l=4), 0, 2, "limit 8192"),
+    (dict(n=1 << 20, k=1000, m=8192, l=4, dtype="c128"), 0, 2, "limit 4096"),
+    (dict(n=1 << 30, k=1000, m=8192, l=4), 0, 2, "limit 65536"),
+    (dict(n=1 << 20, k=1000, m=4096, l=4), 1, 2, "not available"),     # SFT_FLAG_LEARNED
+    (dict(n=1 << 20, k=1000, m=4096, l=4), 2, 2, "not available"),     # SFT_FLAG_SYNC
+    (dict(n=1 << 20, k=1000, m=4096, l=4, mode="general"), 0, 1, "SFT_MODE_EXACT"),
+    (dict(n=1000, k=10, m=8, l=4), 0, 2, "power of two"),
+])
+def test_noalloc_rejects_before_any_device_call(lib, kw, flags, status, text):
+    """sft_exact_noalloc validates on the host and refuses sizes beyond its
+    static workspace with the limit in the error text (no GPU is touched)."""
+    from paper_1407_8315_amd import _lib, make_params
+
+    p = make_params(flags=flags, **kw)
+    o = _lib.SparseOut()
+    o.loc_dev, o.val_dev, o.capacity, o.count_dev = 8, 8, 1, 8   # never dereferenced
+    st = lib.sft_exact_noalloc(ctypes.byref(p), ctypes.c_void_p(8), ctypes.byref(o), None)
+    assert st == status
+    assert text in lib.sft_last_error().decode()

@@ -65,6 +65,9 @@ struct sft_plan_s {
     int4* d_synd_small_items = nullptr;
     int n_synd_small_items = 0;
     int4* d_synd2_items = nullptr;
+    int4* d_pair_items = nullptr;
+    int pair_off[kPairGroups] = {};
+    int pair_n[kPairGroups] = {};
     int2* d_line_items = nullptr;
     void* d_ybuf = nullptr;
     int n_synd2_items = 0, n_line_items = 0;
@@ -172,6 +175,11 @@ LaunchCtx make_ctx(const sft_plan_s* p) {
     c.n_synd_items = p->n_synd_items;
     c.synd_small_items = p->d_synd_small_items;
     c.n_synd_small_items = p->n_synd_small_items;
+    c.pair_items = p->d_pair_items;
+    for (int g = 0; g < kPairGroups; ++g) {
+        c.pair_off[g] = p->pair_off[g];
+        c.pair_n[g] = p->pair_n[g];
+    }
     c.synd2_items = p->d_synd2_items;
     c.n_synd2_items = p->n_synd2_items;
     c.ybuf = p->d_ybuf;
@@ -248,7 +256,14 @@ sft_status enqueue_path(const LaunchCtx& c, const Branching* br, sft_mlp_t mlp, 
     const bool any_exact = c.n_general < c.n_sigs;
     if (events) HIPCHK(hipEventRecord(events[0], c.stream));
     HIPCHK(launch_zero_counters(c));
-    HIPCHK(launch_syndromes(c));
+    // the consecutive-shift lines (pair kernels) beside the rest (general
+    // mode's random shifts): parallel branches
+    if (syndrome_parts_split(c)) {
+        sft_status bs = branches(br, c, 2, [&](const LaunchCtx& ci, int b) { return launch_syndromes(ci, b); });
+        if (bs != SFT_OK) return bs;
+    } else {
+        HIPCHK(launch_syndromes(c));
+    }
     if (events) HIPCHK(hipEventRecord(events[1], c.stream));
     HIPCHK(launch_singular_values(c));
     HIPCHK(launch_select(c));
@@ -485,6 +500,10 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     p->n_synd_items = (int)lay.synd_items.size();
     p->n_synd_small_items = (int)lay.synd_small_items.size();
     p->n_synd2_items = (int)lay.synd2_items.size();
+    for (int g = 0; g < kPairGroups; ++g) {
+        p->pair_off[g] = lay.pair_off[g];
+        p->pair_n[g] = lay.pair_n[g];
+    }
     p->n_line_items = (int)lay.line_items.size();
     p->n_bin_items = (int)lay.bin_items.size();
     p->n_act_items = (int)lay.act_items.size();
@@ -545,6 +564,7 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     TRY(dalloc(p, &p->d_synd_items, lay.synd_items.size()));
     TRY(dalloc(p, &p->d_synd_small_items, lay.synd_small_items.size()));
     TRY(dalloc(p, &p->d_synd2_items, lay.synd2_items.size()));
+    TRY(dalloc(p, &p->d_pair_items, lay.pair_items.size()));
     TRY(dalloc(p, &p->d_line_items, lay.line_items.size()));
     TRY(dalloc(p, &p->d_bin_items, lay.bin_items.size()));
     TRY(dalloc(p, &p->d_act_items, lay.act_items.size()));
@@ -594,6 +614,9 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
         HIPTRY(hipMemcpy(p->d_synd_items, lay.synd_items.data(), lay.synd_items.size() * sizeof(int4), hipMemcpyHostToDevice));
     if (!lay.synd_small_items.empty())
         HIPTRY(hipMemcpy(p->d_synd_small_items, lay.synd_small_items.data(), lay.synd_small_items.size() * sizeof(int4),
+                         hipMemcpyHostToDevice));
+    if (!lay.pair_items.empty())
+        HIPTRY(hipMemcpy(p->d_pair_items, lay.pair_items.data(), lay.pair_items.size() * sizeof(int4),
                          hipMemcpyHostToDevice));
     if (!lay.synd2_items.empty())
         HIPTRY(hipMemcpy(p->d_synd2_items, lay.synd2_items.data(), lay.synd2_items.size() * sizeof(int4),

@@ -33,6 +33,18 @@ constexpr int kFftPointsF32 = 8192;         // points per block in LDS (64 KiB)
 constexpr int kFftPointsF64 = 4096;
 constexpr int kFftPointsF32Small = 4096;     // blocks of FP32 signals with M <= this (32 KiB)
 constexpr int kActivityTile = 4096;         // bins per block of the activity pass
+// Consecutive-shift line pairs (pair_syndrome_kernel): FP32 units with
+// 2^kPairLog2MMin <= M <= 2^kPairLog2MMax, P = 1, 2 or 4 pairs per block; one
+// item list per (P, log2 M) group.
+constexpr int kPairLog2MMin = 8, kPairLog2MMax = 12;
+// log2 of the points of each line a thread holds (8: 107 VGPRs at M = 4096,
+// four waves per SIMD; 16 points need 177 and measured 1.13x slower)
+constexpr int kPairLpt = 3;
+constexpr int kPairSizes = kPairLog2MMax - kPairLog2MMin + 1;
+constexpr int kPairGroups = 3 * kPairSizes;
+__host__ __device__ constexpr int pair_group(int p, int log2m) {
+    return (p == 1 ? 0 : p == 2 ? 1 : 2) * kPairSizes + (log2m - kPairLog2MMin);
+}
 
 enum Mode { kExact = 0, kGeneral = 1, kIterative = 2 };
 constexpr int kFlagSpAll = 32;   // SFT_FLAG_SP_ALL (sft.h)
@@ -245,6 +257,9 @@ struct LaunchCtx {
     int n_synd_items;
     const int4* synd_small_items;   // pass 0 items of FP32 signals with M <= kFftPointsF32Small
     int n_synd_small_items;
+    const int4* pair_items;  // (unit, line0, 0, 0): pair_syndrome_kernel blocks, grouped by pair_group()
+    int pair_off[kPairGroups];
+    int pair_n[kPairGroups];
     const int4* synd2_items; // second pass of two-pass signals (pass 2)
     int n_synd2_items;
     void* ybuf;              // two-pass intermediate (float2* / double2*)
@@ -280,7 +295,11 @@ struct LaunchCtx {
 };
 
 hipError_t launch_zero_counters(const LaunchCtx& c);
-hipError_t launch_syndromes(const LaunchCtx& c);
+// part 0: every syndrome kernel; 1: the consecutive-shift pair kernels only;
+// 2: every other one (one-line-per-block gathers, second passes, energies)
+hipError_t launch_syndromes(const LaunchCtx& c, int part = 0);
+// true when both parts have work (they can then run as parallel branches)
+bool syndrome_parts_split(const LaunchCtx& c);
 hipError_t launch_singular_values(const LaunchCtx& c);
 hipError_t launch_select(const LaunchCtx& c);
 hipError_t launch_activity(const LaunchCtx& c);

@@ -275,6 +275,191 @@ __global__ __launch_bounds__(kBlock) void syndrome_kernel(const SigDev* __restri
     }
 }
 
+// Consecutive-shift lines of FP32 units with 2^8 <= M <= 2^12 points (the
+// 2L consecutive shifts of exact- and general-mode signals, the two shifts of
+// an iterative grid): one block holds P line pairs (lines line0 .. line0+2P-1,
+// shifts sh[line0] + 0 .. 2P-1) of one unit, with T = M / PT threads per pair
+// (PT = 2^LPT points of each line per thread).  Thread (p, j), p < P, j < T,
+// with p fastest so that the P lanes reading one 64 B run of 2P consecutive
+// samples sit next to each other in the wave, loads the samples
+// d (j + T s) + shift, s < PT, of its two lines as one 16-byte load each: a
+// block touches every fetched run once (the one-line-per-block kernel above
+// requests it once per line).
+//
+// FFT (the Stockham passes of stockham_pass, radix PT, then one of a smaller
+// power of two): in every pass, thread j takes the PT points j + T s of a line
+// (one butterfly of radix PT, or PT/R of radix R); the first pass runs on the
+// gathered registers, every later pass reads its inputs from LDS, where the
+// previous pass wrote its outputs; the last pass leaves X[j + T s] in
+// registers.  The LDS holds one line of each pair at a time (both lines of a
+// pair share the butterflies and twiddles), padded by one point per 16
+// against bank conflicts, plus the twiddles w_M^e for e <= M/8 (the others
+// follow exactly by symmetry).
+template <int LOG2M, int LPT>
+struct PairFft {
+    static constexpr int M = 1 << LOG2M;
+    static constexpr int PT = 1 << LPT;
+    static constexpr int T = M / PT;
+    static constexpr int NPASS = (LOG2M + LPT - 1) / LPT;
+    static constexpr int lds_points() { return M + M / 16; }
+    __device__ static inline int pad(int i) { return i + (i >> 4); }
+    __host__ __device__ static constexpr int log2r(int pass) { return pass < LOG2M / LPT ? LPT : LOG2M - LPT * pass; }
+};
+
+// w_M^e, 0 <= e < M, from the table q[e'] = w_M^{e'}, e' <= M/8: within a
+// quarter, w_M^{M/4 - e'} = -i conj(w_M^{e'}); across quarters, powers of -i
+// (every step exact).
+template <int LOG2M>
+__device__ inline float2 twiddle_q(const float2* q, int e) {
+    constexpr int Q = 1 << (LOG2M - 2);
+    const int e0 = e & (Q - 1);
+    float2 w;
+    if (e0 <= Q / 2) {
+        w = q[e0];
+    } else {
+        const float2 t = q[Q - e0];
+        w = float2{-t.y, -t.x};
+    }
+    switch (e >> (LOG2M - 2)) {
+        case 0: return w;
+        case 1: return float2{w.y, -w.x};    // * (-i)
+        case 2: return float2{-w.x, -w.y};   // * (-1)
+        default: return float2{-w.y, w.x};   // * (+i)
+    }
+}
+
+// One Stockham pass of radix 2^LR with ns = 2^LNS on the PT points a thread
+// holds (v[s] = point j + T s); writes its outputs to `lds` (padded line)
+// unless it is the last pass, which leaves X[j + T s] in v[s].
+template <int LOG2M, int LPT, int LR, int LNS, bool LAST>
+__device__ inline void pair_pass(float2 (&v)[1 << LPT], int j, const float2* qtw, float2* lds) {
+    using F = PairFft<LOG2M, LPT>;
+    constexpr int R = 1 << LR, NB = F::PT / R;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int b = j + F::T * q;           // butterfly index
+        const int k = b & ((1 << LNS) - 1);
+        float2 u[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) u[r] = v[q + NB * r];
+        if (LNS > 0) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) u[r] = cmulv(u[r], twiddle_q<LOG2M>(qtw, (r * k) << (LOG2M - LNS - LR)));
+        }
+        Dft<float2, R>::run(u);
+        if (LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q + NB * r] = u[r];
+        } else {
+            const int base = ((b >> LNS) << (LNS + LR)) + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[F::pad(base + (r << LNS))] = u[r];
+        }
+    }
+}
+
+// Passes 1 .. NPASS-1 of one line through LDS (pass 0 already written there).
+template <int LOG2M, int LPT, int PASS>
+__device__ inline void pair_rest(float2 (&v)[1 << LPT], int j, const float2* qtw, float2* lds) {
+    using F = PairFft<LOG2M, LPT>;
+    if constexpr (PASS < F::NPASS) {
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < F::PT; ++s) v[s] = lds[F::pad(j + F::T * s)];
+        __syncthreads();
+        constexpr int LR = F::log2r(PASS);
+        constexpr int LNS = LPT * PASS;   // every earlier pass was of radix PT
+        pair_pass<LOG2M, LPT, LR, LNS, PASS == F::NPASS - 1>(v, j, qtw, lds);
+        pair_rest<LOG2M, LPT, PASS + 1>(v, j, qtw, lds);
+    }
+}
+
+// One line: pass 0 (radix PT, no twiddles) on the registers, the rest through
+// LDS; stores d X[j + T s] to out and returns the energy of the line summed
+// over the P-strided lanes of the wave (fixed order).
+template <int P, int LOG2M, int LPT>
+__device__ inline double pair_line(float2 (&v)[1 << LPT], int j, const float2* qtw, float2* lds,
+                                   float2* __restrict__ out, float dscale) {
+    using F = PairFft<LOG2M, LPT>;
+    pair_pass<LOG2M, LPT, LPT, 0, false>(v, j, qtw, lds);
+    pair_rest<LOG2M, LPT, 1>(v, j, qtw, lds);
+    double acc = 0.0;
+#pragma unroll
+    for (int s = 0; s < F::PT; ++s) {
+        float2 w = v[s];
+        w.x *= dscale;
+        w.y *= dscale;
+        out[j + F::T * s] = w;
+        acc += (double)w.x * (double)w.x + (double)w.y * (double)w.y;
+    }
+    // lanes of the same p differ in the lane bits above log2 P
+#pragma unroll
+    for (int o = 32; o >= P; o >>= 1) acc += __shfl_xor(acc, o);
+    return acc;
+}
+
+template <int P, int LOG2M, int LPT>
+__global__ __launch_bounds__(P * (1 << (LOG2M - LPT))) void pair_syndrome_kernel(
+    const SigDev* __restrict__ sigs, const IoDev* __restrict__ io, const int4* __restrict__ items,
+    const int64_t* __restrict__ shifts, const float2* __restrict__ tw, int tw_log2, float2* __restrict__ synd,
+    double* __restrict__ epart, SigCounters* __restrict__ cnt) {
+    using F = PairFft<LOG2M, LPT>;
+    constexpr int NT = P * F::T;
+    static_assert(NT >= 64 && NT <= 1024, "whole waves, at most 1024 threads");
+    __shared__ float2 lds[P][F::lds_points()];
+    __shared__ float2 qtw[F::M / 8 + 1];
+    __shared__ double red[NT / 64][2 * P];
+    const int4 it = items[blockIdx.x];
+    if (it.x < 0) return;   // padding item
+    const SigDev sg = sigs[it.x];
+    const int line0 = it.y;
+    const int p = threadIdx.x % P, j = threadIdx.x / P;
+    const int64_t shift = shifts[sg.shift_off + line0] + 2 * p;   // shifts of lines line0 + 2p, +1
+    const float2* __restrict__ x = reinterpret_cast<const float2*>(io[sg.parent].x);
+
+    // gather: PT samples of each of the thread's two lines; d k' + shift + 1 < N (no wrap)
+    float2 a[F::PT], b[F::PT];
+    if ((reinterpret_cast<uintptr_t>(x) & 15) == 0) {
+        const float4* __restrict__ x4 = reinterpret_cast<const float4*>(x) + ((sg.d * (int64_t)j + shift) >> 1);
+        const int64_t step = (sg.d * F::T) >> 1;   // T samples of stride d, in 16-byte units
+#pragma unroll
+        for (int s = 0; s < F::PT; ++s) {
+            const float4 w = x4[s * step];
+            a[s] = float2{w.x, w.y};
+            b[s] = float2{w.z, w.w};
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < F::PT; ++s) {
+            const int64_t idx = sg.d * (int64_t)(j + F::T * s) + shift;
+            a[s] = x[idx];
+            b[s] = x[idx + 1];
+        }
+    }
+    if (sg.flags & 4) {
+        int bad = 0;
+#pragma unroll
+        for (int s = 0; s < F::PT; ++s)
+            bad += !(isfinite(a[s].x) && isfinite(a[s].y)) + !(isfinite(b[s].x) && isfinite(b[s].y));
+        if (bad) atomicAdd(&cnt[sg.parent].nonfinite, bad);
+    }
+    for (int e = threadIdx.x; e <= F::M / 8; e += NT) qtw[e] = tw[(int64_t)e << (tw_log2 - LOG2M)];
+
+    const float dscale = (float)sg.d;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float2* __restrict__ out = synd + sg.synd_off + ((int64_t)(line0 + 2 * p) << LOG2M);
+    double acc = pair_line<P, LOG2M, LPT>(a, j, qtw, lds[p], out, dscale);
+    if (lane < P) red[wave][2 * lane] = acc;
+    acc = pair_line<P, LOG2M, LPT>(b, j, qtw, lds[p], out + F::M, dscale);
+    if (lane < P) red[wave][2 * lane + 1] = acc;
+    __syncthreads();
+    if (threadIdx.x < 2 * P) {
+        double e = 0.0;
+        for (int w = 0; w < NT / 64; ++w) e += red[w][threadIdx.x];
+        epart[sg.epart_off + line0 + 2 * (threadIdx.x >> 1) + (threadIdx.x & 1)] = e;
+    }
+}
+
 // Line energies of two-pass signals: one block per (signal, line), fixed-order
 // FP64 reduction (the one-pass kernel computes them in its epilogue).
 template <typename T>
@@ -311,7 +496,44 @@ hipError_t launch_zero_counters(const LaunchCtx& c) {
     return hipGetLastError();
 }
 
-hipError_t launch_syndromes(const LaunchCtx& c) {
+template <int P, int LOG2M>
+static void launch_pair_group(const LaunchCtx& c) {
+    const int g = pair_group(P, LOG2M);
+    if (c.pair_n[g] == 0) return;
+    constexpr int NT = P * (1 << (LOG2M - kPairLpt));
+    if constexpr (NT >= 64 && NT <= 1024)
+        hipLaunchKernelGGL((pair_syndrome_kernel<P, LOG2M, kPairLpt>), dim3(c.pair_n[g]), dim3(NT), 0, c.stream, c.sigs,
+                           c.io, c.pair_items + c.pair_off[g], c.shifts, (const float2*)c.twiddle, c.tw_log2,
+                           (float2*)c.synd, c.epart, c.cnt);
+}
+
+template <int P>
+static void launch_pair_sizes(const LaunchCtx& c) {
+    launch_pair_group<P, 8>(c);
+    launch_pair_group<P, 9>(c);
+    launch_pair_group<P, 10>(c);
+    launch_pair_group<P, 11>(c);
+    launch_pair_group<P, 12>(c);
+}
+
+static void launch_pairs(const LaunchCtx& c) {
+    launch_pair_sizes<1>(c);
+    launch_pair_sizes<2>(c);
+    launch_pair_sizes<4>(c);
+}
+
+bool syndrome_parts_split(const LaunchCtx& c) {
+    if (c.fp64) return false;
+    int pairs = 0;
+    for (int g = 0; g < kPairGroups; ++g) pairs += c.pair_n[g];
+    return pairs > 0 && (c.n_synd_small_items + c.n_synd_items + c.n_synd2_items + c.n_line_items) > 0;
+}
+
+hipError_t launch_syndromes(const LaunchCtx& c, int part) {
+    if (part == 1) {
+        if (!c.fp64) launch_pairs(c);
+        return hipGetLastError();
+    }
     if (c.fp64) {
         // FP64 FFTs of complex128 input, or of complex64 input widened on load
         auto k64 = c.in_fp64 ? syndrome_kernel<double, kFftPointsF64, double> : syndrome_kernel<double, kFftPointsF64, float>;
@@ -327,6 +549,7 @@ hipError_t launch_syndromes(const LaunchCtx& c) {
             hipLaunchKernelGGL(line_energy_kernel<double>, dim3(c.n_line_items), dim3(kBlock), 0, c.stream, c.sigs,
                                c.line_items, (const double2*)c.synd, c.epart);
     } else {
+        if (part == 0) launch_pairs(c);
         if (c.n_synd_small_items)
             hipLaunchKernelGGL((syndrome_kernel<float, kFftPointsF32Small, float>), dim3(c.n_synd_small_items), dim3(kBlock), 0,
                                c.stream, c.sigs, c.io, c.synd_small_items, c.shifts, (const float2*)c.twiddle,

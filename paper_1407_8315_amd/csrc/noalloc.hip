@@ -49,12 +49,19 @@ static_assert(kNaMaxM32 == kFftPointsF32 && kNaMaxM64 == kFftPointsF64, "one-pas
 
 constexpr int64_t align256(int64_t v) { return (v + 255) & ~int64_t(255); }
 
+int ilog2_na(int64_t v) {
+    int r = 0;
+    while ((int64_t(1) << r) < v) ++r;
+    return r;
+}
+
 // Per-call description, passed by value to the set-up kernel.
 struct NaArgs {
     SigDev sig;
     IoDev io;
     int64_t shifts[kNaLines];
     int4 synd_items[kNaLines];
+    int4 pair_items[kMaxL];
     int2 bin_items[kNaMaxBinItems];
     int2 act_items[kNaMaxActItems];
 };
@@ -189,10 +196,16 @@ extern "C" sft_status sft_exact_noalloc(const sft_params* params, const void* x_
     a.sig = sigdev_of(g, kNaMaxD, fp64);
     a.io = IoDev{x_dev, out->loc_dev, (double2*)out->val_dev, out->capacity, out->count_dev};
     for (int l = 0; l < g.S; ++l) a.shifts[l] = l;
+    // the 2L consecutive shifts by pair_syndrome_kernel where a plan uses it
+    const int pb = (!fp64 && 2 * g.L - 1 < g.d) ? pair_block(g.L, g.m) : 0;
+    int n_pair = 0;
+    if (pb)
+        for (int l0 = 0; l0 < 2 * g.L; l0 += 2 * pb) a.pair_items[n_pair++] = int4{0, l0, 0, 0};
+    const int first = pb ? 2 * g.L : 0;
     bool small = false;
-    const int nl = fft_lines_per_block(g.m, g.S, fp64, &small);
+    const int nl = fft_lines_per_block(g.m, g.S - first, fp64, &small);
     int n_synd = 0;
-    for (int l0 = 0; l0 < g.S; l0 += nl) a.synd_items[n_synd++] = int4{0, l0, std::min(nl, g.S - l0), 0};
+    for (int l0 = first; l0 < g.S; l0 += nl) a.synd_items[n_synd++] = int4{0, l0, std::min(nl, g.S - l0), 0};
     int n_bins = 0, n_act = 0;
     for (int64_t b = 0; b < g.m; b += kBlock) a.bin_items[n_bins++] = int2{0, (int)b};
     for (int64_t b = 0; b < g.m; b += kActivityTile) a.act_items[n_act++] = int2{0, (int)b};
@@ -232,6 +245,12 @@ extern "C" sft_status sft_exact_noalloc(const sft_params* params, const void* x_
     } else {
         c.synd_items = hdr->synd_items;
         c.n_synd_items = n_synd;
+    }
+    if (pb) {
+        const int grp = pair_group(pb, ilog2_na(g.m));
+        c.pair_items = hdr->pair_items;
+        c.pair_off[grp] = 0;
+        c.pair_n[grp] = n_pair;
     }
     c.bin_items = hdr->bin_items;
     c.n_bin_items = n_bins;

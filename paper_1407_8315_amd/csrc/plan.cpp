@@ -309,6 +309,19 @@ SigDev sigdev_of(const SigHost& g, int64_t dmax, bool fp64) {
     return s;
 }
 
+int pair_block(int pairs, int64_t m) {
+    if (pairs < 1 || m < (int64_t(1) << kPairLog2MMin) || m > (int64_t(1) << kPairLog2MMax)) return 0;
+    // one pair per block where it makes whole waves (measured at M = 4096: 2
+    // pairs per block are 1.35x slower, with twice the VGPRs per block), more
+    // for short lines
+    for (int p : {1, 2, 4}) {
+        if (p > pairs || pairs % p) continue;
+        const int64_t threads = p * (m >> kPairLpt);
+        if (threads >= 64 && threads <= 1024) return p;
+    }
+    return 0;
+}
+
 int fft_lines_per_block(int64_t m, int lines, bool fp64, bool* small) {
     const bool sm = !fp64 && m <= kFftPointsF32Small;
     if (small) *small = sm;
@@ -482,13 +495,47 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
     // line of 4096, or more lines of fewer) and a smaller LDS footprint, so that
     // more blocks share a CU and overlap their gathers
     const auto small = [&](int64_t m) { return !fp64 && m <= kFftPointsF32Small; };
+    // Lines of a unit taken by pair_syndrome_kernel (FP32, one pass): the 2L
+    // consecutive shifts of a signal, the two shifts of an iterative grid,
+    // when they do not wrap around N (d > last shift); *pb = pairs per block.
+    const auto pair_lines = [&](int idx, int* pb) -> int {
+        const SigDev& u = lay->sigdev[idx];
+        *pb = 0;
+        // general-mode signals keep all their lines in syndrome_kernel: their
+        // R random shifts dominate the gather (one 128 B line per sample), and
+        // splitting off the consecutive shifts measured slower
+        if (fp64 || u.log2m1 != 0 || u.mode == SFT_MODE_GENERAL) return 0;
+        const int pairs = u.mode == SFT_MODE_ITERATIVE ? 1 : u.L;
+        const int64_t last = lay->shifts[(size_t)u.shift_off] + 2 * pairs - 1;
+        if (last >= u.d) return 0;
+        *pb = pair_block(pairs, u.m);
+        return *pb ? 2 * pairs : 0;
+    };
+    for (int g = 0; g < kPairGroups; ++g) {
+        lay->pair_off[g] = (int)lay->pair_items.size();
+        interleave(
+            [&](int s, std::vector<int4>& v) {
+                for_units(s, [&](int idx, int64_t m, int S, int lm1) {
+                    (void)S;
+                    (void)lm1;
+                    int pb = 0;
+                    const int lines = pair_lines(idx, &pb);
+                    if (!lines || pair_group(pb, ilog2(m)) != g) return;
+                    for (int l0 = 0; l0 < lines; l0 += 2 * pb) v.push_back(int4{idx, l0, 0, 0});
+                });
+            },
+            int4{-1, 0, 0, 0}, lay->pair_items);
+        lay->pair_n[g] = (int)lay->pair_items.size() - lay->pair_off[g];
+    }
     interleave(
         [&](int s, std::vector<int4>& v) {
             for_units(s, [&](int idx, int64_t m, int S, int lm1) {
                 (void)lm1;
                 if (!small(m)) return;
-                const int nl = fft_lines_per_block(m, S, fp64, nullptr);
-                for (int l0 = 0; l0 < S; l0 += nl) v.push_back(int4{idx, l0, std::min(nl, S - l0), 0});
+                int pb = 0;
+                const int first = pair_lines(idx, &pb);
+                const int nl = fft_lines_per_block(m, S - first, fp64, nullptr);
+                for (int l0 = first; l0 < S; l0 += nl) v.push_back(int4{idx, l0, std::min(nl, S - l0), 0});
             });
         },
         int4{-1, 0, 0, 0}, lay->synd_small_items);
@@ -497,8 +544,10 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
             for_units(s, [&](int idx, int64_t m, int S, int lm1) {
                 if (small(m)) return;
                 if (m <= pmax) {
-                    const int nl = fft_lines_per_block(m, S, fp64, nullptr);
-                    for (int l0 = 0; l0 < S; l0 += nl) v.push_back(int4{idx, l0, std::min(nl, S - l0), 0});
+                    int pb = 0;
+                    const int first = pair_lines(idx, &pb);
+                    const int nl = fft_lines_per_block(m, S - first, fp64, nullptr);
+                    for (int l0 = first; l0 < S; l0 += nl) v.push_back(int4{idx, l0, std::min(nl, S - l0), 0});
                 } else {
                     // first of two passes: S * M1 lines of length M2
                     const int lm2 = ilog2(m) - lm1;

@@ -29,6 +29,9 @@ struct PlanLayout {
     std::vector<int4> synd_items;         // (sig, line0, nlines, pass 0|1); sig < 0 = padding
     std::vector<int4> synd_small_items;   // one-pass FP32 signals with M <= kFftPointsF32Small
     std::vector<int4> synd2_items;        // (sig, line0, nlines, 2): second FFT pass
+    std::vector<int4> pair_items;         // (unit, line0, 0, 0) of pair_syndrome_kernel, by group
+    int pair_off[kPairGroups] = {};
+    int pair_n[kPairGroups] = {};
     std::vector<int2> line_items;         // (sig, line) of two-pass signals
     std::vector<int2> bin_items;          // (sig, bin0)
     std::vector<int2> act_items;          // (sig, bin0), tiles of kActivityTile
@@ -66,6 +69,11 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay);
 // The device description of one signal with every buffer offset 0 (a plan's
 // layout then places it); dmax: size of the omega table the plan uses.
 SigDev sigdev_of(const SigHost& g, int64_t dmax, bool fp64);
+
+// Line pairs per block of pair_syndrome_kernel for a unit with `pairs`
+// consecutive-shift line pairs of M points (FP32), or 0 when that kernel does
+// not take the unit.
+int pair_block(int pairs, int64_t m);
 
 // Lines per block of the one-pass FFT of a unit of `lines` lines of M points;
 // *small (nullable): the unit goes to the FP32 kernel of kFftPointsF32Small

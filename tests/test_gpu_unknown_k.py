@@ -47,8 +47,7 @@ def test_unknown_k_matches_oracle(torch, sft, n, k, L, m_max, dtype):
     res, m = plan.unknown_k(torch.from_numpy(s.x).cuda(), capacity=m_max * L, stats=True)
     loc, val = res.host()
     plan.close()
-    fft = np.complex64 if dtype == "c64" else np.complex128
-    ref, m_ref = oracle.sfft_unknown_k(s.x, n, L, m_max=m_max, fft_dtype=fft)
+    ref, m_ref = oracle.sfft_unknown_k(s.x, n, L, m_max=m_max)   # FP64 FFTs
     say(f"  M chosen {m} (oracle {m_ref}), flagged {res.stats['flagged_bins']}")
     assert m == m_ref
     assert loc.tolist() == ref.locs.tolist()

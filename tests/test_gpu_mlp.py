@@ -55,24 +55,37 @@ def test_forward_matches_reference(torch, sft):
 
 
 def test_gradient_matches_reference(torch, sft):
-    """Gradient of the mean cross-entropy against the FP64 reference gradient of
-    the BF16-rounded network (the device also rounds the backward activations
-    to BF16, hence the tolerance)."""
+    """Gradient of the mean cross-entropy against the FP64 reference gradient
+    with the device's BF16 rounding points (weights, inputs and hidden
+    activations in the forward pass; dZ3 for dH2 and dW3, dZ2 and dZ1 in the
+    backward pass), entry by entry: |g - g_ref| <= 1e-3 max|g_ref| + 1e-2
+    |g_ref| within each parameter block.  An FP32 emulation of the device's
+    arithmetic stays within 2e-5 max|g_ref| of this reference (FP32
+    accumulation, the polynomial erf and rare BF16 rounding flips of the
+    activations make the rest)."""
     say("[mlp grad]")
     g = np.random.default_rng(1)
     net = sft.Mlp(seed=6)
-    x = g.standard_normal((257, 32)).astype(np.float32)
+    theta = net.get_params().astype(np.float64)
+    for name in ("b1", "b2", "b3"):   # non-zero biases, so that every term of the gradient is exercised
+        idx = omlp.unpack(np.arange(omlp.NPARAMS))[name].astype(int)
+        theta[idx] = g.standard_normal(len(idx)) * 0.1
+    net.set_params(theta)
+    x = g.standard_normal((257, 32)).astype(np.float32)   # 4 full tiles of 64 rows and a ragged one
     y = g.integers(0, 5, 257).astype(np.int32)
     gd, loss = net.grad(to_dev(torch, x), to_dev(torch, y))
     gd = gd.cpu().numpy().astype(np.float64)
-    ref_loss, ref = omlp.loss_and_grad(net.get_params(), x, y, bf16=True)
-    assert abs(float(loss.item()) - ref_loss) < 1e-3 * ref_loss
+    ref_loss, ref = omlp.loss_and_grad(net.get_params(), x, y, bf16=True, bf16_backward=True)
+    assert abs(float(loss.item()) - ref_loss) < 1e-4 * ref_loss
     for name, part_g in omlp.unpack(gd).items():
         part_r = omlp.unpack(ref)[name]
-        rel = np.linalg.norm(part_g - part_r) / np.linalg.norm(part_r)
-        cos = np.sum(part_g * part_r) / (np.linalg.norm(part_g) * np.linalg.norm(part_r))
-        say(f"  {name}: rel {rel:.2e} cos {cos:.6f}")
-        assert rel < 3e-2 and cos > 0.999
+        scale = np.max(np.abs(part_r))
+        err = np.abs(part_g - part_r)
+        bound = 1e-3 * scale + 1e-2 * np.abs(part_r)
+        worst = float(np.max(err / bound))
+        say(f"  {name}: max |g - g_ref| / max|g_ref| {np.max(err) / scale:.2e}, worst error / bound {worst:.3f}")
+        assert scale > 0
+        assert np.all(err <= bound), (name, int(np.sum(err > bound)))
     net.close()
 
 
@@ -158,6 +171,41 @@ def test_training_and_learned_decode(torch, sft):
         act += rl.stats["active_bins"]
     say(f"  fallbacks {fb}/{act}; order+decode ms plain {t_plain:.3f} learned {t_learned:.3f}")
     assert fb <= 0.05 * act
+    plain.close()
+    learned.close()
+    net.close()
+
+
+@pytest.mark.parametrize("kind", ["random", "always4", "always0"])
+def test_sabotaged_weights_change_nothing(torch, sft, kind):
+    """The predictor only orders the hypotheses: with untrained weights, or
+    weights that predict one class for every bin, a learned plan returns the
+    plain plan's output bit for bit (the rank test is the fallback and the
+    residual check the judge, reading R24), with the fallbacks counted."""
+    n, k, m = 1 << 20, 1000, 4096
+    say(f"[sabotaged] {kind}")
+    net = sft.Mlp(seed=123)
+    if kind != "random":
+        theta = np.zeros(omlp.NPARAMS)
+        b3 = omlp.unpack(np.arange(omlp.NPARAMS))["b3"].astype(int)
+        theta[b3[4 if kind == "always4" else 0]] = 10.0
+        net.set_params(theta)
+    plain = sft.Plan(dict(n=n, k=k, m=m, l=4))
+    learned = sft.Plan(dict(n=n, k=k, m=m, l=4, flags=sft.SFT_FLAG_LEARNED))
+    learned.attach(net)
+    for seed in range(2):
+        s = sftgen.make_signal(n, k, sftgen.BASE_SEED + 7700 + seed, amp="gauss", dtype=np.complex64)
+        x = to_dev(torch, s.x)
+        rp = plain.exact(x, stats=True)
+        rl = learned.exact(x, stats=True)
+        lp, vp = rp.host()
+        ll, vl = rl.host()
+        say(f"  seed {seed}: fallbacks {rl.stats['mlp_fallbacks']} of {rl.stats['active_bins']} active bins")
+        assert ll.tolist() == lp.tolist()
+        assert np.array_equal(vl, vp)
+        assert rl.stats["flagged_bins"] == rp.stats["flagged_bins"]
+        if kind != "always0":   # class 0 gives no order: such bins go straight to the rank test
+            assert rl.stats["mlp_fallbacks"] > 0
     plain.close()
     learned.close()
     net.close()

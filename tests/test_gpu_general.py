@@ -37,11 +37,12 @@ def to_dev(torch, x):
 @pytest.mark.parametrize("snr", [10, 20, 30, 40, None])
 def test_general_n20_metrics_match_oracle(torch, sft, snr):
     """N = 2^20, K = 1000, M = 4096, L = 4, R = 12, complex64: support recovery
-    and relative L2 error within 1e-3 of the oracle's (averaged over 2 signals),
+    and relative L2 error within 1e-3 of the oracle's (averaged over 4 signals),
     and the same entries for all but a few bins."""
     n, k, m, L = 1 << 20, 1000, 4096, 4
+    ns = 4
     sr_g, sr_o, rl_g, rl_o, same, tot = 0.0, 0.0, 0.0, 0.0, 0, 0
-    for i in range(2):
+    for i in range(ns):
         say(f"[general] snr={snr} signal={i}")
         s = sftgen.make_signal(n, k, 900 + i, amp="gauss", dtype=np.complex64, snr_db=snr)
         plan = sft.Plan(dict(n=n, k=k, m=m, l=L, mode="general", seed=77 + i))
@@ -50,17 +51,46 @@ def test_general_n20_metrics_match_oracle(torch, sft, snr):
         rsh = plan.info()["rshifts"]
         plan.close()
         ref = oracle.sfft_general(s.x, n, k, m, L, rsh)
-        sr_g += oracle.support_recovery(s.locs, loc) / 2
-        sr_o += oracle.support_recovery(s.locs, ref.locs) / 2
-        rl_g += oracle.relative_l2(s.locs, s.vals, loc, val) / 2
-        rl_o += oracle.relative_l2(s.locs, s.vals, ref.locs, ref.vals) / 2
+        sr_g += oracle.support_recovery(s.locs, loc) / ns
+        sr_o += oracle.support_recovery(s.locs, ref.locs) / ns
+        rl_g += oracle.relative_l2(s.locs, s.vals, loc, val) / ns
+        rl_o += oracle.relative_l2(s.locs, s.vals, ref.locs, ref.vals) / ns
         same += len(np.intersect1d(loc, ref.locs))
         tot += max(len(loc), len(ref.locs))
         assert len(loc) == len(ref.locs)
     say(f"  recovery gpu {sr_g:.5f} oracle {sr_o:.5f}; rel L2 gpu {rl_g:.5f} oracle {rl_o:.5f}; same {same}/{tot}")
     assert abs(sr_g - sr_o) <= 1e-3
     assert abs(rl_g - rl_o) <= 1e-3
-    assert same >= tot - 4
+    assert same >= tot - 8
+
+
+@pytest.mark.parametrize("k", [1 << 10, 1 << 12, 1 << 14])
+def test_general_n24_20db_metrics_match_oracle(torch, sft, k):
+    """N = 2^24, K in {2^10, 2^12, 2^14}, M = 4K (one and two FFT passes),
+    L = 4, R = 12, unit amplitudes, 20 dB, complex64: support recovery and
+    relative L2 error within 1e-3 of the oracle's, the same entries for all
+    but a few bins.  (At d = N/M = 4096 .. 256 the 2L syndromes of a bin
+    place a tone on one of d slots only at high per-bin SNR, so the method
+    itself recovers little here; the oracle recovers the same.)"""
+    n, m, L = 1 << 24, 4 * k, 4
+    say(f"[general N=2^24 20 dB] K={k} M={m}")
+    s = sftgen.make_signal(n, k, sftgen.BASE_SEED + 2424, amp="unit", dtype=np.complex64, snr_db=20)
+    plan = sft.Plan(dict(n=n, k=k, m=m, l=L, mode="general", seed=2424))
+    res = plan.general(to_dev(torch, s.x), stats=True)
+    loc, val = res.host()
+    rsh = plan.info()["rshifts"]
+    plan.close()
+    ref = oracle.sfft_general(s.x, n, k, m, L, rsh)
+    sr_g, sr_o = oracle.support_recovery(s.locs, loc), oracle.support_recovery(s.locs, ref.locs)
+    rl_g = oracle.relative_l2(s.locs, s.vals, loc, val)
+    rl_o = oracle.relative_l2(s.locs, s.vals, ref.locs, ref.vals)
+    same = len(np.intersect1d(loc, ref.locs))
+    say(f"  recovery gpu {sr_g:.5f} oracle {sr_o:.5f}; rel L2 gpu {rl_g:.5f} oracle {rl_o:.5f}; "
+        f"same {same}/{max(len(loc), len(ref.locs))}; cs bins {res.stats['cs_bins']} / {ref.cs_bins}")
+    assert len(loc) == len(ref.locs)
+    assert abs(sr_g - sr_o) <= 1e-3
+    assert abs(rl_g - rl_o) <= 1e-3
+    assert same >= len(ref.locs) - max(4, k // 2048)
 
 
 def test_general_top_k_beyond_one_lds_sort(torch, sft):

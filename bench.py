@@ -51,7 +51,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--mode", choices=["general", "exact", "iterative"], default="general")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of each leg of the oracle sample")
+    ap.add_argument("--parity-signals", type=int, default=32,
+                    help="signals of the timed batch compared with the FP64 oracle (0: none)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for counter calibration)")
@@ -60,6 +62,7 @@ def parse():
     ap.add_argument("--no-iterative", action="store_true", help="skip the iterative-vs-non-iterative comparison")
     ap.add_argument("--fft64", action="store_true", help="FP64 FFTs for the complex64 input (SFT_FLAG_FFT64)")
     ap.add_argument("--no-model", action="store_true", help="skip the recovery-vs-collision-model section")
+    ap.add_argument("--no-large", action="store_true", help="skip the N = 2^24 section")
     ap.add_argument("--paper-tables", action="store_true",
                     help="also run Alg. 2 as printed on the Tables II-IV workload (N = 2^24, mixture Gaussian)")
     return ap.parse_args()
@@ -222,8 +225,30 @@ def recovery_vs_model(B=256):
                              "measured_recovery": round(found / (B * k), 6), "model_recovery": round(model, 6),
                              "signals_with_a_miss": round(imperfect / B, 4), "lemma2_bound": round(min(1.0, lemma2), 6)})
         del xs
+        # Fig. 4 (non-iterative): recovery against K at d = N/(4K), a_m = 4
+        fig4 = []
+        for lk in (6, 8, 10, 12, 14):
+            kk, B4 = 1 << lk, 64
+            m = 4 * kk
+            d = n // m
+            xs, truth = [], []
+            for i in range(B4):
+                x, locs, _ = sftgen.torch_signal(n, kk, sftgen.BASE_SEED + 51000 + 100 * lk + i, dev, amp="unit")
+                xs.append(x)
+                truth.append(locs)
+            plan = Plan([dict(n=n, k=kk, m=m, l=4, flags=SFT_FLAG_FFT64)] * B4, stream=stream)
+            outs = plan.batch(xs)
+            torch.cuda.synchronize()
+            found = sum(len(np.intersect1d(o.host()[0], t)) for o, t in zip(outs, truth))
+            plan.close()
+            model = float(hypergeom.cdf(3, n - 1, d - 1, kk - 1))
+            fig4.append({"log2_k": lk, "m": m, "d": d, "measured_recovery": round(found / (B4 * kk), 6),
+                         "model_recovery": round(model, 6), "signals": B4})
+            del xs
     return {"workload": f"exact, N=2^20, K=1000, unit amplitudes, complex64 with FP64 FFTs, {B} signals per cell",
-            "rows": rows}
+            "rows": rows,
+            "fig4_workload": "exact, N=2^20, d=N/(4K) (M=4K), L=a_m=4, unit amplitudes, FP64 FFTs, 64 signals per K",
+            "fig4_rows": fig4}
 
 
 def paper_tables(reps=3, log2_ks=range(8, 17)):
@@ -339,6 +364,84 @@ def uneven_batch(steps, warmup, count=4096):
             "input_generation_s": round(t_gen, 1)}
 
 
+def large_scale(steps, warmup, batches=((10, 256), (12, 64), (14, 32))):
+    """N = 2^24 with K in {2^10, 2^12, 2^14} and M = 4K, L = 4, complex64
+    (unit amplitudes): per K, a batch of B exact signals (B = 256, 64, 32:
+    enough blocks to fill the device at every M) decoded with the
+    plain rank test and with the learned order (graph-replayed sft_batch
+    calls), and a batch of B general-mode signals at 20 dB.  The gather + FFT
+    stage's algorithmic bandwidth comes from the per-stage events (every
+    gathered sample read once, every syndrome written once)."""
+    import numpy as np
+    import torch
+
+    import sftgen
+    from paper_1407_8315_amd import SFT_FLAG_LEARNED, Mlp, Plan
+
+    n, L = 1 << 24, 4
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.Stream(device=dev)
+    rows = []
+    with torch.cuda.stream(stream):
+        net = None
+        if os.path.exists(WEIGHTS):
+            net = Mlp(seed=0, stream=stream)
+            net.load(WEIGHTS)
+        for lk, B in batches:
+            k = 1 << lk
+            m = 4 * k
+            for variant in ("exact", "general_20db"):
+                xs, truth = [], []
+                for i in range(B):
+                    x, locs, _ = sftgen.torch_signal(n, k, sftgen.BASE_SEED + 80000 + 100 * lk + i, dev, amp="unit",
+                                                     snr_db=20 if variant != "exact" else None)
+                    xs.append(x)
+                    truth.append(locs)
+                forms = [("plain", 0)] + ([("learned", SFT_FLAG_LEARNED)] if variant == "exact" and net else [])
+                for form, flags in forms:
+                    mode = "exact" if variant == "exact" else "general"
+                    plan = Plan([dict(n=n, k=k, m=m, l=L, mode=mode, seed=lk, flags=flags)] * B, stream=stream)
+                    if flags:
+                        plan.attach(net)
+                    outs = [plan.new_output(m * L, dev) for _ in range(B)]
+                    run = plan.prepare_batch(xs, outs)
+                    for _ in range(warmup):
+                        run()
+                    torch.cuda.synchronize()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    for _ in range(steps):
+                        run()
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    ms = e0.elapsed_time(e1) / steps
+                    found = sum(len(np.intersect1d(o.loc[:min(int(o.count.item()), o.loc.numel())].cpu().numpy(), t))
+                                for o, t in zip(outs, truth))
+                    st = run(stats=True)
+                    lines = 2 * L + (plan.infos[0]["r"] if mode == "general" else 0)
+                    stage_gbs = B * lines * m * 8 * 2 / (st["stage_ms"][0] * 1e-3) / 1e9
+                    rows.append({"log2_k": lk, "m": m, "variant": variant, "form": form, "signals": B,
+                                 "ms_per_step": round(ms, 4), "signals_per_s": round(B / ms * 1e3, 1),
+                                 "freqs_per_s": round(found / ms * 1e3, 1),
+                                 "support_recovery": round(found / (B * k), 6),
+                                 "stage_ms": [round(v, 4) for v in st["stage_ms"]],
+                                 "gather_fft_algorithmic_gbs": round(stage_gbs, 1),
+                                 "gather_fft_frac_of_hbm_peak": round(stage_gbs / HBM_PEAK_GBS, 4),
+                                 "mlp_fallbacks": st["mlp_fallbacks"], "active_bins": st["active_bins"]})
+                    plan.close()
+                del xs
+                torch.cuda.empty_cache()
+        if net:
+            net.close()
+    for lk in (10, 12, 14):
+        p = [r for r in rows if r["log2_k"] == lk and r["variant"] == "exact"]
+        if len(p) == 2:
+            p[1]["speedup_over_plain"] = round(p[0]["ms_per_step"] / p[1]["ms_per_step"], 4)
+    return {"workload": "N=2^24, K=2^10/2^12/2^14, M=4K, L=4, unit amplitudes, complex64, batches of "
+                        + "/".join(str(b) for _, b in batches) + "; exact (plain and learned) and general mode at 20 dB",
+            "rows": rows}
+
+
 def mlp_throughput(steps, warmup, rows=1 << 18):
     """The order predictor's kernels on `rows` random feature rows: forward
     (inference) and one Adam training step (forward + backward), each timed
@@ -385,6 +488,14 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import numpy as np
+
+    n, k, m, L, R = 1 << 20, 1000, 4096, 4, 12
+    snrs = [10, 20, 30, 40]
+    cpu = None
+    if not a.no_cpu and not a.copy_calibration:
+        # on the host, before anything initialises the GPU
+        cpu = cpu_baseline(n, k, m, L, R, a.mode, a.cpu_seconds, snrs)
+
     import torch
 
     import sftgen
@@ -401,19 +512,18 @@ def main():
         print(json.dumps({"copy_bytes_each_way": src.numel() * 8, "launches": 5}))
         return
 
-    n, k, m, L, R = 1 << 20, 1000, 4096, 4, 12
     B = a.batch
-    snrs = [10, 20, 30, 40]
     mode = a.mode
     stream = torch.cuda.Stream(device=dev)
-    xs, truth = [], []
+    xs, truth, tvals = [], [], []
     t0 = time.time()
     with torch.cuda.stream(stream):
         for i in range(B):
             snr = snrs[i % 4] if mode == "general" else None
-            x, locs, _ = sftgen.torch_signal(n, k, sftgen.BASE_SEED + i, dev, amp="gauss", snr_db=snr)
+            x, locs, vals = sftgen.torch_signal(n, k, sftgen.BASE_SEED + i, dev, amp="gauss", snr_db=snr)
             xs.append(x)
             truth.append(locs)
+            tvals.append(vals)
     torch.cuda.synchronize()
     gen_s = time.time() - t0
     flags = 16 if a.fft64 else 0   # SFT_FLAG_FFT64
@@ -467,9 +577,10 @@ def main():
                 else "syndrome_kernel<float, 4096, float> (gather + FFT)",
                 "algorithmic_bytes_per_launch": synd_bytes, "avg_launch_ms": round(stage[0], 4)}
 
-    cpu = None
-    if not a.no_cpu:
-        cpu = cpu_baseline(n, k, m, L, R, mode, plan, a.cpu_seconds, snrs)
+    for i, o in enumerate(outs[:a.parity_signals]):
+        o.truth = (truth[i], tvals[i])
+    parity = parity_sample(mode, n, k, m, L, xs, outs, plan.infos, min(a.parity_signals, B)) \
+        if a.parity_signals else None
     plan.close()
     del xs, outs
     torch.cuda.empty_cache()
@@ -482,6 +593,8 @@ def main():
     itv = None if a.no_iterative else iterative_vs_non_iterative(a.steps, a.warmup)
     torch.cuda.empty_cache()
     tables = paper_tables() if a.paper_tables else None
+    torch.cuda.empty_cache()
+    large = None if a.no_large else large_scale(a.steps, a.warmup)
     torch.cuda.empty_cache()
     model = None if a.no_model else recovery_vs_model()
     out = {
@@ -500,47 +613,143 @@ def main():
         "stats_last_step": {kk: v for kk, v in st.items() if kk != "stage_ms"} if st else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "parity": parity,
         "learned_vs_plain": lvp,
         "uneven_batch": unv,
         "mlp_kernels": mlp,
         "iterative_vs_non_iterative": itv,
         "paper_tables_2_4": tables,
+        "large_scale_n24": large,
         "recovery_vs_model": model,
         "input_generation_s": round(gen_s, 2),
     }
     print(json.dumps(out))
 
 
-def cpu_baseline(n, k, m, L, R, mode, plan, budget_s, snrs):
-    """The FP64 oracle on a bounded sample of the same workload, one host thread."""
+def _host_cpu():
+    """Model name, logical CPUs and the CPUs this process may run on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+
+
+def _oracle_task(args):
+    """One signal of the CPU baseline: generate (untimed), run the FP64 oracle
+    (timed, one thread).  Returns (frequencies recovered, oracle seconds)."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
 
     import oracle
     import sftgen
     from oracle import iterative as oracle_iterative
 
-    done, found, t_total, c_total = 0, 0, 0.0, 0.0
-    i = 0
-    while t_total < budget_s and i < min(256, len(plan.infos)):
-        snr = snrs[i % 4] if mode == "general" else None
-        s = sftgen.make_signal(n, k, sftgen.BASE_SEED + i, amp="gauss", dtype=np.complex64, snr_db=snr)
-        t0, c0 = time.perf_counter(), time.process_time()
+    n, k, m, L, R, mode, seed, snr = args
+    with threadpool_limits(1):
+        s = sftgen.make_signal(n, k, seed, amp="gauss", dtype=np.complex64, snr_db=snr)
+        t0 = time.perf_counter()
         if mode == "general":
-            r = oracle.sfft_general(s.x, n, k, m, L, plan.infos[i]["rshifts"])
+            d = n // m
+            rsh = sorted(np.random.default_rng(seed).choice(d, R, replace=False).tolist())
+            r = oracle.sfft_general(s.x, n, k, m, L, rsh)
         elif mode == "iterative":
             r, _ = oracle_iterative.sfft_iterative(s.x, n, m, L)
         else:
             r = oracle.sfft_exact(s.x, n, m, L)
-        t_total += time.perf_counter() - t0
-        c_total += time.process_time() - c0
-        found += len(np.intersect1d(r.locs, s.locs))
-        done += 1
+        dt = time.perf_counter() - t0
+    return len(np.intersect1d(r.locs, s.locs)), dt
+
+
+def cpu_baseline(n, k, m, L, R, mode, budget_s, snrs):
+    """The FP64 oracle on a bounded sample of the same workload (the batch's
+    seeds and SNRs; general mode draws its R random shifts per signal), timed
+    on the host before the GPU is touched: one thread, then one process per
+    available CPU (at most 16) running signals side by side, each with one
+    BLAS thread.  Signal generation is excluded from both."""
+    import concurrent.futures
+    import multiprocessing
+
+    import sftgen
+
+    def task(i):
+        return (n, k, m, L, R, mode, sftgen.BASE_SEED + i, snrs[i % 4] if mode == "general" else None)
+
+    found, t_tot, i = 0, 0.0, 0
+    while t_tot < budget_s and i < 256:
+        f, dt = _oracle_task(task(i))
+        found += f
+        t_tot += dt
         i += 1
-    return {"value": round(found / t_total, 1), "unit": "freqs/s", "cores": max(1, round(c_total / t_total)),
-            "kind": "oracle",
-            "signals_per_s": round(done / t_total, 3),
-            "sample": f"first {done} signals of the batch (same seeds), {t_total:.1f} s of CPU time; "
-                      "signal generation excluded"}
+    single = {"value": round(found / t_tot, 1), "unit": "freqs/s", "cores": 1, "signals": i,
+              "signals_per_s": round(i / t_tot, 3), "oracle_seconds": round(t_tot, 1)}
+    procs = max(1, min(16, _host_cpu()["affinity"]))
+    ctx = multiprocessing.get_context("fork")
+    found_p, t_sum, done = 0, 0.0, 0
+    t0 = time.perf_counter()
+    with concurrent.futures.ProcessPoolExecutor(max_workers=procs, mp_context=ctx) as ex:
+        j = 0
+        while time.perf_counter() - t0 < budget_s and j < 1024:
+            batch = [task(j + q) for q in range(procs)]
+            for f, dt in ex.map(_oracle_task, batch):
+                found_p += f
+                t_sum += dt
+                done += 1
+            j += procs
+    # signals run side by side: the rate is procs x the mean per-process rate
+    multi_value = found_p / t_sum * procs
+    return {"value": round(multi_value, 1), "unit": "freqs/s", "cores": procs, "kind": "oracle",
+            "sample": f"{mode} workload, first {done} signals of the batch's seeds in {procs} processes "
+                      f"(one BLAS thread each, {t_sum:.1f} s of oracle time); single-thread leg: first {i} "
+                      f"signals, {t_tot:.1f} s; signal generation excluded",
+            "single_thread": single, "host": _host_cpu()}
+
+
+def parity_sample(mode, n, k, m, L, xs, outs, infos, count):
+    """The GPU's outputs of the timed batch against the FP64 oracle run on the
+    same complex64 inputs, for the first `count` signals: exact and iterative
+    mode, the locations returned by one side only and the largest relative
+    amplitude error at common locations; general mode (an approximation,
+    compared on metrics), support recovery and relative L2 error of both."""
+    import numpy as np
+
+    import oracle
+    from oracle import iterative as oracle_iterative
+
+    diff_locs, diff_sigs, max_rel = 0, 0, 0.0
+    sr_g = sr_o = rl_g = rl_o = 0.0
+    for i in range(count):
+        x = xs[i].cpu().numpy()
+        loc, val = outs[i].host()
+        if mode == "general":
+            r = oracle.sfft_general(x, n, k, m, L, infos[i]["rshifts"])
+        elif mode == "iterative":
+            r, _ = oracle_iterative.sfft_iterative(x, n, m, L)
+        else:
+            r = oracle.sfft_exact(x, n, m, L)
+        d = len(set(loc.tolist()) ^ set(r.locs.tolist()))
+        diff_locs += d
+        diff_sigs += d > 0
+        common, ia, ib = np.intersect1d(loc, r.locs, return_indices=True)
+        if len(common):
+            max_rel = max(max_rel, float(np.max(np.abs(val[ia] - r.vals[ib]) / np.abs(r.vals[ib]))))
+        if mode == "general":
+            t = outs[i].truth
+            sr_g += oracle.support_recovery(t[0], loc) / count
+            sr_o += oracle.support_recovery(t[0], r.locs) / count
+            rl_g += oracle.relative_l2(t[0], t[1], loc, val) / count
+            rl_o += oracle.relative_l2(t[0], t[1], r.locs, r.vals) / count
+    out = {"signals": count, "reference": "FP64 oracle (FP64 FFTs, complex64 thresholds) on the same inputs",
+           "locations_returned_by_one_side": diff_locs, "signals_with_a_difference": diff_sigs,
+           "max_rel_amplitude_error_common": float(f"{max_rel:.3g}")}
+    if mode == "general":
+        out.update({"support_recovery_gpu": round(sr_g, 6), "support_recovery_oracle": round(sr_o, 6),
+                    "rel_l2_gpu": round(rl_g, 6), "rel_l2_oracle": round(rl_o, 6)})
+    return out
 
 
 if __name__ == "__main__":

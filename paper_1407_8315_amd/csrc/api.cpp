@@ -107,6 +107,8 @@ struct sft_plan_s {
     // branches)
     hipStream_t side[kMaxL - 1] = {nullptr, nullptr, nullptr};
     hipEvent_t ev_fork = nullptr;
+    hipStream_t late = nullptr;   // general mode: random-shift lines beside the rounds
+    hipEvent_t ev_late_fork = nullptr, ev_late_join = nullptr;
     hipEvent_t ev_join[kMaxL - 1] = {nullptr, nullptr, nullptr};
     sft_mlp_t mlp = nullptr;
     std::vector<sft_plan_s*> rungs;   // unknown K: plans of the smaller M, ascending (this plan is the last rung)
@@ -144,6 +146,9 @@ void release(sft_plan_s* p) {
     for (auto& st : p->side)
         if (st) (void)hipStreamDestroy(st);
     if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    if (p->late) (void)hipStreamDestroy(p->late);
+    if (p->ev_late_fork) (void)hipEventDestroy(p->ev_late_fork);
+    if (p->ev_late_join) (void)hipEventDestroy(p->ev_late_join);
     for (auto& e : p->ev_join)
         if (e) (void)hipEventDestroy(e);
     delete p;
@@ -256,11 +261,28 @@ sft_status enqueue_path(const LaunchCtx& c, const Branching* br, sft_mlp_t mlp, 
     const bool any_exact = c.n_general < c.n_sigs;
     if (events) HIPCHK(hipEventRecord(events[0], c.stream));
     HIPCHK(launch_zero_counters(c));
-    // the consecutive-shift lines (pair kernels) beside the rest (general
-    // mode's random shifts): parallel branches
+    // The consecutive-shift lines (pair kernels) and the rest: general-mode
+    // plans start the rest (their random shifts, which only the CS step
+    // reads) right after the consecutive shifts, beside the order estimate
+    // and the rounds, and join it before the CS step (started later, after the
+    // singular values or the selection, it takes the CUs of the kernel
+    // launched next and measured slower); other plans run the two as
+    // parallel branches.  Timed calls keep the stages in order.
+    bool late = false;
     if (syndrome_parts_split(c)) {
-        sft_status bs = branches(br, c, 2, [&](const LaunchCtx& ci, int b) { return launch_syndromes(ci, b); });
-        if (bs != SFT_OK) return bs;
+        if (br && br->late && c.any_general && !events) {
+            HIPCHK(launch_syndromes(c, 1));
+            HIPCHK(hipEventRecord(br->late_fork, c.stream));
+            HIPCHK(hipStreamWaitEvent(br->late, br->late_fork, 0));
+            LaunchCtx cl = c;
+            cl.stream = br->late;
+            HIPCHK(launch_syndromes(cl, 2));
+            HIPCHK(hipEventRecord(br->late_join, br->late));
+            late = true;
+        } else {
+            sft_status bs = branches(br, c, 2, [&](const LaunchCtx& ci, int b) { return launch_syndromes(ci, b); });
+            if (bs != SFT_OK) return bs;
+        }
     } else {
         HIPCHK(launch_syndromes(c));
     }
@@ -299,6 +321,7 @@ sft_status enqueue_path(const LaunchCtx& c, const Branching* br, sft_mlp_t mlp, 
             break;
         }
     }
+    if (late) HIPCHK(hipStreamWaitEvent(c.stream, br->late_join, 0));
     if (c.any_general) {
         // one branch per order: order 1 on the main stream, then the rare
         // orders 3 and 4, then order 2 (with four hardware queues per process,
@@ -344,6 +367,9 @@ sft_status enqueue(const sft_plan_s* p, hipEvent_t* events) {
         br.join[i] = p->ev_join[i];
     }
     br.fork = p->ev_fork;
+    br.late = p->late;
+    br.late_fork = p->ev_late_fork;
+    br.late_join = p->ev_late_join;
     return enqueue_path(c, &br, learned(p) ? p->mlp : nullptr, events);
 }
 
@@ -633,6 +659,11 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     HIPTRY(hipHostMalloc((void**)&p->h_cnt, ns * sizeof(SigCounters), hipHostMallocDefault));
     HIPTRY(hipEventCreateWithFlags(&p->ev_upload, hipEventDisableTiming));
     HIPTRY(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+    if (p->any_general) {
+        HIPTRY(hipStreamCreateWithFlags(&p->late, hipStreamNonBlocking));
+        HIPTRY(hipEventCreateWithFlags(&p->ev_late_fork, hipEventDisableTiming));
+        HIPTRY(hipEventCreateWithFlags(&p->ev_late_join, hipEventDisableTiming));
+    }
     for (auto& e : p->ev_join) HIPTRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     for (auto& st : p->side) HIPTRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     for (auto& e : p->ev) HIPTRY(hipEventCreate(&e));

@@ -501,10 +501,7 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
     const auto pair_lines = [&](int idx, int* pb) -> int {
         const SigDev& u = lay->sigdev[idx];
         *pb = 0;
-        // general-mode signals keep all their lines in syndrome_kernel: their
-        // R random shifts dominate the gather (one 128 B line per sample), and
-        // splitting off the consecutive shifts measured slower
-        if (fp64 || u.log2m1 != 0 || u.mode == SFT_MODE_GENERAL) return 0;
+        if (fp64 || u.log2m1 != 0) return 0;
         const int pairs = u.mode == SFT_MODE_ITERATIVE ? 1 : u.L;
         const int64_t last = lay->shifts[(size_t)u.shift_off] + 2 * pairs - 1;
         if (last >= u.d) return 0;

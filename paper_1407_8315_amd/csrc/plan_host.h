@@ -86,11 +86,18 @@ struct Branching {
     hipStream_t side[kMaxL - 1];
     hipEvent_t fork;
     hipEvent_t join[kMaxL - 1];
+    // general mode: the lines only the CS step reads (the random shifts) on
+    // a stream of their own, from after the consecutive shifts' FFTs to just
+    // before the CS step (nullptr: no such overlap)
+    hipStream_t late;
+    hipEvent_t late_fork, late_join;
 };
 
 // Enqueue the non-iterative path (exact and general signals) described by c on
 // c.stream: syndromes, order estimate or vote, decoding rounds, CS step,
 // output.  br == nullptr runs the branches of a stage in series on c.stream;
+// with br and without events, general-mode plans gather and transform the
+// random shifts beside the order estimate and the rounds;
 // mlp != nullptr gives the exact-mode signals the learned order first; events
 // (5, nullable) mark the stage boundaries.
 sft_status enqueue_path(const LaunchCtx& c, const Branching* br, sft_mlp_t mlp, hipEvent_t* events);

@@ -64,6 +64,9 @@ struct sft_plan_s {
     int4* d_synd_items = nullptr;
     int4* d_synd_small_items = nullptr;
     int n_synd_small_items = 0;
+    int4* d_synd_late_items = nullptr;
+    int4* d_synd_late_small_items = nullptr;
+    int n_synd_late_items = 0, n_synd_late_small_items = 0;
     int4* d_synd2_items = nullptr;
     int4* d_pair_items = nullptr;
     int pair_off[kPairGroups] = {};
@@ -180,6 +183,10 @@ LaunchCtx make_ctx(const sft_plan_s* p) {
     c.n_synd_items = p->n_synd_items;
     c.synd_small_items = p->d_synd_small_items;
     c.n_synd_small_items = p->n_synd_small_items;
+    c.synd_late_items = p->d_synd_late_items;
+    c.n_synd_late_items = p->n_synd_late_items;
+    c.synd_late_small_items = p->d_synd_late_small_items;
+    c.n_synd_late_small_items = p->n_synd_late_small_items;
     c.pair_items = p->d_pair_items;
     for (int g = 0; g < kPairGroups; ++g) {
         c.pair_off[g] = p->pair_off[g];
@@ -261,28 +268,21 @@ sft_status enqueue_path(const LaunchCtx& c, const Branching* br, sft_mlp_t mlp, 
     const bool any_exact = c.n_general < c.n_sigs;
     if (events) HIPCHK(hipEventRecord(events[0], c.stream));
     HIPCHK(launch_zero_counters(c));
-    // The consecutive-shift lines (pair kernels) and the rest: general-mode
-    // plans start the rest (their random shifts, which only the CS step
-    // reads) right after the consecutive shifts, beside the order estimate
-    // and the rounds, and join it before the CS step (started later, after the
-    // singular values or the selection, it takes the CUs of the kernel
-    // launched next and measured slower); other plans run the two as
-    // parallel branches.  Timed calls keep the stages in order.
-    bool late = false;
-    if (syndrome_parts_split(c)) {
-        if (br && br->late && c.any_general && !events) {
-            HIPCHK(launch_syndromes(c, 1));
-            HIPCHK(hipEventRecord(br->late_fork, c.stream));
-            HIPCHK(hipStreamWaitEvent(br->late, br->late_fork, 0));
-            LaunchCtx cl = c;
-            cl.stream = br->late;
-            HIPCHK(launch_syndromes(cl, 2));
-            HIPCHK(hipEventRecord(br->late_join, br->late));
-            late = true;
-        } else {
-            sft_status bs = branches(br, c, 2, [&](const LaunchCtx& ci, int b) { return launch_syndromes(ci, b); });
-            if (bs != SFT_OK) return bs;
-        }
+    // General mode's random-shift lines, which only the CS step reads, start
+    // on a stream of their own right after the other lines, beside the order
+    // estimate and the rounds, and join the main stream before the CS step
+    // (started later, after the singular values or the selection, they take
+    // the CUs of the kernel launched next and measured slower).  Timed calls
+    // keep the stages in order.
+    const bool late = (c.n_synd_late_items + c.n_synd_late_small_items) > 0 && br && br->late && !events;
+    if (late) {
+        HIPCHK(launch_syndromes(c, 1));
+        HIPCHK(hipEventRecord(br->late_fork, c.stream));
+        HIPCHK(hipStreamWaitEvent(br->late, br->late_fork, 0));
+        LaunchCtx cl = c;
+        cl.stream = br->late;
+        HIPCHK(launch_syndromes(cl, 2));
+        HIPCHK(hipEventRecord(br->late_join, br->late));
     } else {
         HIPCHK(launch_syndromes(c));
     }
@@ -525,6 +525,8 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     p->om_log2 = lay.om_log2;
     p->n_synd_items = (int)lay.synd_items.size();
     p->n_synd_small_items = (int)lay.synd_small_items.size();
+    p->n_synd_late_items = (int)lay.synd_late_items.size();
+    p->n_synd_late_small_items = (int)lay.synd_late_small_items.size();
     p->n_synd2_items = (int)lay.synd2_items.size();
     for (int g = 0; g < kPairGroups; ++g) {
         p->pair_off[g] = lay.pair_off[g];
@@ -589,6 +591,8 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     TRY(dalloc(p, &p->d_gram, std::max<size_t>(1, lay.gram.size())));
     TRY(dalloc(p, &p->d_synd_items, lay.synd_items.size()));
     TRY(dalloc(p, &p->d_synd_small_items, lay.synd_small_items.size()));
+    TRY(dalloc(p, &p->d_synd_late_items, lay.synd_late_items.size()));
+    TRY(dalloc(p, &p->d_synd_late_small_items, lay.synd_late_small_items.size()));
     TRY(dalloc(p, &p->d_synd2_items, lay.synd2_items.size()));
     TRY(dalloc(p, &p->d_pair_items, lay.pair_items.size()));
     TRY(dalloc(p, &p->d_line_items, lay.line_items.size()));
@@ -641,6 +645,12 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     if (!lay.synd_small_items.empty())
         HIPTRY(hipMemcpy(p->d_synd_small_items, lay.synd_small_items.data(), lay.synd_small_items.size() * sizeof(int4),
                          hipMemcpyHostToDevice));
+    if (!lay.synd_late_items.empty())
+        HIPTRY(hipMemcpy(p->d_synd_late_items, lay.synd_late_items.data(), lay.synd_late_items.size() * sizeof(int4),
+                         hipMemcpyHostToDevice));
+    if (!lay.synd_late_small_items.empty())
+        HIPTRY(hipMemcpy(p->d_synd_late_small_items, lay.synd_late_small_items.data(),
+                         lay.synd_late_small_items.size() * sizeof(int4), hipMemcpyHostToDevice));
     if (!lay.pair_items.empty())
         HIPTRY(hipMemcpy(p->d_pair_items, lay.pair_items.data(), lay.pair_items.size() * sizeof(int4),
                          hipMemcpyHostToDevice));
@@ -775,7 +785,10 @@ sft_status sft_syndromes(sft_plan_t plan, const void* x_dev, void* out_dev) {
     const SigHost& g = plan->sig[0];
     const size_t elems = g.mode == SFT_MODE_ITERATIVE ? 2 * (size_t)iter_bins_off(g.m, g.L) : (size_t)g.S * (size_t)g.m;
     const size_t bytes = elems * (plan->fp64 ? sizeof(double2) : sizeof(float2));
-    HIPCHK(hipMemcpyAsync(out_dev, plan->d_synd, bytes, hipMemcpyDeviceToDevice, plan->stream));
+    if (g.mode == SFT_MODE_ITERATIVE)
+        HIPCHK(hipMemcpyAsync(out_dev, plan->d_synd, bytes, hipMemcpyDeviceToDevice, plan->stream));
+    else
+        HIPCHK(launch_copy_syndromes(c, (int64_t)elems, out_dev));   // kept by bin: to [S][M]
     if (any_sync(plan)) HIPCHK(hipStreamSynchronize(plan->stream));
     return SFT_OK;
 }

@@ -1,11 +1,14 @@
 // Internal declarations of the sFFT-DT device library (gfx950).
 //
 // Layout in HBM (per plan; offsets are per signal and live in SigDev):
-//   syndromes  [sig][line][k]   line = shift index (2L consecutive shifts, then R
-//                               random shifts n_j), k = bin; complex float for
-//                               complex64 input, complex double for complex128.
-//                               Shift-major so that the FFT writer and the
-//                               lane-per-bin decoder both access it coalesced.
+//   syndromes  [sig][k][2L]     the 2L consecutive shifts of bin k side by side
+//                               (64 B per bin for complex64 input and L = 4),
+//                               so that the lane-per-bin decoder, which takes
+//                               bins in queue order, fetches each as one run;
+//              [sig][R][k]      general mode: the R random shifts n_j by line;
+//                               complex float for complex64 input, complex
+//                               double for complex128.  Iterative grids keep
+//                               [line][k] (synd_at()).
 //   epart      [sig][line]      sum_k |m_l[k]|^2 (FP64), for mean_k E_k
 //   sigma      [sig][k][L]      Hankel singular values (general mode)
 //   ebin       [sig][k]         E_k (general mode)
@@ -64,6 +67,9 @@ struct SigDev {
     int32_t shift_off;       // offset of the S shift values in the shift table
     int32_t tab_stride;      // omega table stride: w_d^q = tab[q * tab_stride]
     int32_t log2m1;          // two-pass FFT (M above one block): M = M1 * M2, log2 M1 (0: one pass)
+    int32_t bstride;         // syndromes of the 2L consecutive shifts by bin, [M][bstride] (bstride = 2L);
+                             // 0: every line by line, [S][M] (iterative grids)
+    int64_t rnd_off;         // general mode: element offset of the random shifts' [R][M] syndromes
     int64_t y_off;           // two-pass FFT: offset of the [S][M2][M1] intermediate
     int32_t parent;          // signal whose input and counters this entry uses (itself, or the owner of a view)
     int32_t view0;           // iterative mode: index of the view of iteration 0
@@ -72,6 +78,18 @@ struct SigDev {
     int64_t gram_off;        // general mode: offset of the signal's Gram row table F[0 .. d) (CS step)
     double tau_zero2, tau_rank, tau_res2, tau_amp, c_res, delta_grid, delta_mag;
 };
+
+// Element index of syndrome (line, k) of a unit in the syndrome buffer.  The
+// non-iterative path keeps a bin's 2L consecutive-shift syndromes side by side
+// (the kernels that follow the FFTs take one bin per lane, in queue order,
+// and fetch them as one 64-byte run); the random shifts of general mode,
+// written by one FFT block per line and read by the CS step only, and the
+// lines of iterative grids stay by line.
+__host__ __device__ inline int64_t synd_at(const SigDev& u, int line, int64_t k) {
+    if (u.bstride == 0) return u.synd_off + ((int64_t)line << u.log2m) + k;
+    if (line < u.bstride) return u.synd_off + k * u.bstride + line;
+    return u.rnd_off + ((int64_t)(line - u.bstride) << u.log2m) + k;
+}
 
 // Per-call input/output pointers of a signal.
 struct IoDev {
@@ -257,6 +275,10 @@ struct LaunchCtx {
     int n_synd_items;
     const int4* synd_small_items;   // pass 0 items of FP32 signals with M <= kFftPointsF32Small
     int n_synd_small_items;
+    const int4* synd_late_items;    // general mode's random-shift lines (pass 0), regular / small blocks
+    int n_synd_late_items;
+    const int4* synd_late_small_items;
+    int n_synd_late_small_items;
     const int4* pair_items;  // (unit, line0, 0, 0): pair_syndrome_kernel blocks, grouped by pair_group()
     int pair_off[kPairGroups];
     int pair_n[kPairGroups];
@@ -295,11 +317,11 @@ struct LaunchCtx {
 };
 
 hipError_t launch_zero_counters(const LaunchCtx& c);
-// part 0: every syndrome kernel; 1: the consecutive-shift pair kernels only;
-// 2: every other one (one-line-per-block gathers, second passes, energies)
+// sft_syndromes: unit 0's S lines into out as [S][M] (elems = S M)
+hipError_t launch_copy_syndromes(const LaunchCtx& c, int64_t elems, void* out);
+// part 0: every syndrome kernel; 1: all but the late items (general mode's
+// random-shift lines); 2: the late items only
 hipError_t launch_syndromes(const LaunchCtx& c, int part = 0);
-// true when both parts have work (they can then run as parallel branches)
-bool syndrome_parts_split(const LaunchCtx& c);
 hipError_t launch_singular_values(const LaunchCtx& c);
 hipError_t launch_select(const LaunchCtx& c);
 hipError_t launch_activity(const LaunchCtx& c);

@@ -21,15 +21,32 @@ struct V2<double> {
     using type = double2;
 };
 
-// Raw syndromes m_l[k] of the lines [0, cnt) (no de-rotation), FP64.
+// Raw syndromes m_l[k] of the lines [0, cnt) (cnt even, at most the unit's
+// 2L consecutive shifts; no de-rotation), FP64.  Kept by bin, they are one
+// contiguous run per bin: FP32 values are read as 16-byte pairs.
 template <typename T, int MAXC>
-__device__ __attribute__((always_inline)) inline void load_raw(const typename V2<T>::type* __restrict__ syn, int log2m, int64_t k, int cnt, zd* out) {
+__device__ __attribute__((always_inline)) inline void load_raw(const typename V2<T>::type* __restrict__ synd,
+                                                                const SigDev& sg, int64_t k, int cnt, zd* out) {
+    const typename V2<T>::type* __restrict__ run = synd + synd_at(sg, 0, k);
 #pragma unroll
-    for (int l = 0; l < MAXC; ++l) {
-        out[l] = zd{0.0, 0.0};
-        if (l < cnt) {
-            auto v = syn[((int64_t)l << log2m) + k];
-            out[l] = zd{(double)v.x, (double)v.y};
+    for (int l = 0; l < MAXC; ++l) out[l] = zd{0.0, 0.0};
+    if constexpr (sizeof(T) == 4) {
+        const float4* __restrict__ r4 = reinterpret_cast<const float4*>(run);
+#pragma unroll
+        for (int l = 0; l < MAXC; l += 2) {
+            if (l < cnt) {
+                const float4 v = r4[l >> 1];
+                out[l] = zd{(double)v.x, (double)v.y};
+                out[l + 1] = zd{(double)v.z, (double)v.w};
+            }
+        }
+    } else {
+#pragma unroll
+        for (int l = 0; l < MAXC; ++l) {
+            if (l < cnt) {
+                auto v = run[l];
+                out[l] = zd{(double)v.x, (double)v.y};
+            }
         }
     }
 }
@@ -40,12 +57,12 @@ __device__ __attribute__((always_inline)) inline void load_raw(const typename V2
 // in registers.
 template <typename T>
 struct RowSource {
-    const typename V2<T>::type* __restrict__ syn;   // line 0 of the random-shift lines
-    int log2m;
+    const typename V2<T>::type* __restrict__ syn;   // the bin's syndrome of the first random shift
+    int log2m;                                        // the others follow M apart
     int64_t k, n;
     const int64_t* sh;                                // n_0 .. n_{R-1}
     __device__ __attribute__((always_inline)) zd at(int j) const {
-        const auto v = syn[((int64_t)j << log2m) + k];
+        const auto v = syn[(int64_t)j << log2m];
         return cmul_conj(unit_root((k * sh[j]) & (n - 1), n), zd{(double)v.x, (double)v.y});
     }
 };
@@ -88,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void singular_values_kernel(const SigDev* _
     // unitary diagonal on both sides (e^{-i phi (i + j)} = e^{-i phi i}
     // e^{-i phi j}), which changes neither its singular values nor E_k
     zd m[2 * kMaxL];
-    load_raw<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, 2 * sg.L, m);
+    load_raw<T, 2 * kMaxL>(synd, sg, k, 2 * sg.L, m);
     double e = 0.0;
 #pragma unroll
     for (int l = 0; l < 2 * kMaxL; ++l) e += norm2(m[l]);   // zero beyond 2L
@@ -1000,7 +1017,7 @@ __global__ __launch_bounds__(kBlock) void activity_kernel(const SigDev* __restri
         if (sg.mode == kExact) {
             double e = 0.0;
             for (int l = 0; l < 2 * L; ++l) {
-                const int64_t idx = sg.synd_off + ((int64_t)l << sg.log2m) + k;
+                const int64_t idx = synd_at(sg, l, k);
                 double re, im;
                 if (synd32) {
                     float2 v = synd32[idx];
@@ -1070,7 +1087,7 @@ __global__ __launch_bounds__(kBlock) void certify_kernel(const SigDev* __restric
             const SigDev& sg = sigs[s];
             const int L = sg.L;
             zd mt[2 * kMaxL];
-            load_raw<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, 2 * L, mt);
+            load_raw<T, 2 * kMaxL>(synd, sg, k, 2 * L, mt);
             double e = 0.0;
 #pragma unroll
             for (int l = 0; l < 2 * kMaxL; ++l) e += norm2(mt[l]);   // zero beyond 2L
@@ -1122,7 +1139,7 @@ __global__ __launch_bounds__(kBlock) void svd_rank_kernel(const SigDev* __restri
             const SigDev& sg = sigs[s];
             const int L = sg.L;
             zd mt[2 * kMaxL];
-            load_raw<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, 2 * L, mt);
+            load_raw<T, 2 * kMaxL>(synd, sg, k, 2 * L, mt);
             derotate_consecutive<2 * kMaxL>(mt, k, sg.n, 2 * L);
             double sv[kMaxL];
             hankel_singular_values(mt, L, sv);
@@ -1171,7 +1188,7 @@ __global__ __launch_bounds__(kBlock, A <= 2 ? 3 : 2) void round_kernel(const Sig
             const int L = sg.L;
             const bool exact = sg.mode == kExact;
             zd mt[2 * kMaxL];
-            load_raw<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, 2 * L, mt);
+            load_raw<T, 2 * kMaxL>(synd, sg, k, 2 * L, mt);
             double e = 0.0;
 #pragma unroll
             for (int l = 0; l < 2 * kMaxL; ++l) e += norm2(mt[l]);
@@ -1252,7 +1269,7 @@ __global__ __launch_bounds__(kBlock) void rest_kernel(const SigDev* __restrict__
         const SigDev& sg = sigs[s];
         const int L = sg.L;
         zd mt[2 * kMaxL];
-        load_raw<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, 2 * L, mt);
+        load_raw<T, 2 * kMaxL>(synd, sg, k, 2 * L, mt);
         double e = 0.0;
 #pragma unroll
         for (int l = 0; l < 2 * kMaxL; ++l) e += norm2(mt[l]);
@@ -1320,10 +1337,10 @@ __global__ __launch_bounds__(kBlock) void cs_kernel(const SigDev* __restrict__ s
         const int L = sg.L;
         const int64_t* sh = shifts + sg.shift_off;
         zd mt[2 * kMaxL];
-        load_raw<T, 2 * kMaxL>(synd + sg.synd_off, sg.log2m, k, 2 * L, mt);
+        load_raw<T, 2 * kMaxL>(synd, sg, k, 2 * L, mt);
         derotate_consecutive<2 * kMaxL>(mt, k, sg.n, 2 * L);
         const int R = sg.R;
-        const RowSource<T> ysrc{synd + sg.synd_off + ((int64_t)(2 * L) << sg.log2m), sg.log2m, k, sg.n, sh + 2 * L};
+        const RowSource<T> ysrc{synd + synd_at(sg, 2 * L, k), sg.log2m, k, sg.n, sh + 2 * L};
         BinOut o;
         o.n = 0;
         const bool ok = cs_recover<A0, G>(mt, ysrc, R, sh + 2 * L, sg, tab, gram, o);

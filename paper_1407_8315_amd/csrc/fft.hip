@@ -228,15 +228,14 @@ __global__ __launch_bounds__(kBlock) void syndrome_kernel(const SigDev* __restri
 
     const T dscale = (T)sg.d;
     if (pass == 0) {
-        // scale by d, store shift-major, per-line energy (FP64, fixed-order tree)
-        V* out = synd + sg.synd_off + ((int64_t)line0 << log2m);
+        // scale by d, store, per-line energy (FP64, fixed-order tree)
         for (int line = 0; line < nl; ++line) {
             double acc = 0.0;
             for (int k = threadIdx.x; k < len; k += kBlock) {
                 V v = buf[(line << log2m) + k];
                 v.x *= dscale;
                 v.y *= dscale;
-                out[((int64_t)line << log2m) + k] = v;
+                synd[synd_at(sg, line0 + line, k)] = v;
                 acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
             }
             red[threadIdx.x] = acc;
@@ -270,7 +269,7 @@ __global__ __launch_bounds__(kBlock) void syndrome_kernel(const SigDev* __restri
             V v = buf[(line << log2len) + k1];
             v.x *= dscale;
             v.y *= dscale;
-            synd[sg.synd_off + ((int64_t)l << log2m) + k2 + ((int64_t)k1 << log2m2)] = v;
+            synd[synd_at(sg, l, k2 + ((int64_t)k1 << log2m2))] = v;
         }
     }
 }
@@ -375,22 +374,23 @@ __device__ inline void pair_rest(float2 (&v)[1 << LPT], int j, const float2* qtw
 }
 
 // One line: pass 0 (radix PT, no twiddles) on the registers, the rest through
-// LDS; stores d X[j + T s] to out and returns the energy of the line summed
-// over the P-strided lanes of the wave (fixed order).
-template <int P, int LOG2M, int LPT>
-__device__ inline double pair_line(float2 (&v)[1 << LPT], int j, const float2* qtw, float2* lds,
-                                   float2* __restrict__ out, float dscale) {
-    using F = PairFft<LOG2M, LPT>;
+// LDS; leaves X[j + T s] in v[s].
+template <int LOG2M, int LPT>
+__device__ inline void pair_fft(float2 (&v)[1 << LPT], int j, const float2* qtw, float2* lds) {
     pair_pass<LOG2M, LPT, LPT, 0, false>(v, j, qtw, lds);
     pair_rest<LOG2M, LPT, 1>(v, j, qtw, lds);
+}
+
+// Scale by d in place and return the line's energy summed over the
+// P-strided lanes of the wave (fixed order).
+template <int P, int LPT>
+__device__ inline double pair_scale_energy(float2 (&v)[1 << LPT], float dscale) {
     double acc = 0.0;
 #pragma unroll
-    for (int s = 0; s < F::PT; ++s) {
-        float2 w = v[s];
-        w.x *= dscale;
-        w.y *= dscale;
-        out[j + F::T * s] = w;
-        acc += (double)w.x * (double)w.x + (double)w.y * (double)w.y;
+    for (int s = 0; s < (1 << LPT); ++s) {
+        v[s].x *= dscale;
+        v[s].y *= dscale;
+        acc += (double)v[s].x * (double)v[s].x + (double)v[s].y * (double)v[s].y;
     }
     // lanes of the same p differ in the lane bits above log2 P
 #pragma unroll
@@ -447,11 +447,28 @@ __global__ __launch_bounds__(P * (1 << (LOG2M - LPT))) void pair_syndrome_kernel
 
     const float dscale = (float)sg.d;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    float2* __restrict__ out = synd + sg.synd_off + ((int64_t)(line0 + 2 * p) << LOG2M);
-    double acc = pair_line<P, LOG2M, LPT>(a, j, qtw, lds[p], out, dscale);
+    pair_fft<LOG2M, LPT>(a, j, qtw, lds[p]);
+    double acc = pair_scale_energy<P, LPT>(a, dscale);
     if (lane < P) red[wave][2 * lane] = acc;
-    acc = pair_line<P, LOG2M, LPT>(b, j, qtw, lds[p], out + F::M, dscale);
+    pair_fft<LOG2M, LPT>(b, j, qtw, lds[p]);
+    acc = pair_scale_energy<P, LPT>(b, dscale);
     if (lane < P) red[wave][2 * lane + 1] = acc;
+    const int line = line0 + 2 * p;
+    if (sg.bstride) {
+        // by bin: the pair's two values of bin k side by side, one 16-byte store
+        // (bstride and line even)
+        float4* __restrict__ out = reinterpret_cast<float4*>(synd + synd_at(sg, line, 0));
+#pragma unroll
+        for (int s = 0; s < F::PT; ++s)
+            out[((int64_t)(j + F::T * s) * sg.bstride) >> 1] = float4{a[s].x, a[s].y, b[s].x, b[s].y};
+    } else {
+        float2* __restrict__ out = synd + synd_at(sg, line, 0);
+#pragma unroll
+        for (int s = 0; s < F::PT; ++s) {
+            out[j + F::T * s] = a[s];
+            out[F::M + j + F::T * s] = b[s];
+        }
+    }
     __syncthreads();
     if (threadIdx.x < 2 * P) {
         double e = 0.0;
@@ -469,10 +486,9 @@ __global__ __launch_bounds__(kBlock) void line_energy_kernel(const SigDev* __res
     __shared__ double red[kBlock];
     const int2 it = items[blockIdx.x];
     const SigDev& sg = sigs[it.x];
-    const typename C2<T>::type* row = synd + sg.synd_off + ((int64_t)it.y << sg.log2m);
     double acc = 0.0;
     for (int64_t k = threadIdx.x; k < sg.m; k += kBlock) {
-        auto v = row[k];
+        auto v = synd[synd_at(sg, it.y, k)];
         acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
     }
     red[threadIdx.x] = acc;
@@ -482,6 +498,28 @@ __global__ __launch_bounds__(kBlock) void line_energy_kernel(const SigDev* __res
         __syncthreads();
     }
     if (threadIdx.x == 0) epart[sg.epart_off + it.y] = red[0];
+}
+
+// sft_syndromes: the S lines of unit 0 as [S][M], whatever the layout.
+template <typename V>
+__global__ void copy_syndromes_kernel(const SigDev* __restrict__ sigs, const V* __restrict__ synd, V* __restrict__ out) {
+    const SigDev& sg = sigs[0];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)sg.S << sg.log2m) return;
+    const int line = (int)(i >> sg.log2m);
+    const int64_t k = i & (sg.m - 1);
+    out[i] = synd[synd_at(sg, line, k)];
+}
+
+hipError_t launch_copy_syndromes(const LaunchCtx& c, int64_t elems, void* out) {
+    const int blocks = (int)((elems + kBlock - 1) / kBlock);
+    if (c.fp64)
+        hipLaunchKernelGGL(copy_syndromes_kernel<double2>, dim3(blocks), dim3(kBlock), 0, c.stream, c.sigs,
+                           (const double2*)c.synd, (double2*)out);
+    else
+        hipLaunchKernelGGL(copy_syndromes_kernel<float2>, dim3(blocks), dim3(kBlock), 0, c.stream, c.sigs,
+                           (const float2*)c.synd, (float2*)out);
+    return hipGetLastError();
 }
 
 __global__ void zero_counters_kernel(SigCounters* cnt, int n, WorkCounters* work) {
@@ -522,46 +560,44 @@ static void launch_pairs(const LaunchCtx& c) {
     launch_pair_sizes<4>(c);
 }
 
-bool syndrome_parts_split(const LaunchCtx& c) {
-    if (c.fp64) return false;
-    int pairs = 0;
-    for (int g = 0; g < kPairGroups; ++g) pairs += c.pair_n[g];
-    return pairs > 0 && (c.n_synd_small_items + c.n_synd_items + c.n_synd2_items + c.n_line_items) > 0;
+template <int PMAX>
+static void launch_f32_items(const LaunchCtx& c, const int4* items, int n) {
+    if (n)
+        hipLaunchKernelGGL((syndrome_kernel<float, PMAX, float>), dim3(n), dim3(kBlock), 0, c.stream, c.sigs, c.io, items,
+                           c.shifts, (const float2*)c.twiddle, c.tw_log2, (float2*)c.synd, (float2*)c.ybuf, c.epart,
+                           c.cnt);
+}
+
+static void launch_f64_items(const LaunchCtx& c, const int4* items, int n) {
+    // FP64 FFTs of complex128 input, or of complex64 input widened on load
+    auto k64 = c.in_fp64 ? syndrome_kernel<double, kFftPointsF64, double> : syndrome_kernel<double, kFftPointsF64, float>;
+    if (n)
+        hipLaunchKernelGGL(k64, dim3(n), dim3(kBlock), 0, c.stream, c.sigs, c.io, items, c.shifts,
+                           (const double2*)c.twiddle, c.tw_log2, (double2*)c.synd, (double2*)c.ybuf, c.epart, c.cnt);
 }
 
 hipError_t launch_syndromes(const LaunchCtx& c, int part) {
-    if (part == 1) {
-        if (!c.fp64) launch_pairs(c);
-        return hipGetLastError();
+    if (part != 1) {
+        // the late items: general mode's random-shift lines
+        if (c.fp64) {
+            launch_f64_items(c, c.synd_late_items, c.n_synd_late_items);
+        } else {
+            launch_f32_items<kFftPointsF32Small>(c, c.synd_late_small_items, c.n_synd_late_small_items);
+            launch_f32_items<kFftPointsF32>(c, c.synd_late_items, c.n_synd_late_items);
+        }
+        if (part == 2) return hipGetLastError();
     }
     if (c.fp64) {
-        // FP64 FFTs of complex128 input, or of complex64 input widened on load
-        auto k64 = c.in_fp64 ? syndrome_kernel<double, kFftPointsF64, double> : syndrome_kernel<double, kFftPointsF64, float>;
-        if (c.n_synd_items)
-            hipLaunchKernelGGL(k64, dim3(c.n_synd_items), dim3(kBlock), 0, c.stream, c.sigs, c.io, c.synd_items,
-                               c.shifts, (const double2*)c.twiddle, c.tw_log2, (double2*)c.synd, (double2*)c.ybuf,
-                               c.epart, c.cnt);
-        if (c.n_synd2_items)
-            hipLaunchKernelGGL(k64, dim3(c.n_synd2_items), dim3(kBlock), 0, c.stream, c.sigs, c.io, c.synd2_items,
-                               c.shifts, (const double2*)c.twiddle, c.tw_log2, (double2*)c.synd, (double2*)c.ybuf,
-                               c.epart, c.cnt);
+        launch_f64_items(c, c.synd_items, c.n_synd_items);
+        launch_f64_items(c, c.synd2_items, c.n_synd2_items);
         if (c.n_line_items)
             hipLaunchKernelGGL(line_energy_kernel<double>, dim3(c.n_line_items), dim3(kBlock), 0, c.stream, c.sigs,
                                c.line_items, (const double2*)c.synd, c.epart);
     } else {
-        if (part == 0) launch_pairs(c);
-        if (c.n_synd_small_items)
-            hipLaunchKernelGGL((syndrome_kernel<float, kFftPointsF32Small, float>), dim3(c.n_synd_small_items), dim3(kBlock), 0,
-                               c.stream, c.sigs, c.io, c.synd_small_items, c.shifts, (const float2*)c.twiddle,
-                               c.tw_log2, (float2*)c.synd, (float2*)c.ybuf, c.epart, c.cnt);
-        if (c.n_synd_items)
-            hipLaunchKernelGGL((syndrome_kernel<float, kFftPointsF32, float>), dim3(c.n_synd_items), dim3(kBlock), 0, c.stream,
-                               c.sigs, c.io, c.synd_items, c.shifts, (const float2*)c.twiddle, c.tw_log2,
-                               (float2*)c.synd, (float2*)c.ybuf, c.epart, c.cnt);
-        if (c.n_synd2_items)
-            hipLaunchKernelGGL((syndrome_kernel<float, kFftPointsF32, float>), dim3(c.n_synd2_items), dim3(kBlock), 0,
-                               c.stream, c.sigs, c.io, c.synd2_items, c.shifts, (const float2*)c.twiddle, c.tw_log2,
-                               (float2*)c.synd, (float2*)c.ybuf, c.epart, c.cnt);
+        launch_pairs(c);
+        launch_f32_items<kFftPointsF32Small>(c, c.synd_small_items, c.n_synd_small_items);
+        launch_f32_items<kFftPointsF32>(c, c.synd_items, c.n_synd_items);
+        launch_f32_items<kFftPointsF32>(c, c.synd2_items, c.n_synd2_items);
         if (c.n_line_items)
             hipLaunchKernelGGL(line_energy_kernel<float>, dim3(c.n_line_items), dim3(kBlock), 0, c.stream, c.sigs,
                                c.line_items, (const float2*)c.synd, c.epart);

@@ -158,7 +158,7 @@ __device__ inline void bin_features(const V* __restrict__ synd, const SigDev& sg
     float e = 0.0f;
 #pragma unroll
     for (int l = 0; l < 8; ++l) {
-        const auto v = synd[sg.synd_off + ((int64_t)l << sg.log2m) + k];
+        const auto v = synd[synd_at(sg, l, k)];
         const int64_t q = (k * l) & (sg.n - 1);
         float sn, cs;
         sincospif((float)(2.0 * (double)q / (double)sg.n), &sn, &cs);

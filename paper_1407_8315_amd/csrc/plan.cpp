@@ -298,6 +298,8 @@ SigDev sigdev_of(const SigHost& g, int64_t dmax, bool fp64) {
     s.stage_cap = (int32_t)(g.m * g.L);
     s.tab_stride = (int32_t)(dmax / g.d);
     s.log2m1 = g.m > pmax ? (ilog2(g.m) + 1) / 2 : 0;   // M1 = 2^ceil(log2 M / 2)
+    s.bstride = g.mode == SFT_MODE_ITERATIVE ? 0 : 2 * g.L;   // by bin (iterative grids: by line)
+    s.rnd_off = (int64_t)g.m * 2 * g.L;                         // relative to synd_off; build_layout adds it
     s.view0 = -1;
     s.tau_zero2 = g.tau_zero * g.tau_zero;
     s.tau_rank = g.tau_rank;
@@ -393,6 +395,7 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
         SigDev& s = lay->sigdev[i];
         s = sigdev_of(g, dmax, fp64);
         s.synd_off = synd;
+        s.rnd_off += synd;
         s.epart_off = ep;
         s.bin_off = bins;
         s.stage_off = stage;
@@ -438,6 +441,7 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
             v.shift_off = lay->sigdev[i].shift_off + 2 * l;
             v.tab_stride = (int32_t)(dmax / v.d);
             v.log2m1 = v.m > pmax ? (v.log2m + 1) / 2 : 0;
+            v.bstride = 0;   // grids of iterative signals: by line
             v.y_off = ybuf;
             if (v.m > pmax) ybuf += 2 * (int64_t)v.m;
             v.view0 = -1;
@@ -524,38 +528,46 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
             int4{-1, 0, 0, 0}, lay->pair_items);
         lay->pair_n[g] = (int)lay->pair_items.size() - lay->pair_off[g];
     }
-    interleave(
-        [&](int s, std::vector<int4>& v) {
-            for_units(s, [&](int idx, int64_t m, int S, int lm1) {
-                (void)lm1;
-                if (!small(m)) return;
-                int pb = 0;
-                const int first = pair_lines(idx, &pb);
-                const int nl = fft_lines_per_block(m, S - first, fp64, nullptr);
-                for (int l0 = first; l0 < S; l0 += nl) v.push_back(int4{idx, l0, std::min(nl, S - l0), 0});
-            });
-        },
-        int4{-1, 0, 0, 0}, lay->synd_small_items);
-    interleave(
-        [&](int s, std::vector<int4>& v) {
-            for_units(s, [&](int idx, int64_t m, int S, int lm1) {
-                if (small(m)) return;
-                if (m <= pmax) {
-                    int pb = 0;
-                    const int first = pair_lines(idx, &pb);
-                    const int nl = fft_lines_per_block(m, S - first, fp64, nullptr);
-                    for (int l0 = first; l0 < S; l0 += nl) v.push_back(int4{idx, l0, std::min(nl, S - l0), 0});
-                } else {
-                    // first of two passes: S * M1 lines of length M2
-                    const int lm2 = ilog2(m) - lm1;
-                    const int64_t lines = (int64_t)S << lm1;
-                    const int nl = (int)std::min<int64_t>(lines, pmax >> lm2);
-                    for (int64_t l0 = 0; l0 < lines; l0 += nl)
-                        v.push_back(int4{idx, (int)l0, (int)std::min<int64_t>(nl, lines - l0), 1});
-                }
-            });
-        },
-        int4{-1, 0, 0, 0}, lay->synd_items);
+    // One-pass items cover [first, S) in chunks of nl lines, cut at 2L in
+    // general mode: the R random shifts (lines 2L .. S-1, read by the CS
+    // step only) form the `late` lists, which the launcher may run beside
+    // the order estimate and the rounds; everything else comes first.
+    const auto one_pass_items = [&](int idx, int64_t m, int S, bool late, std::vector<int4>& v) {
+        int pb = 0;
+        const int first = pair_lines(idx, &pb);
+        const bool general = lay->sigdev[idx].mode == SFT_MODE_GENERAL;
+        const int cut = general ? 2 * lay->sigdev[idx].L : S;
+        const int lo = late ? std::max(first, cut) : first, hi = late ? S : std::max(first, cut);
+        const int nl = fft_lines_per_block(m, hi - lo, fp64, nullptr);
+        for (int l0 = lo; l0 < hi; l0 += nl) v.push_back(int4{idx, l0, std::min(nl, hi - l0), 0});
+    };
+    for (int late = 0; late < 2; ++late) {
+        interleave(
+            [&](int s, std::vector<int4>& v) {
+                for_units(s, [&](int idx, int64_t m, int S, int lm1) {
+                    (void)lm1;
+                    if (small(m)) one_pass_items(idx, m, S, late, v);
+                });
+            },
+            int4{-1, 0, 0, 0}, late ? lay->synd_late_small_items : lay->synd_small_items);
+        interleave(
+            [&](int s, std::vector<int4>& v) {
+                for_units(s, [&](int idx, int64_t m, int S, int lm1) {
+                    if (small(m)) return;
+                    if (m <= pmax) {
+                        one_pass_items(idx, m, S, late, v);
+                    } else if (!late) {
+                        // first of two passes: S * M1 lines of length M2
+                        const int lm2 = ilog2(m) - lm1;
+                        const int64_t lines = (int64_t)S << lm1;
+                        const int nl = (int)std::min<int64_t>(lines, pmax >> lm2);
+                        for (int64_t l0 = 0; l0 < lines; l0 += nl)
+                            v.push_back(int4{idx, (int)l0, (int)std::min<int64_t>(nl, lines - l0), 1});
+                    }
+                });
+            },
+            int4{-1, 0, 0, 0}, late ? lay->synd_late_items : lay->synd_items);
+    }
     interleave(
         [&](int s, std::vector<int4>& v) {
             for_units(s, [&](int idx, int64_t m, int S, int lm1) {

@@ -28,6 +28,8 @@ struct PlanLayout {
     std::vector<double2> gram;            // Gram row tables of the general-mode shift sets
     std::vector<int4> synd_items;         // (sig, line0, nlines, pass 0|1); sig < 0 = padding
     std::vector<int4> synd_small_items;   // one-pass FP32 signals with M <= kFftPointsF32Small
+    std::vector<int4> synd_late_items;    // general mode: the random-shift lines (read by the CS step only)
+    std::vector<int4> synd_late_small_items;
     std::vector<int4> synd2_items;        // (sig, line0, nlines, 2): second FFT pass
     std::vector<int4> pair_items;         // (unit, line0, 0, 0) of pair_syndrome_kernel, by group
     int pair_off[kPairGroups] = {};

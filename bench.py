@@ -11,8 +11,9 @@ over the batch, divided by the step time), with signals/s beside it.
 Two timed regions on the plan's stream:
   1. K graph-replayed steps bracketed by synchronisation -> value, ms/step;
   2. K steps with per-stage HIP events (same kernels and launch shapes, not
-     graph-replayed) -> average duration of the gather+FFT stage and the
-     decode stage, from which the roofline figures are computed.
+     graph-replayed) -> average duration of each stage, and of the dominant
+     kernel of the gather+FFT stage on its own, from which the roofline
+     figures are computed.
 The oracle (FP64 numpy, one host thread) is timed on a bounded sample.
 """
 from __future__ import annotations
@@ -31,11 +32,13 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector, published
 BF16_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 MFMA, published
 
-# HBM bytes of the gather + FFT kernel (syndrome_kernel<float, 4096, float>) per
-# algorithmic byte read and written, from rocprofv3 FETCH_SIZE / WRITE_SIZE
-# scaled by the plain-copy calibration (profiles/syndrome_kernel_n20_b1024_traffic.md,
-# profiles/syndrome_kernel_iterative_n20_b1024_traffic.md).
-TRAFFIC_RATIOS = {"exact": (2.01, 1.00), "general": (7.98, 1.00), "iterative": (5.27, 1.00)}
+# HBM bytes of the dominant gather + FFT kernel per algorithmic byte read and
+# written (fetched, written), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by
+# the plain-copy calibration (profiles/syndrome_kernel_random_shifts_general_n20_b1024_traffic.md,
+# profiles/pair_syndrome_kernel_exact_n20_b1024_traffic.md,
+# profiles/pair_syndrome_kernel_iterative_n20_b1024_traffic.md).  A kernel
+# changed since its counters were taken gets no entry (its traffic is null).
+TRAFFIC_RATIOS = {"general": (12.50, 1.00), "exact": (2.05, 1.18), "iterative": (8.03, 1.00)}
 
 # Algorithmic FLOPs of the order predictor per row (matrix products only):
 # forward 2 (32*128 + 128*128 + 128*5); training adds the three weight
@@ -63,6 +66,8 @@ def parse():
     ap.add_argument("--fft64", action="store_true", help="FP64 FFTs for the complex64 input (SFT_FLAG_FFT64)")
     ap.add_argument("--no-model", action="store_true", help="skip the recovery-vs-collision-model section")
     ap.add_argument("--no-large", action="store_true", help="skip the N = 2^24 section")
+    ap.add_argument("--only-large", type=int, choices=[10, 12, 14], default=None, metavar="LOG2K",
+                    help="run only the N = 2^24 section at K = 2^LOG2K and print it (for profiling)")
     ap.add_argument("--paper-tables", action="store_true",
                     help="also run Alg. 2 as printed on the Tables II-IV workload (N = 2^24, mixture Gaussian)")
     return ap.parse_args()
@@ -492,7 +497,7 @@ def main():
     n, k, m, L, R = 1 << 20, 1000, 4096, 4, 12
     snrs = [10, 20, 30, 40]
     cpu = None
-    if not a.no_cpu and not a.copy_calibration:
+    if not a.no_cpu and not a.copy_calibration and a.only_large is None:
         # on the host, before anything initialises the GPU
         cpu = cpu_baseline(n, k, m, L, R, a.mode, a.cpu_seconds, snrs)
 
@@ -503,6 +508,10 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if a.only_large is not None:
+        b = {10: 256, 12: 64, 14: 32}[a.only_large]
+        print(json.dumps({"large_scale_n24": large_scale(a.steps, a.warmup, batches=((a.only_large, b),))}))
+        return
     if a.copy_calibration:
         src = torch.empty(1 << 27, dtype=torch.complex64, device=dev)   # 1 GiB
         dst = torch.empty_like(src)
@@ -553,11 +562,14 @@ def main():
             found += len(np.intersect1d(loc, t))
         # ---- timed region 2: per-stage HIP events
         stage = np.zeros(4)
+        gather = np.zeros(2)
         st = None
         for _ in range(a.steps):
             st = run(stats=True)
             stage += np.array(st["stage_ms"])
+            gather += np.array(st["gather_ms"])
         stage /= a.steps
+        gather /= a.steps
     signals_per_s = B / (ms_step * 1e-3)
     freqs_per_s = found / (ms_step * 1e-3)
     recovery = found / (B * k)
@@ -565,17 +577,33 @@ def main():
     # samples gathered (= syndromes written) per signal: 2L (+ R) lines of M;
     # iterative: two lines per iteration on grids of M, M/2, ...
     samples = 2 * sum(m >> l for l in range(L)) if mode == "iterative" else (2 * L + (R if mode == "general" else 0)) * m
-    synd_bytes = B * samples * 8 * (3 if a.fft64 else 2)   # gather read (8 B) + syndrome write (8 or 16 B)
-    fft_gbs = synd_bytes / (stage[0] * 1e-3) / 1e9
+    per_sample = 8 + (16 if a.fft64 else 8)                # gather read (complex64) + syndrome write
+    stage_gbs = B * samples * per_sample / (stage[0] * 1e-3) / 1e9
+    # the dominant kernel of the gather + FFT stage, timed on its own (HIP
+    # events around it on the plan's stream): general mode the R random-shift
+    # lines, exact mode the 2L consecutive shifts (one pair kernel per call);
+    # iterative mode the whole stage (pair kernels of the L grid sizes)
+    if mode == "general":
+        k_samples, k_ms = R * m, gather[1]
+        k_name = f"syndrome_kernel<{'double' if a.fft64 else 'float'}, 4096, float> (gather + FFT of the R random shifts)"
+    elif mode == "exact":
+        k_samples, k_ms = 2 * L * m, gather[0]
+        k_name = ("syndrome_kernel<double, 4096, float>" if a.fft64 else "pair_syndrome_kernel<1, 12, 3>") \
+            + " (gather + FFT of the 2L consecutive shifts)"
+    else:
+        k_samples, k_ms = samples, stage[0]
+        k_name = "pair_syndrome_kernel<1, LOG2M, 3>, LOG2M = 12..9 (gather + FFT of every iteration's lines)"
+    k_bytes = B * k_samples * per_sample
+    k_gbs = k_bytes / (k_ms * 1e-3) / 1e9
     ratios = None if a.fft64 else TRAFFIC_RATIOS.get(mode)
-    # measured HBM bytes per launch (fetch + write), when counters were taken for this mode
-    traffic = int(B * samples * 8 * (ratios[0] + ratios[1])) if ratios else None
-    roofline = {"bound": "hbm", "achieved": round(fft_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(fft_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "traffic_gbs": round(traffic / (stage[0] * 1e-3) / 1e9, 1) if traffic else None,
-                "kernel": "syndrome_kernel<double, 4096, float> (gather + FFT)" if a.fft64
-                else "syndrome_kernel<float, 4096, float> (gather + FFT)",
-                "algorithmic_bytes_per_launch": synd_bytes, "avg_launch_ms": round(stage[0], 4)}
+    # measured HBM bytes per launch (fetch + write), when counters were taken for this kernel
+    traffic = int(B * k_samples * 8 * (ratios[0] + ratios[1])) if ratios else None
+    roofline = {"bound": "hbm", "achieved": round(k_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(k_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_gbs": round(traffic / (k_ms * 1e-3) / 1e9, 1) if traffic else None,
+                "kernel": k_name, "algorithmic_bytes_per_launch": k_bytes, "avg_launch_ms": round(k_ms, 4),
+                "stage": {"achieved": round(stage_gbs, 1), "frac": round(stage_gbs / HBM_PEAK_GBS, 4),
+                          "algorithmic_bytes": B * samples * per_sample, "avg_ms": round(stage[0], 4)}}
 
     for i, o in enumerate(outs[:a.parity_signals]):
         o.truth = (truth[i], tvals[i])
@@ -610,7 +638,8 @@ def main():
         "signals_per_s": round(signals_per_s, 1),
         "support_recovery": round(recovery, 5),
         "stage_ms": [round(v, 4) for v in stage],
-        "stats_last_step": {kk: v for kk, v in st.items() if kk != "stage_ms"} if st else None,
+        "gather_ms": [round(v, 4) for v in gather],
+        "stats_last_step": {kk: v for kk, v in st.items() if kk not in ("stage_ms", "gather_ms")} if st else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": parity,

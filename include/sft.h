@@ -134,6 +134,9 @@ typedef struct sft_stats {
     int64_t nonfinite;          /* non-finite gathered samples (SFT_FLAG_CHECK_FINITE) */
     double stage_ms[4];         /* gather+FFT, order estimate/vote, decode, output (HIP events);
                                    iterative: gather+FFT, iteration 0, iterations 1.., output */
+    double gather_ms[2];        /* the gather+FFT stage in two parts (HIP events): every line but
+                                   general mode's random shifts n_j, then those (0 without them);
+                                   -1 in both stage fields when not timed */
 } sft_stats;
 
 /* What a plan chose for one signal; the oracle consumes exactly these. */

@@ -49,11 +49,13 @@ class Stats(ctypes.Structure):
         ("active_bins", ctypes.c_int64), ("flagged_bins", ctypes.c_int64), ("cs_bins", ctypes.c_int64),
         ("mlp_fallbacks", ctypes.c_int64), ("entries", ctypes.c_int64), ("overflowed", ctypes.c_int64),
         ("nonfinite", ctypes.c_int64), ("stage_ms", ctypes.c_double * 4),
+        ("gather_ms", ctypes.c_double * 2),
     ]
 
     def as_dict(self):
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "stage_ms"}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("stage_ms", "gather_ms")}
         d["stage_ms"] = list(self.stage_ms)
+        d["gather_ms"] = list(self.gather_ms)
         return d
 
 

@@ -101,7 +101,9 @@ struct sft_plan_s {
     SigCounters* h_cnt = nullptr;
     hipEvent_t ev_upload = nullptr;
     bool upload_pending = false;
-    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    // stage boundaries of timed calls; ev[5]: between the consecutive-shift
+    // and the random-shift gathers
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     // branches for independent kernels of one stage (the orders of a round,
@@ -266,8 +268,8 @@ static sft_status branches(const Branching* br, const LaunchCtx& c, int n, Fn fn
 sft_status enqueue_path(const LaunchCtx& c, const Branching* br, sft_mlp_t mlp, hipEvent_t* events) {
     const bool use_mlp = mlp != nullptr;
     const bool any_exact = c.n_general < c.n_sigs;
-    if (events) HIPCHK(hipEventRecord(events[0], c.stream));
     HIPCHK(launch_zero_counters(c));
+    if (events) HIPCHK(hipEventRecord(events[0], c.stream));
     // General mode's random-shift lines, which only the CS step reads, start
     // on a stream of their own right after the other lines, beside the order
     // estimate and the rounds, and join the main stream before the CS step
@@ -283,6 +285,11 @@ sft_status enqueue_path(const LaunchCtx& c, const Branching* br, sft_mlp_t mlp, 
         cl.stream = br->late;
         HIPCHK(launch_syndromes(cl, 2));
         HIPCHK(hipEventRecord(br->late_join, br->late));
+    } else if (events && c.n_synd_late_items + c.n_synd_late_small_items > 0) {
+        // timed: the random-shift lines after the others, each part timed
+        HIPCHK(launch_syndromes(c, 1));
+        HIPCHK(hipEventRecord(events[5], c.stream));
+        HIPCHK(launch_syndromes(c, 2));
     } else {
         HIPCHK(launch_syndromes(c));
     }
@@ -348,8 +355,8 @@ sft_status enqueue(const sft_plan_s* p, hipEvent_t* events) {
     if (p->iterative) {
         // Alg. 1: the FFTs of every iteration in one stage (they depend on x
         // only), then the iterations in order, then the output pass
-        if (events) HIPCHK(hipEventRecord(events[0], p->stream));
         HIPCHK(launch_zero_counters(c));
+        if (events) HIPCHK(hipEventRecord(events[0], p->stream));
         HIPCHK(launch_syndromes(c));
         if (events) HIPCHK(hipEventRecord(events[1], p->stream));
         for (int l = 0; l < p->max_l; ++l) {
@@ -414,12 +421,24 @@ sft_status finish(sft_plan_s* p, sft_stats* st, bool timed) {
         if (c.kept > p->h_io[i].cap) s.overflowed += 1;
     }
     for (int i = 0; i < 4; ++i) s.stage_ms[i] = -1.0;
-    if (timed)
+    s.gather_ms[0] = s.gather_ms[1] = -1.0;
+    if (timed) {
         for (int i = 0; i < 4; ++i) {
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, p->ev[i], p->ev[i + 1]));
             s.stage_ms[i] = ms;
         }
+        if (!p->iterative && p->n_synd_late_items + p->n_synd_late_small_items > 0) {
+            float a = 0.f, b = 0.f;
+            HIPCHK(hipEventElapsedTime(&a, p->ev[0], p->ev[5]));
+            HIPCHK(hipEventElapsedTime(&b, p->ev[5], p->ev[1]));
+            s.gather_ms[0] = a;
+            s.gather_ms[1] = b;
+        } else {
+            s.gather_ms[0] = s.stage_ms[0];
+            s.gather_ms[1] = 0.0;
+        }
+    }
     if (st) *st = s;
     if (s.nonfinite > 0) {
         bool check = false;

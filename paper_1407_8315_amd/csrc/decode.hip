@@ -267,20 +267,26 @@ __device__ void block_rank(KeyFn key, int n, RankLds& S, const RankScratch& g) {
     }
 }
 
-// LDS of block_radix_select: the candidates' keys and indices, the indices
-// of the final ties, the digit histogram (kRadixCopies copies, lanes spread
-// over them, so that keys of one digit contend less), the per-wave partials
-// of the common-prefix pass and the broadcast scalars (37 KB, so that four
-// blocks of kRankThreads share a CU's 160 KB).
+// LDS of block_radix_select: the keys and indices of up to CH candidates,
+// the indices of the final ties, the digit histogram (kRadixCopies copies,
+// lanes spread over them, so that keys of one digit contend less), the
+// per-wave partials of the common-prefix pass and the broadcast scalars
+// (37 KB for CH = 2048, so that four blocks of kRankThreads share a CU's
+// 160 KB).
 constexpr int kRadixCopies = 4;
-struct RadixLds {
-    unsigned long long key[kRankChunk];
-    int idx[kRankChunk];
-    int tie[kRankChunk];
+template <int CH>
+struct RadixLdsT {
+    unsigned long long key[CH];
+    int idx[CH];
+    int tie[CH];
     int hist[kRadixCopies * 256];
     unsigned long long kor[kRankThreads / 64], kand[kRankThreads / 64];
     int sel_digit, sel_rr, n_cand, pick;
 };
+using RadixLds = RadixLdsT<kRankChunk>;
+// candidates the selection kernel gathers into LDS (20 KB in all: its blocks
+// still fit beside four blocks of the gather + FFT kernel on one CU)
+constexpr int kSelChunk = 1024;
 
 // Index of the key of ascending rank r (0 <= r < n) in the order (ukey(i), i),
 // by radix selection on the 64-bit keys, 8 bits per pass: each pass counts
@@ -291,8 +297,8 @@ struct RadixLds {
 // there and the remaining passes run on LDS.  Ties of the full key go to the
 // lower index.  Whole block of kRankThreads; the result is the same element a
 // full sort would give.
-template <typename UKeyFn>
-__device__ int block_radix_select(UKeyFn ukey, int n, int r, RadixLds& S) {
+template <typename UKeyFn, int CH>
+__device__ int block_radix_select(UKeyFn ukey, int n, int r, RadixLdsT<CH>& S) {
     int* hist = S.hist;
     int& sel_digit = S.sel_digit;
     int& sel_rr = S.sel_rr;
@@ -330,7 +336,7 @@ __device__ int block_radix_select(UKeyFn ukey, int n, int r, RadixLds& S) {
     bool in_lds = false;
     int nc = n;   // candidates
     for (int shift = first; shift >= 0; shift -= 8) {
-        if (!in_lds && nc <= kRankChunk) {
+        if (!in_lds && nc <= CH) {
             // gather the candidates, one LDS atomic per wave (ascending index
             // order is not kept: ties are resolved by index below)
             if (threadIdx.x == 0) n_cand = 0;
@@ -444,7 +450,7 @@ __device__ int block_radix_select(UKeyFn ukey, int n, int r, RadixLds& S) {
             if (below == rr) pick = v;
         }
     } else {
-        // more than kRankChunk keys equal the selected one: count them per
+        // more than CH keys equal the selected one: count them per
         // contiguous chunk of indices, then the chunk holding rank rr finds it
         const int C = (n + blockDim.x - 1) / blockDim.x;
         const int lo = min(n, (int)threadIdx.x * C), hi = min(n, lo + C);
@@ -487,7 +493,7 @@ __global__ __launch_bounds__(kRankThreads) void select_kernel(const SigDev* __re
                                                               const double* __restrict__ sigma,
                                                               const double* __restrict__ ebin, SelDev* __restrict__ sel,
                                                               double* rk_a, long long* rk_b, int* rk_i, int* rk_r) {
-    __shared__ RadixLds S;
+    __shared__ RadixLdsT<kSelChunk> S;
     const int s = gsigs[blockIdx.x];
     const SigDev& sg = sigs[s];
     const int nv = sg.m * sg.L;

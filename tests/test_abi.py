@@ -57,7 +57,7 @@ def test_struct_layouts_match_c(tmp_path):
 int main(void) {
   printf("%zu %zu %zu %zu\\n", sizeof(sft_params), sizeof(sft_sparse_out), sizeof(sft_stats), sizeof(sft_plan_info));
   printf("%zu %zu %zu\\n", offsetof(sft_params, seed), offsetof(sft_params, delta_mag), offsetof(sft_plan_info, rshifts));
-  printf("%zu %zu\\n", offsetof(sft_plan_info, tau_zero), offsetof(sft_stats, stage_ms));
+  printf("%zu %zu %zu\\n", offsetof(sft_plan_info, tau_zero), offsetof(sft_stats, stage_ms), offsetof(sft_stats, gather_ms));
   return 0;
 }
 """)
@@ -67,7 +67,8 @@ int main(void) {
     got = list(map(int, out))
     want = [ctypes.sizeof(_lib.Params), ctypes.sizeof(_lib.SparseOut), ctypes.sizeof(_lib.Stats),
             ctypes.sizeof(_lib.PlanInfo), _lib.Params.seed.offset, _lib.Params.delta_mag.offset,
-            _lib.PlanInfo.rshifts.offset, _lib.PlanInfo.tau_zero.offset, _lib.Stats.stage_ms.offset]
+            _lib.PlanInfo.rshifts.offset, _lib.PlanInfo.tau_zero.offset, _lib.Stats.stage_ms.offset,
+            _lib.Stats.gather_ms.offset]
     assert got == want
 
 

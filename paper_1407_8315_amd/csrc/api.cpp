@@ -307,7 +307,9 @@ sft_status enqueue_path(const LaunchCtx& c, const Branching* br, sft_mlp_t mlp, 
         if (use_mlp) {
             sft_status s = sft_mlp_launch_infer(mlp, c);
             if (s != SFT_OK) return s;
-            HIPCHK(launch_svd_rank(c, q_round(0, 0), 0));
+            // bins without a predicted order: in plans with general-mode
+            // signals the SVD pass now, otherwise the rest kernel's rank test
+            if (c.n_general > 0) HIPCHK(launch_svd_rank(c, q_round(0, 0), 0));
         } else {
             HIPCHK(launch_svd_rank(c, kQPending, 0));
         }
@@ -320,7 +322,8 @@ sft_status enqueue_path(const LaunchCtx& c, const Branching* br, sft_mlp_t mlp, 
         sft_status bs = branches(br, c, n_orders, [&](const LaunchCtx& ci, int a) { return launch_round(ci, r, a); });
         if (bs != SFT_OK) return bs;
         // bins whose learned order failed: rank test, then on with round 1
-        if (r == 0 && use_mlp && c.max_l > 1) HIPCHK(launch_svd_rank(c, q_round(1, 0), 1));
+        // (without general-mode signals the rest kernel runs it itself)
+        if (r == 0 && use_mlp && c.max_l > 1 && c.n_general > 0) HIPCHK(launch_svd_rank(c, q_round(1, 0), 1));
         // without general-mode signals, the few bins left after round 0 of orders 1
         // and 2 finish in one kernel
         if (r == 0 && c.n_general == 0 && c.max_l > 1) {

@@ -1235,10 +1235,12 @@ __global__ __launch_bounds__(kBlock, A <= 2 ? 3 : 2) void round_kernel(const Sig
 
 // Plans without general-mode signals finish in one kernel what few bins
 // remain after round 0 of orders 1 and 2: the bins of round 0 whose first
-// order is 3 or 4 (set 0, slots 3..4) and those of the later rounds (set 1,
-// slots 1..4).  Each bin tries its remaining orders in turn (same sequence,
-// same judge), is emitted at the first accepted one and flagged when none is
-// left.
+// order is 3 or 4 (set 0, slots 3..4), those of the later rounds (set 1,
+// slots 1..4) and, in learned plans, the bins still without a rank order
+// (set 1, slot 0: a failed predicted order, or no prediction), which take the
+// rank test here first.  Each bin tries its remaining orders in turn (same
+// sequence, same judge), is emitted at the first accepted one and flagged
+// when none is left.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void rest_kernel(const SigDev* __restrict__ sigs,
                                                       const typename V2<T>::type* __restrict__ synd,
@@ -1247,8 +1249,9 @@ __global__ __launch_bounds__(kBlock) void rest_kernel(const SigDev* __restrict__
                                                       const WorkCounters* __restrict__ work,
                                                       const int2* __restrict__ qlist, int64_t list_cap) {
     // the queues as one index space
-    constexpr int kSeg = 2 + kMaxL;
-    const int qs[kSeg] = {q_round(0, 3), q_round(0, 4), q_round(1, 1), q_round(1, 2), q_round(1, 3), q_round(1, 4)};
+    constexpr int kSeg = 3 + kMaxL;
+    const int qs[kSeg] = {q_round(0, 3), q_round(0, 4), q_round(1, 0), q_round(1, 1),
+                          q_round(1, 2), q_round(1, 3), q_round(1, 4)};
     int start[kSeg + 1];
     start[0] = 0;
 #pragma unroll
@@ -1285,8 +1288,8 @@ __global__ __launch_bounds__(kBlock) void rest_kernel(const SigDev* __restrict__
         bool done = false;
         int r0 = a0;
         for (int step = code_step(code); step < L && !done; ++step) {
-            if (step > 0 && r0 == 0) {
-                // a learned order failed and the rank test has not run yet
+            if (r0 == 0) {
+                // no rank order yet (learned plans): the rank test
                 if (rank_one_certified(mt, L, sg.tau_rank)) {
                     r0 = 1;
                 } else {

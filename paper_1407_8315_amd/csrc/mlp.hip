@@ -5,7 +5,8 @@
 // estimate of Pruning Step 1, Sec. III-C.)
 //
 // Network 32 -> 128 -> 128 -> 5 with GELU, BF16 weights, FP32 accumulation on
-// v_mfma_f32_16x16x16_bf16.  A block holds 64 rows (bins) in LDS; each of its
+// gfx950's v_mfma_f32_16x16x32_bf16 (v_mfma_f32_16x16x16_bf16 for the one
+// product with 16-long sums, dZ3 W3).  A block holds 64 rows (bins) in LDS; each of its
 // 4 waves owns 16 rows in the forward pass and in the input-side backward pass;
 // weight gradients reduce over the block's rows with MFMA and are added to a
 // global FP32 buffer.  Adam updates FP32 master weights and refreshes the BF16
@@ -24,13 +25,17 @@ namespace sft {
 constexpr int kNF = 32, kNH = 128, kNC = 5, kNCp = 16;
 constexpr int kOffW1 = 0, kOffB1 = 4096, kOffW2 = 4224, kOffB2 = 20608, kOffW3 = 20736, kOffB3 = 21376;
 constexpr int kNParams = 21381;
-constexpr int kLdX = 36, kLdH = 132, kLdC = 20;   // padded LDS row strides (bf16 / float elements)
+// padded LDS row strides (bf16 / float elements); rows of X and H start on
+// 16-byte boundaries for the 8-element operand loads
+constexpr int kLdX = 40, kLdH = 136, kLdC = 20;
 constexpr int kRows = 64;                          // rows per block tile
 // BF16 weight image (same padded layout in global memory and LDS)
 constexpr int kW1Elems = kNH * kLdX, kW2Elems = kNH * kLdH, kW3Elems = kNCp * kLdH;
 constexpr int kWElems = kW1Elems + kW2Elems + kW3Elems;
 
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef unsigned short bf16;
 
@@ -67,8 +72,21 @@ __device__ inline float gelu_grad(float x) {
     const PhiPdf q = phi_pdf(x);
     return q.cdf + x * q.pdf;
 }
+// D (16 x 16, FP32) += A B over K = 16 or 32: lane l supplies row l % 16 of
+// A and column l % 16 of B at the K positions of its lane group l / 16 (4 or
+// 8 consecutive ones, the same for A and B), and holds D[4 (l / 16) + j][l % 16].
 __device__ inline v4f mfma16(v4s a, v4s b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
+__device__ inline v4f mfma32(v8s a, v8s b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+}
 __device__ inline v4s ld4(const bf16* p) { return *reinterpret_cast<const v4s*>(p); }
+__device__ inline v8s ld8(const bf16* p) { return *reinterpret_cast<const v8s*>(p); }
+__device__ inline v8s gather8(const bf16* p, int stride) {
+    v8s r;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) r[i] = (short)p[i * stride];
+    return r;
+}
 __device__ inline v4s gather4(const bf16* p, int stride) {
     v4s r;
     r.x = (short)p[0];
@@ -79,7 +97,7 @@ __device__ inline v4s gather4(const bf16* p, int stride) {
 }
 
 struct alignas(16) WeightsLds {
-    bf16 w[kWElems];                   // W1 [128][36], W2 [128][132], W3 [16][132]
+    bf16 w[kWElems];                   // W1 [128][40], W2 [128][136], W3 [16][136]
     float b1[kNH], b2[kNH], b3[kNCp];
 };
 
@@ -110,10 +128,10 @@ __device__ inline void forward_rows(const WeightsLds& W, const bf16* X, bf16* H1
 #pragma unroll
     for (int t = 0; t < 8; ++t) f.z1[t] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kk = 0; kk < kNF / 16; ++kk) {
-        v4s a = ld4(X + (r0 + li) * kLdX + kk * 16 + lq * 4);
+    for (int kk = 0; kk < kNF / 32; ++kk) {
+        v8s a = ld8(X + (r0 + li) * kLdX + kk * 32 + lq * 8);
 #pragma unroll
-        for (int t = 0; t < 8; ++t) f.z1[t] = mfma16(a, ld4(w1 + (t * 16 + li) * kLdX + kk * 16 + lq * 4), f.z1[t]);
+        for (int t = 0; t < 8; ++t) f.z1[t] = mfma32(a, ld8(w1 + (t * 16 + li) * kLdX + kk * 32 + lq * 8), f.z1[t]);
     }
 #pragma unroll
     for (int t = 0; t < 8; ++t)
@@ -127,10 +145,10 @@ __device__ inline void forward_rows(const WeightsLds& W, const bf16* X, bf16* H1
 #pragma unroll
     for (int t = 0; t < 8; ++t) f.z2[t] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kk = 0; kk < kNH / 16; ++kk) {
-        v4s a = ld4(H1 + (r0 + li) * kLdH + kk * 16 + lq * 4);
+    for (int kk = 0; kk < kNH / 32; ++kk) {
+        v8s a = ld8(H1 + (r0 + li) * kLdH + kk * 32 + lq * 8);
 #pragma unroll
-        for (int t = 0; t < 8; ++t) f.z2[t] = mfma16(a, ld4(w2 + (t * 16 + li) * kLdH + kk * 16 + lq * 4), f.z2[t]);
+        for (int t = 0; t < 8; ++t) f.z2[t] = mfma32(a, ld8(w2 + (t * 16 + li) * kLdH + kk * 32 + lq * 8), f.z2[t]);
     }
 #pragma unroll
     for (int t = 0; t < 8; ++t)
@@ -143,8 +161,8 @@ __device__ inline void forward_rows(const WeightsLds& W, const bf16* X, bf16* H1
     __syncthreads();
     f.z3 = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kk = 0; kk < kNH / 16; ++kk)
-        f.z3 = mfma16(ld4(H2 + (r0 + li) * kLdH + kk * 16 + lq * 4), ld4(w3 + li * kLdH + kk * 16 + lq * 4), f.z3);
+    for (int kk = 0; kk < kNH / 32; ++kk)
+        f.z3 = mfma32(ld8(H2 + (r0 + li) * kLdH + kk * 32 + lq * 8), ld8(w3 + li * kLdH + kk * 32 + lq * 8), f.z3);
 #pragma unroll
     for (int j = 0; j < 4; ++j) f.z3[j] += W.b3[li];
 }
@@ -218,26 +236,26 @@ __device__ inline v4f infer_rows(const WeightsLds& W, const bf16* X, int r0, bf1
 #pragma unroll
     for (int t = 0; t < 8; ++t) z[t] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kk = 0; kk < kNF / 16; ++kk) {
-        v4s a = ld4(X + (r0 + li) * kLdX + kk * 16 + lq * 4);
+    for (int kk = 0; kk < kNF / 32; ++kk) {
+        v8s a = ld8(X + (r0 + li) * kLdX + kk * 32 + lq * 8);
 #pragma unroll
-        for (int t = 0; t < 8; ++t) z[t] = mfma16(a, ld4(w1 + (t * 16 + li) * kLdX + kk * 16 + lq * 4), z[t]);
+        for (int t = 0; t < 8; ++t) z[t] = mfma32(a, ld8(w1 + (t * 16 + li) * kLdX + kk * 32 + lq * 8), z[t]);
     }
 #pragma unroll
     for (int t = 0; t < 8; ++t)
 #pragma unroll
         for (int j = 0; j < 4; ++j) Hw[(lq * 4 + j) * kLdH + t * 16 + li] = to_bf16(gelu(z[t][j] + W.b1[t * 16 + li]));
     wave_sync();
-    v4s a[kNH / 16];
+    v8s a[kNH / 32];
 #pragma unroll
-    for (int kk = 0; kk < kNH / 16; ++kk) a[kk] = ld4(Hw + li * kLdH + kk * 16 + lq * 4);
+    for (int kk = 0; kk < kNH / 32; ++kk) a[kk] = ld8(Hw + li * kLdH + kk * 32 + lq * 8);
     wave_sync();
 #pragma unroll
     for (int t = 0; t < 8; ++t) z[t] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kk = 0; kk < kNH / 16; ++kk)
+    for (int kk = 0; kk < kNH / 32; ++kk)
 #pragma unroll
-        for (int t = 0; t < 8; ++t) z[t] = mfma16(a[kk], ld4(w2 + (t * 16 + li) * kLdH + kk * 16 + lq * 4), z[t]);
+        for (int t = 0; t < 8; ++t) z[t] = mfma32(a[kk], ld8(w2 + (t * 16 + li) * kLdH + kk * 32 + lq * 8), z[t]);
 #pragma unroll
     for (int t = 0; t < 8; ++t)
 #pragma unroll
@@ -245,8 +263,8 @@ __device__ inline v4f infer_rows(const WeightsLds& W, const bf16* X, int r0, bf1
     wave_sync();
     v4f z3 = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kk = 0; kk < kNH / 16; ++kk)
-        z3 = mfma16(ld4(Hw + li * kLdH + kk * 16 + lq * 4), ld4(w3 + li * kLdH + kk * 16 + lq * 4), z3);
+    for (int kk = 0; kk < kNH / 32; ++kk)
+        z3 = mfma32(ld8(Hw + li * kLdH + kk * 32 + lq * 8), ld8(w3 + li * kLdH + kk * 32 + lq * 8), z3);
     wave_sync();
 #pragma unroll
     for (int j = 0; j < 4; ++j) z3[j] += W.b3[li];
@@ -259,8 +277,10 @@ constexpr int kInferTile = 64 * kInferWaves;   // rows per block trip: one per t
 // Learned orders for the bins the rank-one certificate left pending (exact
 // mode, L = 4): each thread builds the features of one bin, each wave runs
 // the network on 64 rows (4 MFMA row tiles), and the bin is queued for round
-// 0 at its predicted order (or for the SVD rank test when the prediction is
-// 0, i.e. outside 1..L).
+// 0 at its predicted order.  A prediction of 0 (outside 1..L) sends the bin
+// to the rank test: in plans without general-mode signals that is the rest
+// kernel's own (set 1, slot 0, step 0), otherwise the SVD pass before round 0.
+// Blocks with no rows return before loading the weights.
 template <typename T>
 __global__ __launch_bounds__(kInferTile) void infer_kernel(LaunchCtx c, const bf16* __restrict__ wimg,
                                                            const float* __restrict__ theta) {
@@ -270,8 +290,9 @@ __global__ __launch_bounds__(kInferTile) void infer_kernel(LaunchCtx c, const bf
     __shared__ float Zs[kInferWaves * 16 * 8];
     __shared__ signed char pred[kInferTile];
     __shared__ BlockQueues bq;
-    load_weights(W, wimg, theta);
     const int total = c.work->q[kQPending];
+    if ((int64_t)blockIdx.x * kInferTile >= total) return;   // the whole block: no barrier is left waiting
+    load_weights(W, wimg, theta);
     const int2* in = c.qlist + (int64_t)kQPending * c.list_cap;
     const typename VT<T>::type* synd = (const typename VT<T>::type*)c.synd;
     const int w = threadIdx.x >> 6, lane = __lane_id();
@@ -324,7 +345,7 @@ __global__ __launch_bounds__(kInferTile) void infer_kernel(LaunchCtx c, const bf
         if (s >= 0) {
             int ap = pred[threadIdx.x];
             if (ap < 1 || ap > c.sigs[s].L) ap = 0;
-            q = q_round(0, ap);
+            q = (ap == 0 && c.n_general == 0) ? q_round(1, 0) : q_round(0, ap);
             ent = int2{s, pack_code(k, 0, ap, 0)};
         }
         const int slot = bq.reserve(q);
@@ -461,11 +482,11 @@ __global__ __launch_bounds__(256) void grad_kernel(const float* __restrict__ fea
 #pragma unroll
             for (int t = 0; t < 8; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int kk = 0; kk < kNH / 16; ++kk) {
-                v4s a = ld4(D2 + (w * 16 + li) * kLdH + kk * 16 + lq * 4);
+            for (int kk = 0; kk < kNH / 32; ++kk) {
+                v8s a = ld8(D2 + (w * 16 + li) * kLdH + kk * 32 + lq * 8);
 #pragma unroll
                 for (int t = 0; t < 8; ++t)
-                    acc[t] = mfma16(a, gather4(w2 + (kk * 16 + lq * 4) * kLdH + t * 16 + li, kLdH), acc[t]);
+                    acc[t] = mfma32(a, gather8(w2 + (kk * 32 + lq * 8) * kLdH + t * 16 + li, kLdH), acc[t]);
             }
 #pragma unroll
             for (int t = 0; t < 8; ++t)
@@ -480,10 +501,10 @@ __global__ __launch_bounds__(256) void grad_kernel(const float* __restrict__ fea
             const int tm = tile >> 3, tn = tile & 7;
             v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int kk = 0; kk < kRows / 16; ++kk) {
-                v4s a = gather4(D2 + (kk * 16 + lq * 4) * kLdH + tm * 16 + li, kLdH);
-                v4s b = gather4(H1 + (kk * 16 + lq * 4) * kLdH + tn * 16 + li, kLdH);
-                acc = mfma16(a, b, acc);
+            for (int kk = 0; kk < kRows / 32; ++kk) {
+                v8s a = gather8(D2 + (kk * 32 + lq * 8) * kLdH + tm * 16 + li, kLdH);
+                v8s b = gather8(H1 + (kk * 32 + lq * 8) * kLdH + tn * 16 + li, kLdH);
+                acc = mfma32(a, b, acc);
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j)
@@ -494,10 +515,10 @@ __global__ __launch_bounds__(256) void grad_kernel(const float* __restrict__ fea
             const int tm = tile >> 1, tn = tile & 1;
             v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int kk = 0; kk < kRows / 16; ++kk) {
-                v4s a = gather4(D1 + (kk * 16 + lq * 4) * kLdH + tm * 16 + li, kLdH);
-                v4s b = gather4(X + (kk * 16 + lq * 4) * kLdX + tn * 16 + li, kLdX);
-                acc = mfma16(a, b, acc);
+            for (int kk = 0; kk < kRows / 32; ++kk) {
+                v8s a = gather8(D1 + (kk * 32 + lq * 8) * kLdH + tm * 16 + li, kLdH);
+                v8s b = gather8(X + (kk * 32 + lq * 8) * kLdX + tn * 16 + li, kLdX);
+                acc = mfma32(a, b, acc);
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j)
@@ -507,10 +528,10 @@ __global__ __launch_bounds__(256) void grad_kernel(const float* __restrict__ fea
         for (int tn = w; tn < 8; tn += 4) {
             v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int kk = 0; kk < kRows / 16; ++kk) {
-                v4s a = gather4(D3 + (kk * 16 + lq * 4) * kLdC + li, kLdC);
-                v4s b = gather4(H2 + (kk * 16 + lq * 4) * kLdH + tn * 16 + li, kLdH);
-                acc = mfma16(a, b, acc);
+            for (int kk = 0; kk < kRows / 32; ++kk) {
+                v8s a = gather8(D3 + (kk * 32 + lq * 8) * kLdC + li, kLdC);
+                v8s b = gather8(H2 + (kk * 32 + lq * 8) * kLdH + tn * 16 + li, kLdH);
+                acc = mfma32(a, b, acc);
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j)

@@ -1361,6 +1361,92 @@ __global__ __launch_bounds__(kBlock) void cs_kernel(const SigDev* __restrict__ s
 
 // ------------------------------------------------------------ output lists
 
+// Location sort of long lists (more than kRankChunk entries) by buckets of
+// the location's high bits: counts per bucket, their exclusive scan (the
+// bucket's first output position), the entries scattered into their
+// buckets' ranges (any order within a range), then every entry's position =
+// its range's start + the number of its range's locations below its own
+// (locations within a signal are distinct).  About 4 entries per bucket for
+// uniformly spread locations; a list with a bucket above kOutBucketMax
+// entries is left to block_rank.
+constexpr int kOutBuckets = 4096;
+constexpr int kOutBucketMax = 256;
+struct BucketLds {
+    int base[kOutBuckets + 1];   // counts, then their exclusive scan
+    int cur[kOutBuckets];        // scatter cursors
+    int part[kRankThreads / 64];
+    int maxc;
+};
+
+// Writes the sorted list (positions below cap) and returns true, or returns
+// false (nothing written) when some bucket holds more than kOutBucketMax
+// entries.  e_of(j) = staging index of list entry j < nk; tl / tj: scratch
+// of nk locations / staging indices.  Whole block.
+template <typename EntryFn>
+__device__ bool bucket_sort_out(EntryFn e_of, int nk, const int64_t* __restrict__ loc, const double2* __restrict__ val,
+                                int64_t n, BucketLds& B, long long* __restrict__ tl, int* __restrict__ tj, int64_t* o_loc,
+                                double2* o_val, int64_t cap) {
+    int lnb = 0;
+    while ((1 << lnb) < kOutBuckets && (4 << lnb) < nk) ++lnb;   // about 4 entries per bucket
+    const int log2n = __builtin_ctzll((unsigned long long)n);
+    if (lnb > log2n) lnb = log2n;
+    const int nb = 1 << lnb, shift = log2n - lnb;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) B.base[b] = 0;
+    if (threadIdx.x == 0) B.maxc = 0;
+    __syncthreads();
+    for (int j = threadIdx.x; j < nk; j += blockDim.x) atomicAdd(&B.base[(int)(loc[e_of(j)] >> shift)], 1);
+    __syncthreads();
+    // exclusive scan of the counts: each thread a contiguous run, wave then block partials
+    const int per = (nb + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int lo = min(nb, (int)threadIdx.x * per), hi = min(nb, lo + per);
+    int run = 0, mx = 0;
+    for (int b = lo; b < hi; ++b) {
+        run += B.base[b];
+        mx = max(mx, B.base[b]);
+    }
+    if (mx > 0) atomicMax(&B.maxc, mx);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int inc = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += u;
+    }
+    if (lane == 63) B.part[wv] = inc;
+    __syncthreads();
+    int before = inc - run;
+    for (int w = 0; w < wv; ++w) before += B.part[w];
+    for (int b = lo; b < hi; ++b) {
+        const int c = B.base[b];
+        B.base[b] = before;
+        B.cur[b] = before;
+        before += c;
+    }
+    if (threadIdx.x == 0) B.base[nb] = nk;
+    __syncthreads();
+    if (B.maxc > kOutBucketMax) return false;   // uniform: read after the barrier
+    for (int j = threadIdx.x; j < nk; j += blockDim.x) {
+        const int e = e_of(j);
+        const int64_t l = loc[e];
+        const int pos = atomicAdd(&B.cur[(int)(l >> shift)], 1);
+        tl[pos] = (long long)l;
+        tj[pos] = e;
+    }
+    __syncthreads();   // the block's scratch writes are visible to the block
+    for (int p = threadIdx.x; p < nk; p += blockDim.x) {
+        const long long l = tl[p];
+        const int b = (int)(l >> shift);
+        const int q0 = B.base[b], q1 = B.base[b + 1];
+        int r = q0;
+        for (int q = q0; q < q1; ++q) r += tl[q] < l ? 1 : 0;
+        if (r < cap) {
+            o_loc[r] = (int64_t)l;
+            o_val[r] = val[tj[p]];
+        }
+    }
+    return true;
+}
+
 // One block per signal.  General mode keeps the K entries of largest |value|
 // when more were found (ties to the lower location); iterative mode drops the
 // entries marked cancelled; the kept entries are written sorted by location
@@ -1375,6 +1461,7 @@ __global__ __launch_bounds__(kRankThreads) void output_kernel(const SigDev* __re
     __shared__ union {
         RankLds rank;
         RadixLds radix;
+        BucketLds bucket;
     } U;
     RankLds& S = U.rank;
     const int s = blockIdx.x;
@@ -1461,7 +1548,9 @@ __global__ __launch_bounds__(kRankThreads) void output_kernel(const SigDev* __re
             o.loc[r] = loc[e];
             o.val[r] = val[e];
         }
-    } else {
+    } else if (!bucket_sort_out([&](int j) { return kx[j]; }, nk, loc, val, sg.n, U.bucket, g.b, g.idx, o.loc, o.val,
+                                o.cap)) {
+        __syncthreads();   // U is reused
         block_rank([&](int j) { return RankKey{0.0, (long long)loc[kx[j]]}; }, nk, S, g);
         for (int j = threadIdx.x; j < nk; j += blockDim.x) {
             const int r = g.rank[j];

@@ -244,3 +244,33 @@ def test_exact_n24(torch, sft, k):
     loc, val, st = run_exact(torch, sft, s.x, n, m, L, "c64")
     exact_vs_fp64(loc, val, st, s.x, n, m, L, max_diff=max(2, k // 4096), truth=(s.locs, s.vals), say=say)
     assert len(loc) >= 0.99 * k
+
+
+@pytest.mark.parametrize("layout", ["spread", "clustered"])
+def test_long_output_lists_sorted(torch, sft, layout):
+    """Output lists longer than one LDS sort (2048 entries), complex128 (FP64
+    FFTs), N = 2^20, M = 8192, L = 4, K = 3000.  Locations spread over [0, N)
+    go through the bucket sort (about 3 entries per bucket of 1024
+    locations); locations packed below 4096 (one tone per bin) fill four
+    buckets beyond the bucket limit and go through the chunked rank.  Either
+    way the list equals the oracle's (sorted by location, values within
+    1e-10), and a capacity of 2500 keeps its first 2500 entries."""
+    n, m, L, k = 1 << 20, 8192, 4, 3000
+    g = np.random.default_rng(11)
+    hi = n if layout == "spread" else 4096
+    locs = np.sort(g.choice(hi, size=k, replace=False)).astype(np.int64)
+    vals = np.exp(2j * np.pi * g.random(k))
+    s = sftgen.make_signal(n, k, 0, locs=locs, vals=vals, dtype=np.complex128)
+    say(f"[long output] {layout}")
+    ref = oracle.sfft_exact(s.x, n, m, L)
+    assert len(ref.locs) > 2048
+    plan = sft.Plan(dict(n=n, k=k, m=m, l=L, dtype="c128"))
+    res = plan.exact(to_dev(torch, s.x), stats=True)
+    loc, val = res.host()
+    assert loc.tolist() == ref.locs.tolist()
+    assert np.max(np.abs(val - ref.vals)) <= 1e-10
+    res = plan.exact(to_dev(torch, s.x), capacity=2500, stats=True)
+    assert res.stats.get("capacity_exceeded")
+    assert int(res.count.item()) == len(ref.locs)
+    assert res.loc[:2500].cpu().numpy().tolist() == ref.locs[:2500].tolist()
+    plan.close()

@@ -48,6 +48,7 @@ struct sft_plan_s {
     double* d_epart = nullptr;
     double* d_sigma = nullptr;
     double* d_ebin = nullptr;
+    unsigned char* d_prechk = nullptr;
     SelDev* d_sel = nullptr;
     SigCounters* d_cnt = nullptr;
     int64_t* d_stloc = nullptr;
@@ -171,6 +172,7 @@ LaunchCtx make_ctx(const sft_plan_s* p) {
     c.epart = p->d_epart;
     c.sigma = p->d_sigma;
     c.ebin = p->d_ebin;
+    c.prechk = p->d_prechk;
     c.sel = p->d_sel;
     c.cnt = p->d_cnt;
     c.st_loc = p->d_stloc;
@@ -319,7 +321,13 @@ sft_status enqueue_path(const LaunchCtx& c, const Branching* br, sft_mlp_t mlp, 
         if (r >= 1) HIPCHK(launch_zero_set(c, (r + 1) & 1));
         // the orders of a round read their own queues: parallel branches
         const int n_orders = (r == 0 && !c.any_general) ? std::min(c.max_l, 2) : c.max_l;
-        sft_status bs = branches(br, c, n_orders, [&](const LaunchCtx& ci, int a) { return launch_round(ci, r, a); });
+        // round 0 of general mode: the pre-checks of orders 3 and 4 for the
+        // later rounds, after the short order-2 kernel in its branch
+        sft_status bs = branches(br, c, n_orders, [&](const LaunchCtx& ci, int a) {
+            hipError_t e = launch_round(ci, r, a);
+            if (e == hipSuccess && r == 0 && a == 2 && c.any_general) e = launch_precheck(ci);
+            return e;
+        });
         if (bs != SFT_OK) return bs;
         // bins whose learned order failed: rank test, then on with round 1
         // (without general-mode signals the rest kernel runs it itself)
@@ -599,6 +607,7 @@ sft_status sft_plan(sft_plan_t* out, const sft_params* params, int64_t n_params,
     TRY(dalloc(p, &p->d_epart, (size_t)lay.epart_elems));
     TRY(dalloc(p, &p->d_sigma, lay.n_general ? (size_t)lay.sigma_elems : 1));
     TRY(dalloc(p, &p->d_ebin, lay.n_general ? (size_t)lay.bin_elems : 1));
+    TRY(dalloc(p, &p->d_prechk, lay.n_general ? (size_t)lay.bin_elems : 1));
     TRY(dalloc(p, &p->d_sel, ns));
     TRY(dalloc(p, &p->d_cnt, ns));
     TRY(dalloc(p, &p->d_stloc, (size_t)lay.stage_elems));

@@ -261,6 +261,7 @@ struct LaunchCtx {
     double* epart;
     double* sigma;
     double* ebin;
+    unsigned char* prechk;   // general mode, per bin: round 0's |c_0| checks of orders 3, 4 (bit 0: taken)
     SelDev* sel;
     SigCounters* cnt;
     int64_t* st_loc;
@@ -330,6 +331,7 @@ hipError_t launch_svd_rank(const LaunchCtx& c, int q_in, int set_out);   // rank
 hipError_t launch_zero_set(const LaunchCtx& c, int set);
 hipError_t launch_round(const LaunchCtx& c, int round, int a);   // the kernels of order a in round `round`
 hipError_t launch_rest(const LaunchCtx& c);   // rounds 1.. in one kernel (plans without general-mode signals)
+hipError_t launch_precheck(const LaunchCtx& c);   // general mode: round 0's pre-checks of orders 3 and 4
 hipError_t launch_cs(const LaunchCtx& c, int a0);                // CS step of the bins flagged with vote order a0
 hipError_t launch_output(const LaunchCtx& c);
 hipError_t launch_iteration(const LaunchCtx& c, int l);   // Alg. 1, iteration l (scan, then SynDec for l >= 1)

@@ -1173,7 +1173,7 @@ __global__ __launch_bounds__(kBlock, A <= 2 ? 3 : 2) void round_kernel(const Sig
                                                        SigCounters* __restrict__ cnt, int64_t* __restrict__ st_loc,
                                                        double2* __restrict__ st_val, WorkCounters* __restrict__ work,
                                                        int2* __restrict__ active, int2* __restrict__ qlist,
-                                                       int64_t list_cap, int round) {
+                                                       int64_t list_cap, int round, unsigned char* __restrict__ prechk) {
     __shared__ BlockQueues bq;
     const int set_in = round & 1;
     const int q_in = PHASE == 2 ? q_roots(set_in, A) : q_round(set_in, A);
@@ -1210,13 +1210,23 @@ __global__ __launch_bounds__(kBlock, A <= 2 ? 3 : 2) void round_kernel(const Sig
                 emit(sg, &cnt[s], k, o, st_loc, st_val);
             } else {
                 if (step == 0 && ap > 0) wave_count(&cnt[s].mlp_fb, true);
-                const int nx = step + 1;
+                // general mode, rounds after the first: a hypothesis of order
+                // 3 or 4 whose |c_0| pre-check failed (precheck_kernel, in
+                // round 0) is skipped, as its round would reject it by the
+                // same check on the same syndromes; one whose check passed
+                // goes straight to the roots pass
+                const unsigned pc = (!exact && round > 0) ? (unsigned)prechk[sg.bin_off + k] : 0u;
+                int nx = step + 1, nord = 0;
+                for (; nx < L; ++nx) {
+                    nord = (ap > 0 && a0 == 0) ? 0 : seq_order(a0, ap, L, nx);
+                    if (!((pc & 1u) && nord >= 3 && !(pc & (nord == 3 ? 2u : 4u)))) break;
+                }
                 if (nx < L) {
                     if (ap > 0 && a0 == 0) {
                         q = q_round(set_in ^ 1, 0);
                         ent = int2{s, pack_code(k, nx, ap, 0)};
                     } else {
-                        q = q_round(set_in ^ 1, seq_order(a0, ap, L, nx));
+                        q = ((pc & 1u) && nord >= 3) ? q_roots(set_in ^ 1, nord) : q_round(set_in ^ 1, nord);
                         ent = int2{s, pack_code(k, nx, ap, a0)};
                     }
                 } else {
@@ -1230,6 +1240,50 @@ __global__ __launch_bounds__(kBlock, A <= 2 ? 3 : 2) void round_kernel(const Sig
         }
         const int slot = bq.reserve(q);
         bq.commit(work, active, qlist, list_cap, q, slot, ent);
+    }
+}
+
+// General mode, beside round 0: the |c_0| pre-checks (locator_check) of
+// orders 3 and 4 for every bin queued for round 0, into prechk[bin] (bit 0:
+// taken, bits 1 and 2: order 3 and 4 pass).  Bins whose round-0 order is 3
+// or 4 get 0 (not taken): their pre-check is part of their rounds.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void precheck_kernel(const SigDev* __restrict__ sigs,
+                                                          const typename V2<T>::type* __restrict__ synd,
+                                                          const WorkCounters* __restrict__ work,
+                                                          const int2* __restrict__ qlist, int64_t list_cap,
+                                                          unsigned char* __restrict__ prechk) {
+    constexpr int kSeg = kMaxL;
+    int start[kSeg + 1];
+    start[0] = 0;
+#pragma unroll
+    for (int i = 0; i < kSeg; ++i) start[i + 1] = start[i] + work->q[q_round(0, i + 1)];
+    const int total = start[kSeg];
+    for (int item = blockIdx.x * kBlock + threadIdx.x; item < total; item += gridDim.x * kBlock) {
+        int seg = 0;
+#pragma unroll
+        for (int i = 1; i < kSeg; ++i)
+            if (item >= start[i]) seg = i;
+        int s0 = start[0];
+#pragma unroll
+        for (int i = 1; i < kSeg; ++i)
+            if (seg == i) s0 = start[i];
+        const int2 en = qlist[(int64_t)q_round(0, seg + 1) * list_cap + (item - s0)];
+        const SigDev& sg = sigs[en.x];
+        if (sg.mode != kGeneral) continue;
+        const int64_t k = code_k(en.y);
+        unsigned pc = 0u;
+        if (seg <= 1) {
+            const int L = sg.L;
+            zd mt[2 * kMaxL];
+            load_raw<T, 2 * kMaxL>(synd, sg, k, 2 * L, mt);
+            derotate_consecutive<2 * kMaxL>(mt, k, sg.n, 2 * L);
+            zd cc[kMaxL];
+            pc = 1u;
+            if (L >= 3 && locator_check(mt, 3, sg, cc)) pc |= 2u;
+            if (L >= 4 && locator_check(mt, 4, sg, cc)) pc |= 4u;
+        }
+        prechk[sg.bin_off + k] = (unsigned char)pc;
     }
 }
 
@@ -1635,7 +1689,7 @@ static void launch_round_one(const LaunchCtx& c, int round) {
     using V = typename V2<T>::type;
     hipLaunchKernelGGL((round_kernel<T, A, PHASE>), dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs, c.shifts,
                        (const V*)c.synd, c.sel, c.omega, c.cnt, c.st_loc, c.st_val, c.work, c.active_list, c.qlist,
-                       c.list_cap, round);
+                       c.list_cap, round, c.prechk);
 }
 
 // Orders 3 and 4 in two passes when the plan has general-mode signals (most
@@ -1663,6 +1717,17 @@ static void launch_round_t(const LaunchCtx& c, int round, int a) {
         case 3: launch_order<T, 3>(c, round); break;
         default: launch_order<T, 4>(c, round); break;
     }
+}
+
+hipError_t launch_precheck(const LaunchCtx& c) {
+    if (!c.any_general || c.n_bin_items == 0) return hipSuccess;
+    if (c.fp64)
+        hipLaunchKernelGGL(precheck_kernel<double>, dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs,
+                           (const double2*)c.synd, c.work, c.qlist, c.list_cap, c.prechk);
+    else
+        hipLaunchKernelGGL(precheck_kernel<float>, dim3(c.n_work_blocks), dim3(kBlock), 0, c.stream, c.sigs,
+                           (const float2*)c.synd, c.work, c.qlist, c.list_cap, c.prechk);
+    return hipGetLastError();
 }
 
 hipError_t launch_rest(const LaunchCtx& c) {

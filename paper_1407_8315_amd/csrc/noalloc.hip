@@ -229,6 +229,7 @@ extern "C" sft_status sft_exact_noalloc(const sft_params* params, const void* x_
     c.epart = (double*)(base + kOffEpart);
     c.sigma = (double*)(base + kOffSigma);
     c.ebin = (double*)(base + kOffEbin);
+    c.prechk = nullptr;   // general mode only
     c.sel = (SelDev*)(base + kOffSel);
     c.cnt = (SigCounters*)(base + kOffCnt);
     c.st_loc = (int64_t*)(base + kOffStLoc);

@@ -38,15 +38,17 @@ constexpr int kFftPointsF32Small = 4096;     // blocks of FP32 signals with M <=
 constexpr int kActivityTile = 4096;         // bins per block of the activity pass
 // Consecutive-shift line pairs (pair_syndrome_kernel): FP32 units with
 // 2^kPairLog2MMin <= M <= 2^kPairLog2MMax, P = 1, 2 or 4 pairs per block; one
-// item list per (P, log2 M) group.
+// item list per (P, log2 M) group.  P = 0: iterative signals whose grids
+// all qualify, every grid of a signal in one launch (iter_pair_kernel, by
+// log2 M_0).
 constexpr int kPairLog2MMin = 8, kPairLog2MMax = 12;
 // log2 of the points of each line a thread holds (8: 107 VGPRs at M = 4096,
 // four waves per SIMD; 16 points need 177 and measured 1.13x slower)
 constexpr int kPairLpt = 3;
 constexpr int kPairSizes = kPairLog2MMax - kPairLog2MMin + 1;
-constexpr int kPairGroups = 3 * kPairSizes;
+constexpr int kPairGroups = 4 * kPairSizes;
 __host__ __device__ constexpr int pair_group(int p, int log2m) {
-    return (p == 1 ? 0 : p == 2 ? 1 : 2) * kPairSizes + (log2m - kPairLog2MMin);
+    return (p == 1 ? 0 : p == 2 ? 1 : p == 4 ? 2 : 3) * kPairSizes + (log2m - kPairLog2MMin);
 }
 
 enum Mode { kExact = 0, kGeneral = 1, kIterative = 2 };

@@ -331,9 +331,10 @@ __device__ inline float2 twiddle_q(const float2* q, int e) {
 // holds (v[s] = point j + T s); writes its outputs to `lds` (padded line)
 // unless it is the last pass, which leaves X[j + T s] in v[s].
 template <int LOG2M, int LPT, int LR, int LNS, bool LAST>
-__device__ inline void pair_pass(float2 (&v)[1 << LPT], int j, const float2* qtw, float2* lds) {
+__device__ inline void pair_pass(float2 (&v)[1 << LPT], int j, const float2* qtw, float2* lds, bool on) {
     using F = PairFft<LOG2M, LPT>;
     constexpr int R = 1 << LR, NB = F::PT / R;
+    if (!on) return;
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         const int b = j + F::T * q;           // butterfly index
@@ -358,27 +359,31 @@ __device__ inline void pair_pass(float2 (&v)[1 << LPT], int j, const float2* qtw
 }
 
 // Passes 1 .. NPASS-1 of one line through LDS (pass 0 already written there).
+// Threads with on = false (beyond the line's T) only take part in the
+// barriers.
 template <int LOG2M, int LPT, int PASS>
-__device__ inline void pair_rest(float2 (&v)[1 << LPT], int j, const float2* qtw, float2* lds) {
+__device__ inline void pair_rest(float2 (&v)[1 << LPT], int j, const float2* qtw, float2* lds, bool on) {
     using F = PairFft<LOG2M, LPT>;
     if constexpr (PASS < F::NPASS) {
         __syncthreads();
+        if (on) {
 #pragma unroll
-        for (int s = 0; s < F::PT; ++s) v[s] = lds[F::pad(j + F::T * s)];
+            for (int s = 0; s < F::PT; ++s) v[s] = lds[F::pad(j + F::T * s)];
+        }
         __syncthreads();
         constexpr int LR = F::log2r(PASS);
         constexpr int LNS = LPT * PASS;   // every earlier pass was of radix PT
-        pair_pass<LOG2M, LPT, LR, LNS, PASS == F::NPASS - 1>(v, j, qtw, lds);
-        pair_rest<LOG2M, LPT, PASS + 1>(v, j, qtw, lds);
+        pair_pass<LOG2M, LPT, LR, LNS, PASS == F::NPASS - 1>(v, j, qtw, lds, on);
+        pair_rest<LOG2M, LPT, PASS + 1>(v, j, qtw, lds, on);
     }
 }
 
 // One line: pass 0 (radix PT, no twiddles) on the registers, the rest through
 // LDS; leaves X[j + T s] in v[s].
 template <int LOG2M, int LPT>
-__device__ inline void pair_fft(float2 (&v)[1 << LPT], int j, const float2* qtw, float2* lds) {
-    pair_pass<LOG2M, LPT, LPT, 0, false>(v, j, qtw, lds);
-    pair_rest<LOG2M, LPT, 1>(v, j, qtw, lds);
+__device__ inline void pair_fft(float2 (&v)[1 << LPT], int j, const float2* qtw, float2* lds, bool on = true) {
+    pair_pass<LOG2M, LPT, LPT, 0, false>(v, j, qtw, lds, on);
+    pair_rest<LOG2M, LPT, 1>(v, j, qtw, lds, on);
 }
 
 // Scale by d in place and return the line's energy summed over the
@@ -447,10 +452,10 @@ __global__ __launch_bounds__(P * (1 << (LOG2M - LPT))) void pair_syndrome_kernel
 
     const float dscale = (float)sg.d;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    pair_fft<LOG2M, LPT>(a, j, qtw, lds[p]);
+    pair_fft<LOG2M, LPT>(a, j, qtw, lds[p], true);
     double acc = pair_scale_energy<P, LPT>(a, dscale);
     if (lane < P) red[wave][2 * lane] = acc;
-    pair_fft<LOG2M, LPT>(b, j, qtw, lds[p]);
+    pair_fft<LOG2M, LPT>(b, j, qtw, lds[p], true);
     acc = pair_scale_energy<P, LPT>(b, dscale);
     if (lane < P) red[wave][2 * lane + 1] = acc;
     const int line = line0 + 2 * p;
@@ -474,6 +479,103 @@ __global__ __launch_bounds__(P * (1 << (LOG2M - LPT))) void pair_syndrome_kernel
         double e = 0.0;
         for (int w = 0; w < NT / 64; ++w) e += red[w][threadIdx.x];
         epart[sg.epart_off + line0 + 2 * (threadIdx.x >> 1) + (threadIdx.x & 1)] = e;
+    }
+}
+
+// Iterative signals: the two lines of one grid M_l = M_0 / 2^l per block, in
+// one launch for every grid of the signals of one M_0 (LOG2M0 = log2 M_0;
+// grid l uses the first M_l / 8 threads of the block, the others take part in
+// the barriers only).  Grid l reads x[d_l k' + 2l] and x[d_l k' + 2l + 1],
+// d_l = 2^l d_0: the 16 bytes 16 l past x[d_0 (2^l k')], in a 128-byte line
+// that grid 0 reads too; the blocks of a signal's grids are dispatched
+// together on one XCD, so that its L2 serves the line to all of them.
+template <int LOG2M, int LOG2M0>
+__device__ inline void iter_grid(const SigDev& sg, const float2* __restrict__ x, int64_t shift, const float2* __restrict__ tw,
+                                 int tw_log2, float2* __restrict__ synd, double* __restrict__ epart, SigCounters* cnt,
+                                 float2* lds, float2* qtw, double (*red)[2]) {
+    using F = PairFft<LOG2M, kPairLpt>;
+    constexpr int NT = 1 << (LOG2M0 - kPairLpt);
+    const int j = threadIdx.x;
+    const bool on = j < F::T;
+    float2 a[F::PT], b[F::PT];
+#pragma unroll
+    for (int s = 0; s < F::PT; ++s) a[s] = b[s] = float2{0.0f, 0.0f};
+    if (on) {
+        if ((reinterpret_cast<uintptr_t>(x) & 15) == 0) {   // shift even: 16-byte pairs
+            const float4* __restrict__ x4 = reinterpret_cast<const float4*>(x) + ((sg.d * (int64_t)j + shift) >> 1);
+            const int64_t step = (sg.d * F::T) >> 1;
+#pragma unroll
+            for (int s = 0; s < F::PT; ++s) {
+                const float4 w = x4[s * step];
+                a[s] = float2{w.x, w.y};
+                b[s] = float2{w.z, w.w};
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < F::PT; ++s) {
+                const int64_t idx = sg.d * (int64_t)(j + F::T * s) + shift;
+                a[s] = x[idx];
+                b[s] = x[idx + 1];
+            }
+        }
+        if (sg.flags & 4) {
+            int bad = 0;
+#pragma unroll
+            for (int s = 0; s < F::PT; ++s)
+                bad += !(isfinite(a[s].x) && isfinite(a[s].y)) + !(isfinite(b[s].x) && isfinite(b[s].y));
+            if (bad) atomicAdd(&cnt[sg.parent].nonfinite, bad);
+        }
+    }
+    __syncthreads();   // the previous grid is done with lds, qtw and red
+    for (int e = j; e <= F::M / 8; e += NT) qtw[e] = tw[(int64_t)e << (tw_log2 - LOG2M)];
+    const float dscale = (float)sg.d;
+    const int lane = j & 63, wave = j >> 6;
+    pair_fft<LOG2M, kPairLpt>(a, j, qtw, lds, on);
+    double acc = pair_scale_energy<1, kPairLpt>(a, dscale);
+    if (lane == 0) red[wave][0] = acc;
+    pair_fft<LOG2M, kPairLpt>(b, j, qtw, lds, on);
+    acc = pair_scale_energy<1, kPairLpt>(b, dscale);
+    if (lane == 0) red[wave][1] = acc;
+    if (on) {
+        float2* __restrict__ out = synd + synd_at(sg, 0, 0);
+#pragma unroll
+        for (int s = 0; s < F::PT; ++s) {
+            out[j + F::T * s] = a[s];
+            out[F::M + j + F::T * s] = b[s];
+        }
+    }
+    __syncthreads();
+    if (j < 2) {
+        double e = 0.0;
+        for (int w = 0; w < (NT + 63) / 64; ++w) e += red[w][j];
+        epart[sg.epart_off + j] = e;
+    }
+}
+
+template <int LOG2M0>
+__global__ __launch_bounds__(1 << (LOG2M0 - kPairLpt)) void iter_pair_kernel(
+    const SigDev* __restrict__ sigs, const IoDev* __restrict__ io, const int4* __restrict__ items,
+    const int64_t* __restrict__ shifts, const float2* __restrict__ tw, int tw_log2, float2* __restrict__ synd,
+    double* __restrict__ epart, SigCounters* __restrict__ cnt) {
+    constexpr int NT = 1 << (LOG2M0 - kPairLpt);
+    static_assert(NT >= 64 && NT <= 1024, "whole waves, at most 1024 threads");
+    __shared__ float2 lds[PairFft<LOG2M0, kPairLpt>::lds_points()];
+    __shared__ float2 qtw[(1 << LOG2M0) / 8 + 1];
+    __shared__ double red[NT / 64][2];
+    const int4 it = items[blockIdx.x];
+    if (it.x < 0) return;   // padding item
+    const SigDev sg = sigs[it.x];   // the grid's view
+    const float2* __restrict__ x = reinterpret_cast<const float2*>(io[sg.parent].x);
+    const auto grid = [&](auto lg) {
+        constexpr int LG = decltype(lg)::value;
+        if constexpr (LG >= kPairLog2MMin)
+            iter_grid<LG, LOG2M0>(sg, x, shifts[sg.shift_off], tw, tw_log2, synd, epart, cnt, lds, qtw, red);
+    };
+    switch (it.y) {   // l, uniform over the block
+        case 0: grid(std::integral_constant<int, LOG2M0>{}); break;
+        case 1: grid(std::integral_constant<int, LOG2M0 - 1>{}); break;
+        case 2: grid(std::integral_constant<int, LOG2M0 - 2>{}); break;
+        default: grid(std::integral_constant<int, LOG2M0 - 3>{}); break;
     }
 }
 
@@ -554,10 +656,25 @@ static void launch_pair_sizes(const LaunchCtx& c) {
     launch_pair_group<P, 12>(c);
 }
 
+template <int LOG2M0>
+static void launch_iter_group(const LaunchCtx& c) {
+    const int g = pair_group(0, LOG2M0);
+    if (c.pair_n[g] == 0) return;
+    constexpr int NT = 1 << (LOG2M0 - kPairLpt);
+    if constexpr (NT >= 64 && NT <= 1024)
+        hipLaunchKernelGGL((iter_pair_kernel<LOG2M0>), dim3(c.pair_n[g]), dim3(NT), 0, c.stream, c.sigs, c.io,
+                           c.pair_items + c.pair_off[g], c.shifts, (const float2*)c.twiddle, c.tw_log2,
+                           (float2*)c.synd, c.epart, c.cnt);
+}
+
 static void launch_pairs(const LaunchCtx& c) {
     launch_pair_sizes<1>(c);
     launch_pair_sizes<2>(c);
     launch_pair_sizes<4>(c);
+    launch_iter_group<9>(c);
+    launch_iter_group<10>(c);
+    launch_iter_group<11>(c);
+    launch_iter_group<12>(c);
 }
 
 template <int PMAX>

@@ -502,9 +502,29 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
     // Lines of a unit taken by pair_syndrome_kernel (FP32, one pass): the 2L
     // consecutive shifts of a signal, the two shifts of an iterative grid,
     // when they do not wrap around N (d > last shift); *pb = pairs per block.
+    // Iterative signals whose every grid is one-pass FP32 without wrap, with
+    // 2^kPairLog2MMin <= M_l and M_0 <= 2^kPairLog2MMax: all their grids in
+    // one launch (iter_pair_kernel), a signal's grids in adjacent items of its
+    // lane, so that the later grids' samples, which share grid 0's 128-byte
+    // lines, are read from the same L2 at about the same time.
+    const auto fused_iter = [&](int s) -> bool {
+        const SigHost& g = sigs[(size_t)s];
+        if (g.mode != SFT_MODE_ITERATIVE || fp64 || g.L < 2) return false;
+        const int lm0 = ilog2(g.m);
+        if (lm0 > kPairLog2MMax || lm0 - (g.L - 1) < kPairLog2MMin) return false;
+        for (int l = 0; l < g.L; ++l) {
+            const SigDev& u = lay->sigdev[(size_t)(lay->sigdev[(size_t)s].view0 + l)];
+            if (u.log2m1 != 0 || lay->shifts[(size_t)u.shift_off] + 1 >= u.d) return false;
+        }
+        return true;
+    };
     const auto pair_lines = [&](int idx, int* pb) -> int {
         const SigDev& u = lay->sigdev[idx];
         *pb = 0;
+        if (u.mode == SFT_MODE_ITERATIVE && fused_iter(u.parent)) {
+            *pb = 1;
+            return 2;
+        }
         if (fp64 || u.log2m1 != 0) return 0;
         const int pairs = u.mode == SFT_MODE_ITERATIVE ? 1 : u.L;
         const int64_t last = lay->shifts[(size_t)u.shift_off] + 2 * pairs - 1;
@@ -516,6 +536,12 @@ void build_layout(const std::vector<SigHost>& sigs, bool fp64, PlanLayout* lay) 
         lay->pair_off[g] = (int)lay->pair_items.size();
         interleave(
             [&](int s, std::vector<int4>& v) {
+                if (fused_iter(s)) {   // one item per grid: (view, l), the signal's grids adjacent
+                    if (pair_group(0, ilog2(sigs[(size_t)s].m)) == g)
+                        for (int l = 0; l < sigs[(size_t)s].L; ++l)
+                            v.push_back(int4{lay->sigdev[(size_t)s].view0 + l, l, 0, 0});
+                    return;
+                }
                 for_units(s, [&](int idx, int64_t m, int S, int lm1) {
                     (void)S;
                     (void)lm1;

@@ -67,7 +67,10 @@ def run_iter(torch, sft, x, n, m0, L, dtype):
 
 @pytest.mark.parametrize("n,m0,L,dtype", [
     (1 << 14, 256, 4, "c128"),
-    (1 << 20, 4096, 4, "c64"),
+    (1 << 20, 4096, 4, "c64"),       # every grid of a signal in one block (M_l = 4096 .. 512)
+    (1 << 18, 2048, 4, "c64"),       # the same, down to M_l = 256 (half a wave busy)
+    (1 << 14, 512, 2, "c64"),        # the same, one wave per block
+    (1 << 18, 1024, 4, "c64"),       # a grid of 128 bins: one kernel per grid size
     (16, 8, 4, "c128"),              # d_0 = 2: indices wrap; the last grid has one bin
     (1 << 16, 16384, 2, "c64"),      # iteration 0 in two FFT passes, iteration 1 in one
     (1 << 20, 4096, 4, "c64+fft64"),  # complex64 input, FP64 FFTs

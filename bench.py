@@ -36,9 +36,9 @@ BF16_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 MFMA, published
 # written (fetched, written), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by
 # the plain-copy calibration (profiles/syndrome_kernel_random_shifts_general_n20_b1024_traffic.md,
 # profiles/pair_syndrome_kernel_exact_n20_b1024_traffic.md,
-# profiles/pair_syndrome_kernel_iterative_n20_b1024_traffic.md).  A kernel
+# profiles/iter_pair_kernel_iterative_n20_b1024_traffic.md).  A kernel
 # changed since its counters were taken gets no entry (its traffic is null).
-TRAFFIC_RATIOS = {"general": (12.50, 1.00), "exact": (2.05, 1.18), "iterative": (8.03, 1.00)}
+TRAFFIC_RATIOS = {"general": (12.50, 1.00), "exact": (2.05, 1.18), "iterative": (6.09, 1.00)}
 
 # Algorithmic FLOPs of the order predictor per row (matrix products only):
 # forward 2 (32*128 + 128*128 + 128*5); training adds the three weight
@@ -582,7 +582,7 @@ def main():
     # the dominant kernel of the gather + FFT stage, timed on its own (HIP
     # events around it on the plan's stream): general mode the R random-shift
     # lines, exact mode the 2L consecutive shifts (one pair kernel per call);
-    # iterative mode the whole stage (pair kernels of the L grid sizes)
+    # iterative mode the whole stage (one kernel for every grid)
     if mode == "general":
         k_samples, k_ms = R * m, gather[1]
         k_name = f"syndrome_kernel<{'double' if a.fft64 else 'float'}, 4096, float> (gather + FFT of the R random shifts)"
@@ -592,7 +592,7 @@ def main():
             + " (gather + FFT of the 2L consecutive shifts)"
     else:
         k_samples, k_ms = samples, stage[0]
-        k_name = "pair_syndrome_kernel<1, LOG2M, 3>, LOG2M = 12..9 (gather + FFT of every iteration's lines)"
+        k_name = "iter_pair_kernel<12> (gather + FFT of every iteration's lines, one launch)"
     k_bytes = B * k_samples * per_sample
     k_gbs = k_bytes / (k_ms * 1e-3) / 1e9
     ratios = None if a.fft64 else TRAFFIC_RATIOS.get(mode)

@@ -598,8 +598,24 @@ def main():
     ratios = None if a.fft64 else TRAFFIC_RATIOS.get(mode)
     # measured HBM bytes per launch (fetch + write), when counters were taken for this kernel
     traffic = int(B * k_samples * 8 * (ratios[0] + ratios[1])) if ratios else None
+    # the least HBM traffic the access pattern allows (128-byte lines): the
+    # random shifts need one line per 8-byte sample; exact mode's 2L = 8
+    # consecutive shifts one line per 64-byte run; the iterative grids the
+    # lines of grid 0 (16 bytes used of each; the later grids' samples lie in
+    # them); syndromes written once.  Its ratio to the algorithmic bytes bounds
+    # `frac` at full HBM speed.
+    if a.fft64:
+        floor = None
+    elif mode == "general":
+        floor = B * k_samples * (128 + 8)
+    elif mode == "exact":
+        floor = B * m * (128 + 2 * L * 8)
+    else:
+        floor = B * m * 128 + B * samples * 8
     roofline = {"bound": "hbm", "achieved": round(k_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(k_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "pattern_floor_bytes": floor,
+                "pattern_ceiling_frac": round(k_bytes / floor, 4) if floor else None,
                 "traffic_gbs": round(traffic / (k_ms * 1e-3) / 1e9, 1) if traffic else None,
                 "kernel": k_name, "algorithmic_bytes_per_launch": k_bytes, "avg_launch_ms": round(k_ms, 4),
                 "stage": {"achieved": round(stage_gbs, 1), "frac": round(stage_gbs / HBM_PEAK_GBS, 4),

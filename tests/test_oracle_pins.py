@@ -438,3 +438,40 @@ def test_cs_on_a_singular_locator_keeps_no_column(k_votes):
     r = oracle.sfft_general(x, n, k_votes, m, L, rshifts=[3, 17, 40, 51, 60, 62])
     assert r.locs.tolist() == [0] and np.allclose(r.vals, [1.0 + 0.5j], atol=1e-12)
     assert (r.active_bins, r.flagged_bins, r.cs_bins) == (2, 1, 0)
+
+
+@pytest.mark.parametrize("a", [1, 2])
+def test_noisy_judge_follows_chi_square(a):
+    """The residual judge on noisy bins against a closed form (Sec. II-B
+    Step (iii) with the noise term of the judge).  A bin holds a tones of
+    amplitude 10^5 on random grid slots, plus complex Gaussian noise of
+    variance sigma^2 = 1 per syndrome, independent over the 2L shifts (the
+    alias sum of white spectral noise over the bin's d frequencies).  At that
+    SNR the locator's roots round to the true slots even for adjacent slots
+    (at 10^3 an adjacent pair's roots miss the grid in about a quarter of the
+    trials, before the judge is reached), so the least-squares
+    residual over the 2L syndromes is (sigma^2 / 2) chi^2 with 2 (2L - a)
+    degrees of freedom.  With nu = sigma^2, tau_res = 0 and c_res = 1.5 the
+    order-a hypothesis is accepted at the true support with probability
+    F_chi2(2 c_res (2L - a); 2 (2L - a)); a dropped c_res, a 2L in place of
+    2L - a, or a residual over other syndromes moves the rate by many
+    standard deviations."""
+    from scipy.stats import chi2
+
+    n, m, L, k = 1 << 12, 64, 4, 5
+    d = n // m
+    taus = osf.Taus(tau_zero=1e-9, tau_rank=1e-10, tau_res=0.0, tau_amp=1e-9, c_res=1.5)
+    g = np.random.default_rng(2024 + a)
+    trials, ok = 3000, 0
+    ls = np.arange(2 * L)
+    for _ in range(trials):
+        slots = np.sort(g.choice(d, size=a, replace=False))
+        s = k + slots * m
+        p = 1e5 * np.exp(2j * np.pi * g.random(a))
+        noise = (g.standard_normal(2 * L) + 1j * g.standard_normal(2 * L)) / math.sqrt(2.0)
+        mk = (p[None, :] * np.exp(2j * np.pi * np.outer(ls, s) / n)).sum(axis=1) + noise
+        out = osf.decode_bin(mk, k, n, m, L, a, float(np.sum(np.abs(mk) ** 2)), 1.0, taus, only=[a])
+        ok += out is not None and out[0].tolist() == s.tolist()
+    want = float(chi2.cdf(2 * taus.c_res * (2 * L - a), 2 * (2 * L - a)))
+    sd = math.sqrt(want * (1 - want) / trials)
+    assert abs(ok / trials - want) <= 4 * sd, (ok / trials, want)

@@ -21,32 +21,31 @@ struct V2<double> {
     using type = double2;
 };
 
-// Raw syndromes m_l[k] of the lines [0, cnt) (cnt even, at most the unit's
-// 2L consecutive shifts; no de-rotation), FP64.  Kept by bin, they are one
-// contiguous run per bin: FP32 values are read as 16-byte pairs.
+// Raw syndromes m_l[k] of the lines [0, cnt) (cnt even, 2 <= cnt <= the
+// unit's 2L consecutive shifts; no de-rotation), FP64, zero beyond cnt.  Kept
+// by bin, they are one contiguous run per bin: FP32 values are read as
+// 16-byte pairs.  Every load is unconditional (indices clamped to the run),
+// so that they are issued together: a load behind a branch on cnt would wait
+// for the one before it.
 template <typename T, int MAXC>
 __device__ __attribute__((always_inline)) inline void load_raw(const typename V2<T>::type* __restrict__ synd,
                                                                 const SigDev& sg, int64_t k, int cnt, zd* out) {
     const typename V2<T>::type* __restrict__ run = synd + synd_at(sg, 0, k);
-#pragma unroll
-    for (int l = 0; l < MAXC; ++l) out[l] = zd{0.0, 0.0};
     if constexpr (sizeof(T) == 4) {
         const float4* __restrict__ r4 = reinterpret_cast<const float4*>(run);
+        const int last = (cnt >> 1) - 1;
 #pragma unroll
         for (int l = 0; l < MAXC; l += 2) {
-            if (l < cnt) {
-                const float4 v = r4[l >> 1];
-                out[l] = zd{(double)v.x, (double)v.y};
-                out[l + 1] = zd{(double)v.z, (double)v.w};
-            }
+            const float4 v = r4[min(l >> 1, last)];
+            const bool on = l < cnt;
+            out[l] = on ? zd{(double)v.x, (double)v.y} : zd{0.0, 0.0};
+            out[l + 1] = on ? zd{(double)v.z, (double)v.w} : zd{0.0, 0.0};
         }
     } else {
 #pragma unroll
         for (int l = 0; l < MAXC; ++l) {
-            if (l < cnt) {
-                auto v = run[l];
-                out[l] = zd{(double)v.x, (double)v.y};
-            }
+            const auto v = run[min(l, cnt - 1)];
+            out[l] = l < cnt ? zd{(double)v.x, (double)v.y} : zd{0.0, 0.0};
         }
     }
 }
@@ -685,22 +684,43 @@ __device__ inline bool sp_run(const int64_t* cand, int keep, unsigned all, int s
                               const int64_t* nj, int64_t d, const double2* tab, int stride, const double2* gram,
                               unsigned& T_out, zd* coef_out) {
     // b = Phi^H y (Phi_jc = w_d^{(t_c n_j) mod d}) and ||y||^2, folding in
-    // one y_j at a time; G = Phi^H Phi from the signal's Gram row table:
+    // the y_j in order; G = Phi^H Phi from the signal's Gram row table:
     // G_ie = sum_j w_d^{((t_e - t_i) n_j) mod d} = F[(t_e - t_i) mod d]
     // (d a power of two: the low bits, also for a negative difference)
+    //
+    // Four shifts at a time: a chunk's loads (y_j, n_j, the table entries) are
+    // unconditional, with indices clamped to R - 1, so that they are issued
+    // together instead of each waiting behind a branch for the one before;
+    // positions past R add zeros, and unused candidate slots keep b = 0.
     zd b[KC];
     CandGram<KC> g;
     double yy = 0.0;
 #pragma unroll
     for (int i = 0; i < KC; ++i) b[i] = zd{0.0, 0.0};
+    constexpr int kChunk = 4;
+    static_assert(kMaxR % kChunk == 0, "whole chunks");
+    const uint64_t qmask = (uint64_t)(d - 1);
 #pragma unroll
-    for (int j = 0; j < kMaxR; ++j) {
-        if (j < R) {
-            const zd yj = ysrc.at(j);
-            yy += norm2(yj);
+    for (int j0 = 0; j0 < kMaxR; j0 += kChunk) {
+        if (j0 < R) {
+            zd yv[kChunk];
+            zd wv[kChunk][KC];
 #pragma unroll
-            for (int i = 0; i < KC; ++i)
-                if (i < keep) b[i] = b[i] + cmul_conj(omega(tab, stride, (cand[i] * nj[j]) & (d - 1)), yj);
+            for (int c = 0; c < kChunk; ++c) {
+                const int jj = min(j0 + c, R - 1);
+                const uint64_t nv = (uint64_t)nj[jj];
+                yv[c] = ysrc.at(jj);
+#pragma unroll
+                for (int i = 0; i < KC; ++i) wv[c][i] = omega(tab, stride, (int64_t)(((uint64_t)cand[i] * nv) & qmask));
+            }
+#pragma unroll
+            for (int c = 0; c < kChunk; ++c) {
+                const zd yj = (j0 + c < R) ? yv[c] : zd{0.0, 0.0};
+                yy += norm2(yj);
+#pragma unroll
+                for (int i = 0; i < KC; ++i)
+                    if (i < keep) b[i] = b[i] + cmul_conj(wv[c][i], yj);
+            }
         }
     }
     g.f = gram;
@@ -712,8 +732,10 @@ __device__ inline bool sp_run(const int64_t* cand, int keep, unsigned all, int s
         for (int i = 0; i < KC; ++i)
 #pragma unroll
             for (int e = 0; e <= i; ++e) {
-                const double2 f = i < keep ? gram[(cand[e] - cand[i]) & (d - 1)] : double2{0.0, 0.0};
-                g.g[i * (i + 1) / 2 + e] = zd{f.x, f.y};
+                // unconditional load (unused slots hold INT64_MAX: any index
+                // mod d is in range), then zero rows for unused slots
+                const double2 f = gram[(cand[e] - cand[i]) & (d - 1)];
+                g.g[i * (i + 1) / 2 + e] = i < keep ? zd{f.x, f.y} : zd{0.0, 0.0};
             }
     }
     double corr[KC];
@@ -1090,7 +1112,8 @@ __global__ __launch_bounds__(kBlock) void certify_kernel(const SigDev* __restric
             const int2 en = active[item];
             const int s = en.x;
             const int64_t k = code_k(en.y);
-            const SigDev& sg = sigs[s];
+            // by value: the fields are read together, not at their first use behind a branch
+            const SigDev sg = sigs[s];
             const int L = sg.L;
             zd mt[2 * kMaxL];
             load_raw<T, 2 * kMaxL>(synd, sg, k, 2 * L, mt);
@@ -1142,7 +1165,8 @@ __global__ __launch_bounds__(kBlock) void svd_rank_kernel(const SigDev* __restri
             const int code = en.y;
             const int64_t k = code_k(code);
             const int step = code_step(code), ap = code_ap(code);
-            const SigDev& sg = sigs[s];
+            // by value: the fields are read together, not at their first use behind a branch
+            const SigDev sg = sigs[s];
             const int L = sg.L;
             zd mt[2 * kMaxL];
             load_raw<T, 2 * kMaxL>(synd, sg, k, 2 * L, mt);
@@ -1190,7 +1214,8 @@ __global__ __launch_bounds__(kBlock, A <= 2 ? 3 : 2) void round_kernel(const Sig
             const int code = en.y;
             const int64_t k = code_k(code);
             const int step = code_step(code), ap = code_ap(code), a0 = code_a0(code);
-            const SigDev& sg = sigs[s];
+            // by value: the fields are read together, not at their first use behind a branch
+            const SigDev sg = sigs[s];
             const int L = sg.L;
             const bool exact = sg.mode == kExact;
             zd mt[2 * kMaxL];
@@ -1269,7 +1294,8 @@ __global__ __launch_bounds__(kBlock) void precheck_kernel(const SigDev* __restri
         for (int i = 1; i < kSeg; ++i)
             if (seg == i) s0 = start[i];
         const int2 en = qlist[(int64_t)q_round(0, seg + 1) * list_cap + (item - s0)];
-        const SigDev& sg = sigs[en.x];
+        // by value: the fields are read together, not at their first use behind a branch
+        const SigDev sg = sigs[en.x];
         if (sg.mode != kGeneral) continue;
         const int64_t k = code_k(en.y);
         unsigned pc = 0u;
@@ -1329,7 +1355,8 @@ __global__ __launch_bounds__(kBlock) void rest_kernel(const SigDev* __restrict__
         const int code = en.y;
         const int64_t k = code_k(code);
         const int ap = code_ap(code), a0 = code_a0(code);
-        const SigDev& sg = sigs[s];
+        // by value: the fields are read together, not at their first use behind a branch
+        const SigDev sg = sigs[s];
         const int L = sg.L;
         zd mt[2 * kMaxL];
         load_raw<T, 2 * kMaxL>(synd, sg, k, 2 * L, mt);
@@ -1396,7 +1423,9 @@ __global__ __launch_bounds__(kBlock) void cs_kernel(const SigDev* __restrict__ s
         const int2 en = in[item];
         const int s = en.x;
         const int64_t k = en.y;
-        const SigDev& sg = sigs[s];
+        // the signal's fields by value: read together here rather than one
+        // at a time at their first use behind the branches below
+        const SigDev sg = sigs[s];
         const int L = sg.L;
         const int64_t* sh = shifts + sg.shift_off;
         zd mt[2 * kMaxL];

@@ -291,8 +291,9 @@ constexpr int kSelChunk = 1024;
 // by radix selection on the 64-bit keys, 8 bits per pass: each pass counts
 // the candidates (keys matching the digits fixed so far) per next digit and
 // keeps the digit that holds rank r.  A first pass finds the bits common to
-// all keys (their OR and AND), and the digit passes start at the digit of the
-// highest bit that differs.  Once the candidates fit in LDS they are gathered
+// all keys (their OR and AND) and counts the keys per top byte, and the digit
+// passes start at the digit of the highest bit that differs (the top byte's
+// counts serve when that is the top byte).  Once the candidates fit in LDS they are gathered
 // there and the remaining passes run on LDS.  Ties of the full key go to the
 // lower index.  Whole block of kRankThreads; the result is the same element a
 // full sort would give.
@@ -303,12 +304,18 @@ __device__ int block_radix_select(UKeyFn ukey, int n, int r, RadixLdsT<CH>& S) {
     int& sel_rr = S.sel_rr;
     int& n_cand = S.n_cand;
     const int lane = threadIdx.x & 63;
-    // bits common to all keys
+    int* hc = hist + (lane & (kRadixCopies - 1)) * 256;
+    // bits common to all keys, and in the same pass the counts per top byte
+    // (bits 56..63): when the keys differ there, that byte is the first
+    // digit and its pass is already done
+    for (int i = threadIdx.x; i < kRadixCopies * 256; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
     unsigned long long kor = 0ull, kand = ~0ull;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const unsigned long long k = ukey(i);
         kor |= k;
         kand &= k;
+        atomicAdd(&hc[(int)(k >> 56)], 1);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -365,21 +372,22 @@ __device__ int block_radix_select(UKeyFn ukey, int n, int r, RadixLdsT<CH>& S) {
             nc = n_cand;
             in_lds = true;
         }
-        for (int i = threadIdx.x; i < kRadixCopies * 256; i += blockDim.x) hist[i] = 0;
-        __syncthreads();
-        int* hc = hist + (lane & (kRadixCopies - 1)) * 256;
-        if (in_lds) {
-            for (int j = threadIdx.x; j < nc; j += blockDim.x) {
-                const unsigned long long k = S.key[j];
-                if ((k & mask) == prefix) atomicAdd(&hc[(k >> shift) & 255], 1);
+        if (shift != 56) {   // the top byte was counted with the common bits
+            for (int i = threadIdx.x; i < kRadixCopies * 256; i += blockDim.x) hist[i] = 0;
+            __syncthreads();
+            if (in_lds) {
+                for (int j = threadIdx.x; j < nc; j += blockDim.x) {
+                    const unsigned long long k = S.key[j];
+                    if ((k & mask) == prefix) atomicAdd(&hc[(k >> shift) & 255], 1);
+                }
+            } else {
+                for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                    const unsigned long long k = ukey(i);
+                    if ((k & mask) == prefix) atomicAdd(&hc[(k >> shift) & 255], 1);
+                }
             }
-        } else {
-            for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                const unsigned long long k = ukey(i);
-                if ((k & mask) == prefix) atomicAdd(&hc[(k >> shift) & 255], 1);
-            }
+            __syncthreads();
         }
-        __syncthreads();
         if (threadIdx.x < 256) {   // fold the copies into copy 0
             int v = 0;
 #pragma unroll

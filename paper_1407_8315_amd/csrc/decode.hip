@@ -293,9 +293,9 @@ constexpr int kSelChunk = 1024;
 // keeps the digit that holds rank r.  A first pass finds the bits common to
 // all keys (their OR and AND) and counts the keys per top byte, and the digit
 // passes start at the digit of the highest bit that differs (the top byte's
-// counts serve when that is the top byte).  Once the candidates fit in LDS they are gathered
-// there and the remaining passes run on LDS.  Ties of the full key go to the
-// lower index.  Whole block of kRankThreads; the result is the same element a
+// counts serve when that is the top byte).  Once the candidates fit in LDS
+// they are gathered there and the remaining passes run on LDS.  Ties of the
+// full key go to the lower index.  Whole block of kRankThreads; the result is the same element a
 // full sort would give.
 template <typename UKeyFn, int CH>
 __device__ int block_radix_select(UKeyFn ukey, int n, int r, RadixLdsT<CH>& S) {

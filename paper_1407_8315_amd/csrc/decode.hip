@@ -280,7 +280,7 @@ struct RadixLdsT {
     int tie[CH];
     int hist[kRadixCopies * 256];
     unsigned long long kor[kRankThreads / 64], kand[kRankThreads / 64];
-    int sel_digit, sel_rr, n_cand, pick;
+    int sel_digit, sel_rr, sel_count, n_cand, pick;
 };
 using RadixLds = RadixLdsT<kRankChunk>;
 // candidates the selection kernel gathers into LDS (20 KB in all: its blocks
@@ -294,9 +294,10 @@ constexpr int kSelChunk = 1024;
 // all keys (their OR and AND) and counts the keys per top byte, and the digit
 // passes start at the digit of the highest bit that differs (the top byte's
 // counts serve when that is the top byte).  Once the candidates fit in LDS
-// they are gathered there and the remaining passes run on LDS.  Ties of the
-// full key go to the lower index.  Whole block of kRankThreads; the result is the same element a
-// full sort would give.
+// they are gathered there and the remaining passes run on LDS; the passes stop
+// once a single candidate is left.  Ties of the full key go to the lower
+// index.  Whole block of kRankThreads; the result is the same element a full
+// sort would give.
 template <typename UKeyFn, int CH>
 __device__ int block_radix_select(UKeyFn ukey, int n, int r, RadixLdsT<CH>& S) {
     int* hist = S.hist;
@@ -424,10 +425,12 @@ __device__ int block_radix_select(UKeyFn ukey, int n, int r, RadixLdsT<CH>& S) {
                 }
                 sel_digit = d;
                 sel_rr = rr - cum;
+                S.sel_count = hist[d];
                 if (!in_lds) n_cand = hist[d];
             } else if (t == 63 && rr >= inc) {   // not reached for 0 <= r < n: the last bin
                 sel_digit = 255;
                 sel_rr = rr - (inc - h3);
+                S.sel_count = h3;
                 if (!in_lds) n_cand = h3;
             }
         }
@@ -436,9 +439,12 @@ __device__ int block_radix_select(UKeyFn ukey, int n, int r, RadixLdsT<CH>& S) {
         mask |= 255ull << shift;
         rr = sel_rr;
         if (!in_lds) nc = n_cand;
+        const bool single = S.sel_count == 1;   // one candidate left: the lower digits decide nothing
         __syncthreads();
+        if (single) break;
     }
-    // the rr-th lowest index among the keys equal to prefix
+    // the rr-th lowest index among the keys matching prefix on mask (all bits,
+    // unless the digits stopped at a single candidate)
     int& pick = S.pick;
     if (threadIdx.x == 0) {
         n_cand = 0;
@@ -447,7 +453,7 @@ __device__ int block_radix_select(UKeyFn ukey, int n, int r, RadixLdsT<CH>& S) {
     __syncthreads();
     if (in_lds) {
         for (int j = threadIdx.x; j < nc; j += blockDim.x)
-            if (S.key[j] == prefix) S.tie[atomicAdd(&n_cand, 1)] = S.idx[j];
+            if ((S.key[j] & mask) == prefix) S.tie[atomicAdd(&n_cand, 1)] = S.idx[j];
         __syncthreads();
         const int ne = n_cand;
         for (int j = threadIdx.x; j < ne; j += blockDim.x) {
@@ -462,7 +468,7 @@ __device__ int block_radix_select(UKeyFn ukey, int n, int r, RadixLdsT<CH>& S) {
         const int C = (n + blockDim.x - 1) / blockDim.x;
         const int lo = min(n, (int)threadIdx.x * C), hi = min(n, lo + C);
         int c = 0;
-        for (int i = lo; i < hi; ++i) c += ukey(i) == prefix ? 1 : 0;
+        for (int i = lo; i < hi; ++i) c += (ukey(i) & mask) == prefix ? 1 : 0;
         S.idx[threadIdx.x] = c;
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -478,7 +484,7 @@ __device__ int block_radix_select(UKeyFn ukey, int n, int r, RadixLdsT<CH>& S) {
         if (rr >= before && rr < before + c) {
             int m = rr - before;
             for (int i = lo; i < hi; ++i)
-                if (ukey(i) == prefix) {
+                if ((ukey(i) & mask) == prefix) {
                     if (m == 0) {
                         pick = i;
                         break;

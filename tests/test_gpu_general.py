@@ -125,6 +125,34 @@ def test_general_exact_input_is_exact(torch, sft):
     assert np.max(np.abs(val - s.vals)) < 1e-9
 
 
+@pytest.mark.parametrize("k_votes", [5, 6, 8])
+def test_cs_on_a_singular_locator_keeps_no_column(torch, sft, k_votes):
+    """The constructed case of the oracle pin of the same name, on the
+    device: one tone at location 0 makes every line constant, so the FP64
+    transforms are exactly zero outside bin 0 (every radix step of a
+    constant sequence takes differences first); the vote gives bin 0 all L
+    orders and bin 1 the remaining k_votes - L (zero singular values tie,
+    lower bin first); bin 1's locators are singular at every order, so the
+    decoder flags it and the CS step, which prunes with the order-a0
+    locator (Sec. III-C Steps 2-3), has no candidate column and keeps
+    nothing.  Same output, counts and value as the FP64 oracle."""
+    n, m, L = 1024, 16, 4
+    x = sftgen.make_signal(n, 1, 0, locs=np.array([0]), vals=np.array([1.0 + 0.5j]), dtype=np.complex128).x
+    say(f"[general singular locator] K={k_votes}")
+    plan = sft.Plan(dict(n=n, k=k_votes, m=m, l=L, mode="general", dtype="c128", seed=5))
+    res = plan.general(to_dev(torch, x), stats=True)
+    loc, val = res.host()
+    rsh = plan.info()["rshifts"]
+    plan.close()
+    ref = oracle.sfft_general(x, n, k_votes, m, L, rsh)
+    say(f"  gpu {loc.tolist()} stats active {res.stats['active_bins']} flagged {res.stats['flagged_bins']} "
+        f"cs {res.stats['cs_bins']}; oracle {ref.locs.tolist()} ({ref.active_bins}, {ref.flagged_bins}, {ref.cs_bins})")
+    assert ref.locs.tolist() == [0] and (ref.active_bins, ref.flagged_bins, ref.cs_bins) == (2, 1, 0)
+    assert loc.tolist() == [0]
+    assert abs(val[0] - (1.0 + 0.5j)) < 1e-12
+    assert (res.stats["active_bins"], res.stats["flagged_bins"], res.stats["cs_bins"]) == (2, 1, 0)
+
+
 def test_batch_equals_single_calls_and_replays(torch, sft):
     """A batch of uneven signals (exact and general) gives each signal's
     single-call result, and replaying the captured graph repeats it bit for bit."""

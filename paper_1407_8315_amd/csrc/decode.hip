@@ -1228,7 +1228,11 @@ __global__ __launch_bounds__(kBlock, A <= 2 ? 3 : 2) void round_kernel(const Sig
             const int code = en.y;
             const int64_t k = code_k(code);
             const int step = code_step(code), ap = code_ap(code), a0 = code_a0(code);
-            // by value: the fields are read together, not at their first use behind a branch
+            // by value: the fields are read together, not at their first use
+            // behind a branch (as in rest_kernel, which decodes the same
+            // hypotheses when a plan has no general-mode signal: the two must
+            // compile try_order alike for a batch to equal single calls bit
+            // for bit; by reference here, the values differ in the last bits)
             const SigDev sg = sigs[s];
             const int L = sg.L;
             const bool exact = sg.mode == kExact;

@@ -1057,27 +1057,28 @@ __global__ __launch_bounds__(kBlock) void activity_kernel(const SigDev* __restri
         int a0 = 0;
         bool act;
         if (sg.mode == kExact) {
+            // the bin's 2L syndromes as one run of unconditional loads
+            zd mr[2 * kMaxL];
+            if (synd32)
+                load_raw<float, 2 * kMaxL>(synd32, sg, k, 2 * L, mr);
+            else
+                load_raw<double, 2 * kMaxL>(synd64, sg, k, 2 * L, mr);
             double e = 0.0;
-            for (int l = 0; l < 2 * L; ++l) {
-                const int64_t idx = synd_at(sg, l, k);
-                double re, im;
-                if (synd32) {
-                    float2 v = synd32[idx];
-                    re = v.x;
-                    im = v.y;
-                } else {
-                    double2 v = synd64[idx];
-                    re = v.x;
-                    im = v.y;
-                }
-                e += re * re + im * im;
-            }
+#pragma unroll
+            for (int l = 0; l < 2 * kMaxL; ++l) e += mr[l].x * mr[l].x + mr[l].y * mr[l].y;   // zero beyond 2L
             act = e > sg.tau_zero2 * eref;
         } else {
-            for (int i = 0; i < L; ++i) {
-                int64_t flat = k * L + i;
-                unsigned long long kv = sv_key(sigma[(sg.bin_off + k) * L + i]);
-                a0 += (kv > sd.thr_key || (kv == sd.thr_key && flat <= sd.thr_idx)) ? 1 : 0;
+            // the bin's L singular values, loaded unconditionally (index
+            // clamped to the bin's run), counted for i < L
+            const double* sb = sigma + (sg.bin_off + k) * L;
+            double sv[kMaxL];
+#pragma unroll
+            for (int i = 0; i < kMaxL; ++i) sv[i] = sb[min(i, L - 1)];
+#pragma unroll
+            for (int i = 0; i < kMaxL; ++i) {
+                const int64_t flat = k * L + i;
+                const unsigned long long kv = sv_key(sv[i]);
+                a0 += (i < L && (kv > sd.thr_key || (kv == sd.thr_key && flat <= sd.thr_idx))) ? 1 : 0;
             }
             act = a0 > 0;
         }
